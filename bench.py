@@ -1,0 +1,339 @@
+#!/usr/bin/env python3
+"""Throughput of the failure-less Aho-Corasick scan on one MI355X.
+
+One step is one whole scan of the workload's text through the C ABI
+(``pfac_scan``: reset, the scan kernel, the tile-ordering finisher), with the
+text and the trie already resident in HBM.  Prints one JSON line:
+
+* ``value``: Gbit/s of text scanned (8 * text bytes / step time);
+* ``roofline``: the scan kernel alone, timed with HIP events recorded by the
+  library around it on the launch stream, against the MI355X HBM peak;
+  ``traffic`` comes from committed rocprofv3 FETCH_SIZE / WRITE_SIZE counts
+  when they were taken on the current kernel source;
+* ``cpu_baseline``: the oracle's bucketed matcher on the machine's host cores.
+
+Workloads (seeded synthetic data, see synth/workloads.py): ``c2`` (default,
+10,000 patterns of 8-64 bytes, 70% printable bytes, 256 MiB text), ``c1``,
+``c3`` (1 GiB DNA text, 100,000 patterns).  ``--extras`` adds the batched vs
+plain per-text comparison (65,600 texts) and the serving loop latencies.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
+KERNEL_SRC = os.path.join(ROOT, "paper_1702_03657_amd", "csrc", "kernels.hip")
+
+WORKLOADS = {
+    "c1": ("c1: 100 patterns len U[4,16] bytes U[0,255]; 1 MiB uniform text, 1000 planted copies",
+           lambda w: w.c1_plain_small()),
+    "c2": ("c2: 10,000 patterns len U[8,64], 70% printable bytes; 256 MiB text of the same mix, "
+           "one planted copy per ~4 KiB", lambda w: w.c2_signature_set()),
+    "c3": ("c3: 100,000 patterns len U[20,32] over ACGT; 1 GiB uniform ACGT text, "
+           "10,000 planted copies", lambda w: w.c3_dna()),
+}
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def tuning_cache_path():
+    return os.environ.get("PFAC_TUNING_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "pfac_tuning.json"))
+
+
+def choose_tuning(pf, trie, ws, text_dev, n, workload, device_name, retune):
+    """Autotune once per (workload, device); later runs reuse the cached choice."""
+    path = tuning_cache_path()
+    key = f"{workload}|{n}|{device_name}"
+    cache = {}
+    if os.path.exists(path):
+        try:
+            with open(path) as f:
+                cache = json.load(f)
+        except (OSError, ValueError):
+            cache = {}
+    if key in cache and not retune:
+        t = cache[key]
+        trie.set_tuning(t["bytes_per_lane"], t["index_bits"], t["wg_per_cu"])
+        return t, False
+    t0 = time.time()
+    best = pf.pfac_autotune(trie, ws, text_dev, n)
+    log(f"autotune: {best} in {time.time() - t0:.1f}s")
+    cache[key] = best
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(cache, f)
+    except OSError:
+        pass
+    return best, True
+
+
+def traffic_from_profiles(workload, n_launch_bytes):
+    """HBM bytes per scan-kernel launch from committed counter summaries."""
+    path = os.path.join(ROOT, "profiles", f"traffic_scan_tiles_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_sha256_16") != kernel_hash():
+        return None  # the kernel changed since the counters were taken
+    return d.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(oracle, wl, threads):
+    """Bucketed oracle over the whole text on `threads` host threads."""
+    tm = [0.0, 0.0]
+    m = oracle.bucketed(wl.text, wl.patterns, threads=threads, timing=tm)
+    gbps = wl.text.size * 8 / tm[1] / 1e9
+    return {"value": round(gbps, 3), "unit": "Gbit/s", "cores": threads, "kind": "oracle",
+            "sample": f"bucketed matcher (first-min(len,8)-byte index + memcmp) over the whole "
+                      f"{wl.text.size} B text; index build {tm[0]:.3f}s excluded; "
+                      f"{m.n} matches"}, m
+
+
+def run_copy_probe(torch, nbytes):
+    """A plain device copy of known size, to calibrate the HBM byte counters."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy probe: 3 copies of {nbytes} bytes")
+
+
+def extras_batched(pf, torch, steps):
+    """C4: one graph-captured persistent launch vs one launch per text."""
+    import numpy as np
+    from synth import workloads
+    t0 = time.time()
+    wl = workloads.c4_batched()
+    log(f"c4 generated in {time.time() - t0:.1f}s: {wl.n_texts} texts, {wl.text.size} bytes")
+    trie = pf.Trie(wl.patterns)
+    ws = pf.Workspace()
+    text = torch.from_numpy(wl.text).cuda()
+    offs_host = wl.offsets.astype(np.uint64)
+    offs = torch.from_numpy(offs_host.view(np.int64)).cuda()
+    total = int(offs_host[-1])
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    cap = 4 << 20
+    out = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.Stream()
+    res = {"workload": "c4: 65,536 texts lognormal(512, 0.75) clipped [64,1500] B + 64 texts "
+                       "U[1,64] MiB; 20,000 patterns len U[8,64]; copies 1 per 2 KiB",
+           "texts": wl.n_texts, "text_bytes": total}
+    with torch.cuda.stream(stream):
+        g = pf.Graph(trie, ws, text, offs, wl.n_texts, total, out, cap, cnt, stream)
+        g.launch(stream)
+        stream.synchronize()
+        n_batched = int(cnt.item())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            g.launch(stream)
+        e1.record(stream)
+        stream.synchronize()
+        ms_b = e0.elapsed_time(e1) / steps
+        pf.pfac_scan_batch_plain(trie, ws, text, offs_host, wl.n_texts, out, cap, cnt, stream)
+        stream.synchronize()
+        n_plain = int(cnt.item())
+        plain_steps = max(1, min(steps, 3))
+        e0.record(stream)
+        for _ in range(plain_steps):
+            pf.pfac_scan_batch_plain(trie, ws, text, offs_host, wl.n_texts, out, cap, cnt, stream)
+        e1.record(stream)
+        stream.synchronize()
+        ms_p = e0.elapsed_time(e1) / plain_steps
+    res.update({
+        "matches": n_batched, "plain_matches_equal": n_plain == n_batched,
+        "batched_ms": round(ms_b, 4), "plain_ms": round(ms_p, 4),
+        "batched_gbit_s": round(total * 8 / ms_b / 1e6, 2),
+        "plain_gbit_s": round(total * 8 / ms_p / 1e6, 2),
+        "speedup": round(ms_p / ms_b, 2),
+    })
+    g.close()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--retune", action="store_true", help="ignore the cached autotune choice")
+    ap.add_argument("--tuning", default=None, help="bytes_per_lane,index_bits,wg_per_cu")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--extras", action="store_true", help="add batched-vs-plain (c4)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain copy of the text size (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU: the scan shards by "
+                                   "text range with no exchange, so more GPUs are not measured "
+                                   "here (run with --gpus 1)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1702_03657_amd as pf
+    from synth import workloads
+
+    torch.cuda.set_device(0)
+    dev_name = torch.cuda.get_device_name(0)
+    desc, make = WORKLOADS[args.workload]
+    t0 = time.time()
+    wl = make(workloads)
+    log(f"{args.workload} generated in {time.time() - t0:.1f}s: {wl.text.size} bytes, "
+        f"{len(wl.patterns)} patterns")
+    n = int(wl.text.size)
+
+    trie = pf.Trie(wl.patterns)
+    st = trie.stats()
+    ws = pf.Workspace()
+
+    # host -> device copy of the text, timed separately (not part of `value`)
+    host = torch.from_numpy(wl.text).pin_memory()
+    text = torch.empty(n, dtype=torch.uint8, device="cuda")
+    h0, h1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    h0.record()
+    text.copy_(host, non_blocking=True)
+    h1.record()
+    torch.cuda.synchronize()
+    h2d_ms = h0.elapsed_time(h1)
+
+    if args.tuning:
+        b, i, w = (int(x) for x in args.tuning.split(","))
+        trie.set_tuning(b, i, w)
+        tuning, tuned_now = trie.tuning(), False
+    else:
+        tuning, tuned_now = choose_tuning(pf, trie, ws, text, n, args.workload, dev_name,
+                                          args.retune)
+    st = trie.stats()
+
+    stream = torch.cuda.current_stream()
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rc, n_matches = pf.pfac_scan_sync(trie, ws, text, n, None, 0)
+    cap = max(1024, n_matches)
+    out = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    ws.reserve(n, 1, cap)
+
+    for _ in range(args.warmup):
+        pf.pfac_scan(trie, ws, text, n, out, cap, cnt, None, stream)
+    torch.cuda.synchronize()
+
+    kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s0.record(stream)
+    for i in range(args.steps):
+        ws.set_timing(kev[i][0], kev[i][1])
+        pf.pfac_scan(trie, ws, text, n, out, cap, cnt, None, stream)
+    s1.record(stream)
+    torch.cuda.synchronize()
+    ws.set_timing(None, None)
+    total_ms = s0.elapsed_time(s1)
+    ms_per_step = total_ms / args.steps
+    kms = [a.elapsed_time(b) for a, b in kev]
+    kernel_ms = statistics.mean(kms)
+    got = int(cnt.item())
+    if got != n_matches:
+        raise SystemExit(f"match count changed between runs: {got} != {n_matches}")
+
+    gbit_s = n * 8 / (ms_per_step / 1e3) / 1e9
+    image_bytes = int(st["bytes_device"])
+    alg_bytes = n + 16 * n_matches + image_bytes
+    achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
+    traffic = traffic_from_profiles(args.workload, alg_bytes)
+
+    if args.copy_probe:
+        run_copy_probe(torch, n)
+
+    line = {
+        "metric": "Gbit/s scanned on 1 MI355X (plain PFAC scan, text resident in HBM)",
+        "value": round(gbit_s, 2),
+        "unit": "Gbit/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic",
+        "config": {
+            "workload": desc,
+            "text_bytes": n,
+            "patterns": len(wl.patterns),
+            "matches": n_matches,
+            "tuning": {k: int(v) for k, v in tuning.items() if k != "reserved"},
+            "autotuned_this_run": tuned_now,
+            "index_depth": int(st["index_depth"]),
+            "symbol_bits": int(st["symbol_bits"]),
+            "device": dev_name,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "scan_tiles",
+            "kernel_ms": round(kernel_ms, 5),
+            "algorithmic_bytes_per_launch": alg_bytes,
+        },
+        "h2d_gbit_s": round(n * 8 / (h2d_ms / 1e3) / 1e9, 2),
+        "trie": {
+            "nodes": int(st["nodes"]), "bytes_crs": int(st["bytes_crs"]),
+            "bytes_dense256": int(st["bytes_dense256"]),
+            "bytes_bitmap36": int(st["bytes_bitmap36"]),
+            "bytes_device": image_bytes,
+            "build_s": round(st["build_seconds"], 3),
+        },
+    }
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        cb, want = cpu_baseline(oracle, wl, threads)
+        line["cpu_baseline"] = cb
+        # the timed run's list equals the oracle's
+        got_m = pf.matches_to_numpy(out, n_matches)
+        same = (got_m.size == want.n and np.array_equal(got_m["pos"], want["pos"])
+                and np.array_equal(got_m["pattern_id"], want["id"]))
+        line["parity_with_oracle"] = bool(same)
+    if args.extras:
+        line["batched_vs_plain"] = extras_batched(pf, torch, max(3, args.steps // 5))
+
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,286 @@
+/*
+ * pfac.h - C ABI of the MI355X (gfx950) failure-less Aho-Corasick scanner.
+ *
+ * The library answers the problem of Background, "Multi-Pattern Matching":
+ * given patterns P_0..P_{k-1} and a text T, report every (start position i,
+ * pattern j) with T[i .. i+|P_j|) == P_j.  It does so with the failure-less
+ * walk of Background, "Parallel Failure-Less Aho-Corasick" (one GPU lane per
+ * start byte, walking the trie from the root until the first mismatch and
+ * reporting every pattern that ends on the way), over the trie of Design and
+ * Implementation: built breadth first, level by level (step I), stored as a
+ * row-major array (step II) and compressed as a compressed-row-storage matrix
+ * (the CRS step): row_ptr per node, the edge label as column index and the
+ * child as value.
+ *
+ * Conventions shared by every call:
+ *   - Functions return PFAC_OK (0) or a negative PFAC_E* code.
+ *   - pattern_id is the 0-based index of the pattern in the build call.
+ *   - pos is the 0-based byte offset of the match inside its own text.
+ *   - Results are sorted by (text_id, pos, pattern_id), ascending; every match
+ *     is reported exactly once, duplicate patterns under each of their ids.
+ *   - No match crosses the end of a text.
+ *   - Pointers named *_dev are device (HBM) addresses on the current HIP
+ *     device; *_host are host addresses.  `stream` is a hipStream_t (NULL =
+ *     the default stream).  All scan calls are asynchronous on `stream`
+ *     unless their name ends in _sync.
+ *   - The caller owns every buffer it passes; the library owns the objects
+ *     it returns until the matching *_free call.
+ *   - A trie is immutable after pfac_build and may be shared by many streams
+ *     and threads.  A workspace serializes: calls that share a workspace must
+ *     be issued on one stream (or otherwise ordered); calls on different
+ *     workspaces may overlap.
+ */
+#ifndef PFAC_H
+#define PFAC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PFAC_OK 0
+#define PFAC_EINVAL (-1)   /* NULL pointer, bad size or bad flag */
+#define PFAC_EEMPTY (-2)   /* a pattern of length 0 */
+#define PFAC_ENOMEM (-3)   /* host or device allocation failed */
+#define PFAC_EDEVICE (-4)  /* a HIP call failed; see pfac_last_hip_error() */
+#define PFAC_ETRUNC (-5)   /* more matches than `capacity`; the count is still exact */
+#define PFAC_ENODEV (-6)   /* the trie was built without a device image */
+#define PFAC_EBUSY (-7)    /* serving: over budget / queue full, retry later */
+
+/* pfac_build flags */
+#define PFAC_BUILD_HOST_ONLY 1u  /* build the CRS trie on the host only; no HIP call */
+
+/* One match: 16 bytes, naturally aligned. */
+typedef struct {
+    uint64_t pos;          /* start offset inside text `text_id` */
+    uint32_t pattern_id;   /* index of the pattern in the build call */
+    uint32_t text_id;      /* index of the text in the batch (0 for single-text scans) */
+} pfac_match;
+
+typedef struct pfac_trie pfac_trie;
+typedef struct pfac_workspace pfac_workspace;
+typedef struct pfac_graph pfac_graph;
+typedef struct pfac_server pfac_server;
+
+/* Sizes and footprint of a built trie (Design and Implementation; Results). */
+typedef struct {
+    uint64_t nodes;            /* N = distinct non-empty prefixes + 1 (the root) */
+    uint64_t edges;            /* nnz = N - 1 */
+    uint64_t n_patterns;       /* k */
+    uint64_t min_len, max_len; /* shortest / longest pattern (0 when k = 0) */
+    uint64_t depth;            /* levels below the root = max_len */
+    uint64_t bytes_crs;        /* row_ptr + labels + child + term_ptr + term_ids */
+    uint64_t crs_elements;     /* 2 nnz + N + 1 (row_ptr, col_ind, val) */
+    uint64_t bytes_dense256;   /* uncompressed node x 256 int32 transition table = 1024 N */
+    uint64_t bytes_bitmap36;   /* 256-bit bitmap + 4-byte offset per node = 36 N */
+    uint64_t bytes_device;     /* device image actually resident in HBM */
+    uint32_t alphabet_size;    /* distinct bytes used by the patterns */
+    uint32_t symbol_bits;      /* bits per symbol in the level index */
+    uint32_t index_depth;      /* K: levels resolved by the level index in LDS */
+    uint32_t lds_bytes;        /* dynamic LDS per workgroup of the scan kernel */
+    double build_seconds;      /* host build time (not part of scan timing) */
+    double upload_seconds;     /* host -> device copy time of the image */
+} pfac_stats;
+
+/* Launch parameters chosen by hand or by pfac_autotune. */
+typedef struct {
+    uint32_t bytes_per_lane;   /* start positions per lane per tile: 4, 8 or 16 */
+    uint32_t index_bits;       /* level-index width in bits (8..18); depth K = bits / symbol_bits */
+    uint32_t wg_per_cu;        /* persistent workgroups per compute unit (1..8, 0 = occupancy max) */
+    uint32_t reserved;
+} pfac_tuning;
+
+/* ----------------------------------------------------------------- errors */
+
+/* Last HIP error code seen by this thread (0 = hipSuccess). */
+int pfac_last_hip_error(void);
+/* Static description of a PFAC_E* code. */
+const char *pfac_strerror(int code);
+
+/* ------------------------------------------------------------------ build */
+
+/*
+ * Build the CRS trie of `n_patterns` patterns (Design and Implementation,
+ * steps I, II, VI and the CRS step) and, unless PFAC_BUILD_HOST_ONLY, upload
+ * its device image to the current HIP device.  Pattern j is
+ * patterns[j][0 .. lengths[j]).  The bytes are copied; the caller may free
+ * them on return.  n_patterns = 0 is valid (nothing ever matches).
+ * Errors: PFAC_EINVAL (out == NULL, or n_patterns > 0 with NULL arrays),
+ * PFAC_EEMPTY (some lengths[j] == 0), PFAC_ENOMEM, PFAC_EDEVICE.
+ */
+int pfac_build(const uint8_t *const *patterns, const uint64_t *lengths, uint32_t n_patterns,
+               uint32_t flags, pfac_trie **out);
+
+/*
+ * Same as pfac_build with the patterns stored back to back:
+ * pattern j = data[offsets[j] .. offsets[j+1]); offsets has n_patterns + 1
+ * entries, non-decreasing.
+ */
+int pfac_build_packed(const uint8_t *data, const uint64_t *offsets, uint32_t n_patterns,
+                      uint32_t flags, pfac_trie **out);
+
+int pfac_trie_stats(const pfac_trie *t, pfac_stats *out);
+
+/*
+ * Copy the CRS arrays into caller-allocated host arrays (any may be NULL):
+ *   row_ptr[N+1]   edges of node v are row_ptr[v] .. row_ptr[v+1]
+ *   labels[N-1]    edge label (unsigned byte), ascending within a row
+ *   child[N-1]     child node of each edge (breadth-first numbering makes
+ *                  child[e] == e + 1)
+ *   term_ptr[N+1]  pattern ids ending at node v are term_ids[term_ptr[v] ..
+ *   term_ids[k]    term_ptr[v+1]), ascending
+ * Nodes are numbered breadth first, children by ascending label.
+ */
+int pfac_trie_export(const pfac_trie *t, uint32_t *row_ptr, uint8_t *labels, uint32_t *child,
+                     uint32_t *term_ptr, uint32_t *term_ids);
+
+/* Free a trie and its device image.  NULL is ignored. */
+void pfac_trie_free(pfac_trie *t);
+
+/* Current / new launch parameters.  Setting them may rebuild the level
+ * index on the host and re-upload it (synchronous). */
+int pfac_trie_get_tuning(const pfac_trie *t, pfac_tuning *out);
+int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tuning);
+
+/* -------------------------------------------------------------- workspace */
+
+/* Device scratch for scans: match staging, per-tile counts, plan tables.
+ * It grows on demand (hipMalloc) and is reused across calls. */
+int pfac_workspace_create(pfac_workspace **out);
+void pfac_workspace_free(pfac_workspace *w);
+/* Pre-size the scratch for texts of up to `max_bytes` bytes, `max_texts`
+ * texts and `max_matches` matches, so later scans allocate nothing. */
+int pfac_workspace_reserve(pfac_workspace *w, uint64_t max_bytes, uint32_t max_texts,
+                           uint64_t max_matches);
+
+/*
+ * Instrumentation: when both events are set (hipEvent_t, NULL to clear),
+ * every later scan on this workspace records `start_event` on its stream
+ * right before the main scan kernel and `stop_event` right after it, so the
+ * caller can time that kernel alone.  The events are only recorded, never
+ * created or destroyed, by the library.
+ */
+int pfac_workspace_set_timing(pfac_workspace *w, void *start_event, void *stop_event);
+
+/* ------------------------------------------------------------------- scan */
+
+/*
+ * Scan one text of n bytes at text_dev.  Writes the sorted matches to
+ * out_dev[0 .. min(count, capacity)) and the exact count to *n_matches_dev
+ * (device uint64).  If counts_dev is not NULL it receives the number of
+ * matches starting at each position, counts_dev[0 .. n).  Asynchronous on
+ * `stream`; n = 0 and an empty trie are valid.  When the count exceeds
+ * capacity the output contents are unspecified: grow and scan again.
+ * Errors: PFAC_EINVAL, PFAC_ENODEV, PFAC_ENOMEM, PFAC_EDEVICE.
+ */
+int pfac_scan(const pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev, uint64_t n,
+              pfac_match *out_dev, uint64_t capacity, uint64_t *n_matches_dev,
+              uint32_t *counts_dev, void *stream);
+
+/* pfac_scan, then wait for `stream` and return the count in *n_matches_host;
+ * returns PFAC_ETRUNC when it exceeds capacity. */
+int pfac_scan_sync(const pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev, uint64_t n,
+                   pfac_match *out_dev, uint64_t capacity, uint64_t *n_matches_host,
+                   uint32_t *counts_dev, void *stream);
+
+/*
+ * Scan a batch of texts stored back to back in one device buffer: text i is
+ * texts_dev[offsets[i] .. offsets[i+1]), offsets_dev has n_texts + 1
+ * non-decreasing device uint64 entries with offsets[0] == 0 and
+ * offsets[n_texts] == total_bytes (empty texts are allowed).  One persistent
+ * launch covers every text; tiles span text boundaries and every walk stops
+ * at the end of its own text.  Results carry text_id.  Asynchronous.
+ */
+int pfac_scan_batch(const pfac_trie *t, pfac_workspace *w, const uint8_t *texts_dev,
+                    const uint64_t *offsets_dev, uint32_t n_texts, uint64_t total_bytes,
+                    pfac_match *out_dev, uint64_t capacity, uint64_t *n_matches_dev,
+                    void *stream);
+
+/*
+ * Baseline for the batched scan: one pfac_scan launch per text, in order,
+ * each writing at the running output offset.  Needs the offsets on the host
+ * (offsets_host, n_texts + 1 entries) to size every launch; writes the total
+ * count to *n_matches_dev.  Same output as pfac_scan_batch.
+ */
+int pfac_scan_batch_plain(const pfac_trie *t, pfac_workspace *w, const uint8_t *texts_dev,
+                          const uint64_t *offsets_host, uint32_t n_texts,
+                          pfac_match *out_dev, uint64_t capacity, uint64_t *n_matches_dev,
+                          void *stream);
+
+/*
+ * Capture pfac_scan_batch with these exact arguments into a HIP graph and
+ * instantiate it.  Replays read the texts, offsets and outputs at the same
+ * device addresses, so the caller may refill them between replays as long
+ * as n_texts and total_bytes stay the same.
+ */
+int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w, const uint8_t *texts_dev,
+                            const uint64_t *offsets_dev, uint32_t n_texts, uint64_t total_bytes,
+                            pfac_match *out_dev, uint64_t capacity, uint64_t *n_matches_dev,
+                            void *stream, pfac_graph **out);
+int pfac_graph_launch(pfac_graph *g, void *stream);
+void pfac_graph_free(pfac_graph *g);
+
+/*
+ * Time a grid of launch parameters on the given text (device buffer, n
+ * bytes), keep the fastest in the trie and return it in *best.  Every
+ * candidate's match list is checked against the current parameters' list;
+ * a candidate that disagrees is discarded.  Results are cached per
+ * (trie, size bucket) for the life of the trie.  Synchronous.
+ */
+int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev, uint64_t n,
+                  void *stream, pfac_tuning *best);
+
+/* ---------------------------------------------------------------- serving */
+
+/*
+ * Continuous-batching scan server over one resident trie.
+ *   arena_dev / arena_bytes: caller-owned device memory the server carves
+ *     into text slots and result buffers (it allocates no text memory itself);
+ *   budget_bytes: cap on text bytes + reserved result bytes in flight
+ *     (<= arena_bytes);
+ *   max_batch: most requests in one batched launch;
+ *   compute_stream / copy_stream: scans run on the first, host<->device
+ *     copies on the second, so copies overlap scans.
+ * A worker thread admits queued requests in arrival order as budget and
+ * slots free up, copies them to the device, and launches one batched scan
+ * over every request whose copy has landed while the previous batch runs.
+ */
+int pfac_server_create(const pfac_trie *t, void *arena_dev, uint64_t arena_bytes,
+                       uint64_t budget_bytes, uint32_t max_batch, void *compute_stream,
+                       void *copy_stream, pfac_server **out);
+
+/*
+ * Queue a scan of text_host[0 .. n).  The bytes are read until the request
+ * completes, so the buffer must stay valid until pfac_server_wait returns
+ * for it.  Returns the request id in *request_id.  PFAC_EINVAL if a single
+ * request can never fit the budget.
+ */
+int pfac_server_submit(pfac_server *s, const uint8_t *text_host, uint64_t n,
+                       uint64_t *request_id);
+
+/*
+ * Wait for a request (timeout_ms < 0: forever).  On PFAC_OK, *n_matches holds
+ * its match count and, if out_host is not NULL, up to `capacity` matches are
+ * copied there (text_id = 0, positions relative to the request's text).
+ * PFAC_ETRUNC when the count exceeds capacity (count still exact).
+ * latency_s (optional) receives submit-to-completion seconds.  Returns
+ * PFAC_EBUSY on timeout.  Each request may be waited for once.
+ */
+int pfac_server_wait(pfac_server *s, uint64_t request_id, int64_t timeout_ms,
+                     pfac_match *out_host, uint64_t capacity, uint64_t *n_matches,
+                     double *latency_s);
+
+/* Counters since creation: requests completed, batches launched, text bytes scanned. */
+int pfac_server_stats(const pfac_server *s, uint64_t *requests, uint64_t *batches,
+                      uint64_t *bytes);
+
+/* Finish every queued request, stop the worker and free the server. */
+void pfac_server_free(pfac_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PFAC_H */

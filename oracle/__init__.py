@@ -118,6 +118,9 @@ def _texts(text, offsets) -> Tuple[np.ndarray, np.ndarray]:
 class Matches(dict):
     """Result arrays: 'text' (uint32), 'pos' (uint64), 'id' (uint32), sorted by (text, pos, id)."""
 
+    def __repr__(self):
+        return f"Matches(n={self.n})"
+
     @property
     def n(self) -> int:
         return int(self["pos"].size)

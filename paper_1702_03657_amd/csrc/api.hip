@@ -1,0 +1,688 @@
+// C ABI of the scanner: trie objects, device images, workspaces, scans,
+// batched scans, graph capture and autotuning.  Every step of a scan runs in
+// the kernels of kernels.hip; this file only plans launches and owns memory.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pfac.h"
+#include "kernels.hpp"
+#include "trie.hpp"
+
+using namespace pfac;
+
+static thread_local int g_last_hip = 0;
+
+static int hip_fail(hipError_t e) {
+    g_last_hip = (int)e;
+    return e == hipErrorOutOfMemory ? PFAC_ENOMEM : PFAC_EDEVICE;
+}
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return hip_fail(e_);     \
+    } while (0)
+
+struct DeviceBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    // grow to at least `need` bytes; contents are not preserved
+    hipError_t reserve(size_t need) {
+        if (need <= bytes) return hipSuccess;
+        release();
+        size_t want = std::max<size_t>(need, 256);
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        bytes = want;
+        return hipSuccess;
+    }
+};
+
+struct pfac_trie {
+    CrsTrie crs;
+    DeviceImageHost img;
+    pfac_tuning tuning{16, 16, 0, 0};
+    bool host_only = false;
+    int device = -1;
+    int n_cu = 0;
+    DeviceBuf dev;
+    ImageView view{};
+    uint32_t halo = 16;
+    double build_s = 0, upload_s = 0;
+    std::map<uint32_t, pfac_tuning> tuned;  // by log2 size bucket
+    std::mutex mu;
+};
+
+struct pfac_workspace {
+    DeviceBuf stage, unit_count, unit_off, blocksum, tile_first, misc;
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // optional kernel timing
+    // misc: [0] stage cursor, [1] running total, [2] per-launch count
+    unsigned long long *cursor() { return (unsigned long long *)misc.p; }
+    unsigned long long *running() { return (unsigned long long *)misc.p + 1; }
+    uint64_t *tmp_count() { return (uint64_t *)misc.p + 2; }
+};
+
+struct pfac_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+extern "C" int pfac_last_hip_error(void) { return g_last_hip; }
+
+extern "C" const char *pfac_strerror(int code) {
+    switch (code) {
+        case PFAC_OK: return "ok";
+        case PFAC_EINVAL: return "invalid argument";
+        case PFAC_EEMPTY: return "empty pattern";
+        case PFAC_ENOMEM: return "out of memory";
+        case PFAC_EDEVICE: return "HIP error";
+        case PFAC_ETRUNC: return "more matches than capacity";
+        case PFAC_ENODEV: return "trie has no device image";
+        case PFAC_EBUSY: return "busy";
+        default: return "unknown error";
+    }
+}
+
+// ------------------------------------------------------------- device image
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static int upload_image(pfac_trie *t) {
+    const DeviceImageHost &I = t->img;
+    size_t o_node = 0;
+    size_t o_label = align256(o_node + I.node.size() * 4);
+    size_t o_pptr = align256(o_label + I.label.size() + 16);
+    size_t o_pids = align256(o_pptr + I.pout_ptr.size() * 4);
+    size_t o_lvl = align256(o_pids + I.pout_ids.size() * 4);
+    size_t o_sym = align256(o_lvl + std::max<size_t>(I.lvl.size(), 2) * 4);
+    size_t total = align256(o_sym + 256);
+    auto t0 = std::chrono::steady_clock::now();
+    t->dev.release();
+    HIP_TRY(t->dev.reserve(total));
+    uint8_t *b = (uint8_t *)t->dev.p;
+    HIP_TRY(hipMemcpy(b + o_node, I.node.data(), I.node.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b + o_label, I.label.data(), I.label.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b + o_pptr, I.pout_ptr.data(), I.pout_ptr.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b + o_pids, I.pout_ids.data(), I.pout_ids.size() * 4, hipMemcpyHostToDevice));
+    if (!I.lvl.empty())
+        HIP_TRY(hipMemcpy(b + o_lvl, I.lvl.data(), I.lvl.size() * 4, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(b + o_sym, I.sym.data(), 256, hipMemcpyHostToDevice));
+    ImageView &v = t->view;
+    v.node = (const uint4 *)(b + o_node);
+    v.label = b + o_label;
+    v.pout_ptr = (const uint32_t *)(b + o_pptr);
+    v.pout_ids = (const uint32_t *)(b + o_pids);
+    v.lvl = (const uint32_t *)(b + o_lvl);
+    v.sym = b + o_sym;
+    v.K = I.K;
+    v.b = I.b;
+    v.identity = I.identity;
+    v.lvl_words = I.lvl_words;
+    v.lvl_start = I.lvl_start;
+    v.max_len = (uint32_t)std::min<uint64_t>(t->crs.max_len, 0xffffffffu);
+    v.n_nodes = t->crs.n_nodes();
+    t->upload_s =
+        std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return PFAC_OK;
+}
+
+static void set_halo(pfac_trie *t) {
+    uint64_t need = t->crs.max_len ? t->crs.max_len - 1 : 0;
+    uint64_t h = (need + 15) & ~15ull;
+    t->halo = (uint32_t)std::max<uint64_t>(16, std::min<uint64_t>(h, kHaloCap));
+}
+
+static int build_common(const uint8_t *data, const uint64_t *offsets, uint32_t k, uint32_t flags,
+                        pfac_trie **out) {
+    if (!out) return PFAC_EINVAL;
+    *out = nullptr;
+    if (flags & ~PFAC_BUILD_HOST_ONLY) return PFAC_EINVAL;
+    if (k > 0 && (!offsets || (!data && offsets[k] != offsets[0]))) return PFAC_EINVAL;
+    for (uint32_t j = 0; j < k; j++) {
+        if (offsets[j + 1] < offsets[j]) return PFAC_EINVAL;
+        if (offsets[j + 1] == offsets[j]) return PFAC_EEMPTY;
+    }
+    pfac_trie *t = new (std::nothrow) pfac_trie();
+    if (!t) return PFAC_ENOMEM;
+    auto t0 = std::chrono::steady_clock::now();
+    std::string err;
+    try {
+        if (!build_crs(data, offsets, k, t->crs, err)) {
+            delete t;
+            return PFAC_EINVAL;
+        }
+        pack_image(t->crs, t->tuning.index_bits, t->img);
+    } catch (const std::bad_alloc &) {
+        delete t;
+        return PFAC_ENOMEM;
+    }
+    t->build_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    set_halo(t);
+    t->host_only = (flags & PFAC_BUILD_HOST_ONLY) != 0;
+    if (!t->host_only) {
+        hipError_t e = hipGetDevice(&t->device);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&t->n_cu, hipDeviceAttributeMultiprocessorCount, t->device);
+        if (e != hipSuccess) {
+            delete t;
+            return hip_fail(e);
+        }
+        int rc = upload_image(t);
+        if (rc != PFAC_OK) {
+            t->dev.release();
+            delete t;
+            return rc;
+        }
+    }
+    *out = t;
+    return PFAC_OK;
+}
+
+extern "C" int pfac_build_packed(const uint8_t *data, const uint64_t *offsets, uint32_t n_patterns,
+                                 uint32_t flags, pfac_trie **out) {
+    return build_common(data, offsets, n_patterns, flags, out);
+}
+
+extern "C" int pfac_build(const uint8_t *const *patterns, const uint64_t *lengths,
+                          uint32_t n_patterns, uint32_t flags, pfac_trie **out) {
+    if (!out) return PFAC_EINVAL;
+    *out = nullptr;
+    if (n_patterns > 0 && (!patterns || !lengths)) return PFAC_EINVAL;
+    std::vector<uint64_t> off(n_patterns + 1, 0);
+    for (uint32_t j = 0; j < n_patterns; j++) {
+        if (lengths[j] == 0) return PFAC_EEMPTY;
+        if (!patterns[j]) return PFAC_EINVAL;
+        off[j + 1] = off[j] + lengths[j];
+    }
+    std::vector<uint8_t> data;
+    try {
+        data.resize(off[n_patterns]);
+    } catch (const std::bad_alloc &) {
+        return PFAC_ENOMEM;
+    }
+    for (uint32_t j = 0; j < n_patterns; j++)
+        std::memcpy(data.data() + off[j], patterns[j], lengths[j]);
+    return build_common(data.data(), off.data(), n_patterns, flags, out);
+}
+
+static uint32_t lds_bytes_for(const pfac_trie *t, uint32_t bpl) {
+    ScanArgs a{};
+    a.im = t->view;
+    a.im.lvl_words = t->img.lvl_words;
+    a.im.identity = t->img.identity;
+    a.halo = t->halo;
+    lds_layout(a, bpl);
+    return a.lds_total;
+}
+
+extern "C" int pfac_trie_stats(const pfac_trie *t, pfac_stats *o) {
+    if (!t || !o) return PFAC_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    const CrsTrie &c = t->crs;
+    uint64_t N = c.n_nodes(), E = c.n_edges();
+    o->nodes = N;
+    o->edges = E;
+    o->n_patterns = c.k;
+    o->min_len = c.min_len;
+    o->max_len = c.max_len;
+    o->depth = c.level_start.size() >= 2 ? c.level_start.size() - 2 : 0;
+    o->bytes_crs = 4 * (N + 1) + E + 4 * E + 4 * (N + 1) + 4ull * c.k;
+    o->crs_elements = 2 * E + N + 1;
+    o->bytes_dense256 = 1024 * N;
+    o->bytes_bitmap36 = 36 * N;
+    o->bytes_device = t->dev.bytes;
+    o->alphabet_size = t->img.alphabet;
+    o->symbol_bits = t->img.b;
+    o->index_depth = t->img.K;
+    o->lds_bytes = lds_bytes_for(t, t->tuning.bytes_per_lane);
+    o->build_seconds = t->build_s;
+    o->upload_seconds = t->upload_s;
+    return PFAC_OK;
+}
+
+extern "C" int pfac_trie_export(const pfac_trie *t, uint32_t *row_ptr, uint8_t *labels,
+                                uint32_t *child, uint32_t *term_ptr, uint32_t *term_ids) {
+    if (!t) return PFAC_EINVAL;
+    const CrsTrie &c = t->crs;
+    if (row_ptr) std::memcpy(row_ptr, c.row_ptr.data(), c.row_ptr.size() * 4);
+    if (labels && !c.labels.empty()) std::memcpy(labels, c.labels.data(), c.labels.size());
+    if (child)
+        for (uint32_t e = 0; e < c.n_edges(); e++) child[e] = e + 1;
+    if (term_ptr) std::memcpy(term_ptr, c.term_ptr.data(), c.term_ptr.size() * 4);
+    if (term_ids && !c.term_ids.empty()) std::memcpy(term_ids, c.term_ids.data(), c.term_ids.size() * 4);
+    return PFAC_OK;
+}
+
+extern "C" void pfac_trie_free(pfac_trie *t) {
+    if (!t) return;
+    t->dev.release();
+    delete t;
+}
+
+extern "C" int pfac_trie_get_tuning(const pfac_trie *t, pfac_tuning *out) {
+    if (!t || !out) return PFAC_EINVAL;
+    *out = t->tuning;
+    return PFAC_OK;
+}
+
+static bool valid_tuning(const pfac_tuning *p) {
+    return (p->bytes_per_lane == 4 || p->bytes_per_lane == 8 || p->bytes_per_lane == 16) &&
+           p->index_bits >= 1 && p->index_bits <= 18 && p->wg_per_cu <= 8;
+}
+
+extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
+    if (!t || !tn || !valid_tuning(tn)) return PFAC_EINVAL;
+    const bool repack = tn->index_bits != t->tuning.index_bits;
+    t->tuning = *tn;
+    if (repack) {
+        try {
+            pack_image(t->crs, t->tuning.index_bits, t->img);
+        } catch (const std::bad_alloc &) {
+            return PFAC_ENOMEM;
+        }
+        if (!t->host_only) return upload_image(t);
+    }
+    return PFAC_OK;
+}
+
+// ---------------------------------------------------------------- workspace
+
+extern "C" int pfac_workspace_create(pfac_workspace **out) {
+    if (!out) return PFAC_EINVAL;
+    pfac_workspace *w = new (std::nothrow) pfac_workspace();
+    if (!w) return PFAC_ENOMEM;
+    hipError_t e = w->misc.reserve(256);
+    if (e == hipSuccess) e = hipMemset(w->misc.p, 0, 256);
+    if (e != hipSuccess) {
+        delete w;
+        *out = nullptr;
+        return hip_fail(e);
+    }
+    *out = w;
+    return PFAC_OK;
+}
+
+extern "C" void pfac_workspace_free(pfac_workspace *w) {
+    if (!w) return;
+    w->stage.release();
+    w->unit_count.release();
+    w->unit_off.release();
+    w->blocksum.release();
+    w->tile_first.release();
+    w->misc.release();
+    delete w;
+}
+
+static int ws_reserve(pfac_workspace *w, uint64_t n_tiles, uint64_t capacity) {
+    uint64_t n_blocks = std::max<uint64_t>(1, (n_tiles + (1u << kTpbShift) - 1) >> kTpbShift);
+    HIP_TRY(w->unit_count.reserve(std::max<uint64_t>(n_tiles, 1) * 4));
+    HIP_TRY(w->unit_off.reserve(std::max<uint64_t>(n_tiles, 1) * 8));
+    HIP_TRY(w->tile_first.reserve(std::max<uint64_t>(n_tiles, 1) * 4));
+    HIP_TRY(w->blocksum.reserve(n_blocks * 8));
+    HIP_TRY(w->stage.reserve(std::max<uint64_t>(capacity, 1) * sizeof(pfac_match)));
+    return PFAC_OK;
+}
+
+extern "C" int pfac_workspace_set_timing(pfac_workspace *w, void *start_event, void *stop_event) {
+    if (!w || (!start_event) != (!stop_event)) return PFAC_EINVAL;
+    w->ev_start = (hipEvent_t)start_event;
+    w->ev_stop = (hipEvent_t)stop_event;
+    return PFAC_OK;
+}
+
+extern "C" int pfac_workspace_reserve(pfac_workspace *w, uint64_t max_bytes, uint32_t max_texts,
+                                      uint64_t max_matches) {
+    (void)max_texts;
+    if (!w) return PFAC_EINVAL;
+    uint64_t n_tiles = (max_bytes + 16 + kWG * 4 - 1) / (kWG * 4);  // smallest tile
+    return ws_reserve(w, n_tiles, max_matches);
+}
+
+// ---------------------------------------------------------------------- scan
+
+struct Launch {
+    const pfac_trie *t;
+    pfac_workspace *w;
+    const uint8_t *text;
+    uint64_t total;
+    const uint64_t *offsets;    // device, NULL for one text
+    uint32_t n_texts;
+    uint32_t text_id0;
+    pfac_match *out;
+    uint64_t capacity;
+    uint64_t *n_matches;
+    uint32_t *counts;
+    const unsigned long long *base_dev;
+    hipStream_t s;
+};
+
+static uint64_t tiles_for(uint64_t total, uint64_t shift, uint32_t tile) {
+    return total ? (shift + total + tile - 1) / tile : 0;
+}
+
+static int enqueue_scan(const Launch &L, bool reserve) {
+    const pfac_trie *t = L.t;
+    const uint32_t bpl = t->tuning.bytes_per_lane;
+    const uint32_t tile = kWG * bpl;
+    const uintptr_t addr = (uintptr_t)L.text;
+    const uint64_t shift = addr & 15;
+    uint64_t n_tiles = tiles_for(L.total, shift, tile);
+    if (t->crs.k == 0) n_tiles = 0;  // nothing can match
+    if (reserve) {
+        int rc = ws_reserve(L.w, n_tiles, L.capacity);
+        if (rc != PFAC_OK) return rc;
+    }
+    pfac_workspace *w = L.w;
+    const uint32_t n_blocks = (uint32_t)std::max<uint64_t>(1, (n_tiles + (1u << kTpbShift) - 1) >> kTpbShift);
+
+    ScanArgs a{};
+    a.im = t->view;
+    a.base = (const uint8_t *)(addr - shift);
+    a.shift = shift;
+    a.total = L.total;
+    a.offsets = L.offsets;
+    a.n_texts = L.n_texts;
+    a.text_id0 = L.text_id0;
+    a.tile_first_text = L.offsets ? (const uint32_t *)w->tile_first.p : nullptr;
+    a.n_tiles = n_tiles;
+    a.halo = t->halo;
+    lds_layout(a, bpl);
+    a.stage = (pfac_match *)w->stage.p;
+    a.stage_cap = std::min<uint64_t>(L.capacity, w->stage.bytes / sizeof(pfac_match));
+    a.stage_cursor = w->cursor();
+    a.unit_count = (uint32_t *)w->unit_count.p;
+    a.unit_off = (unsigned long long *)w->unit_off.p;
+    a.blocksum = (unsigned long long *)w->blocksum.p;
+    a.counts = L.counts;
+
+    HIP_TRY(launch_reset(a.stage_cursor, a.blocksum, n_blocks, L.s));
+    if (L.counts) HIP_TRY(launch_fill_u32(L.counts, L.total, 0, L.s));
+    if (n_tiles) {
+        if (L.offsets)
+            HIP_TRY(launch_plan(L.offsets, L.n_texts, shift, n_tiles, tile,
+                                (uint32_t *)w->tile_first.p, L.s));
+        if (a.lds_total > 64 * 1024) {
+            // kernels need an explicit opt-in above 64 KiB of dynamic LDS
+            static std::mutex mu;
+            static uint32_t granted[3] = {0, 0, 0};
+            const int slot = bpl == 4 ? 0 : bpl == 8 ? 1 : 2;
+            std::lock_guard<std::mutex> lock(mu);
+            if (granted[slot] < a.lds_total) {
+                HIP_TRY(prepare_kernels(bpl, a.lds_total));
+                granted[slot] = a.lds_total;
+            }
+        }
+        int per_cu = (int)t->tuning.wg_per_cu;
+        const int occ = max_wg_per_cu(bpl, a.lds_total);
+        if (per_cu == 0 || per_cu > occ) per_cu = occ;
+        const uint64_t resident = (uint64_t)std::max(1, t->n_cu) * (uint64_t)per_cu;
+        const uint32_t grid = (uint32_t)std::min<uint64_t>(n_tiles, resident);
+        if (w->ev_start) HIP_TRY(hipEventRecord(w->ev_start, L.s));
+        HIP_TRY(launch_scan(a, bpl, grid, L.s));
+        if (w->ev_stop) HIP_TRY(hipEventRecord(w->ev_stop, L.s));
+    }
+    FinishArgs f{};
+    f.unit_count = a.unit_count;
+    f.unit_off = a.unit_off;
+    f.blocksum = a.blocksum;
+    f.stage = a.stage;
+    f.stage_cap = a.stage_cap;
+    f.n_tiles = n_tiles;
+    f.n_blocks = n_blocks;
+    f.out = L.out;
+    f.capacity = L.out ? L.capacity : 0;
+    f.n_matches = L.n_matches;
+    f.base_dev = L.base_dev;
+    HIP_TRY(launch_finish(f, L.s));
+    return PFAC_OK;
+}
+
+static int check_scan_args(const pfac_trie *t, pfac_workspace *w, const void *text, uint64_t n,
+                           const void *out, uint64_t capacity, const void *n_matches) {
+    if (!t || !w || !n_matches) return PFAC_EINVAL;
+    if (t->host_only) return PFAC_ENODEV;
+    if (n > 0 && !text) return PFAC_EINVAL;
+    if (capacity > 0 && !out) return PFAC_EINVAL;
+    return PFAC_OK;
+}
+
+extern "C" int pfac_scan(const pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev,
+                         uint64_t n, pfac_match *out_dev, uint64_t capacity,
+                         uint64_t *n_matches_dev, uint32_t *counts_dev, void *stream) {
+    int rc = check_scan_args(t, w, text_dev, n, out_dev, capacity, n_matches_dev);
+    if (rc) return rc;
+    Launch L{t, w, text_dev, n, nullptr, 1, 0, out_dev, capacity, n_matches_dev, counts_dev,
+             nullptr, (hipStream_t)stream};
+    return enqueue_scan(L, true);
+}
+
+extern "C" int pfac_scan_sync(const pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev,
+                              uint64_t n, pfac_match *out_dev, uint64_t capacity,
+                              uint64_t *n_matches_host, uint32_t *counts_dev, void *stream) {
+    if (!n_matches_host || !w) return PFAC_EINVAL;
+    uint64_t *dcount = w->tmp_count();
+    int rc = pfac_scan(t, w, text_dev, n, out_dev, capacity, dcount, counts_dev, stream);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(n_matches_host, dcount, 8, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    return *n_matches_host > capacity ? PFAC_ETRUNC : PFAC_OK;
+}
+
+extern "C" int pfac_scan_batch(const pfac_trie *t, pfac_workspace *w, const uint8_t *texts_dev,
+                               const uint64_t *offsets_dev, uint32_t n_texts, uint64_t total_bytes,
+                               pfac_match *out_dev, uint64_t capacity, uint64_t *n_matches_dev,
+                               void *stream) {
+    int rc = check_scan_args(t, w, texts_dev, total_bytes, out_dev, capacity, n_matches_dev);
+    if (rc) return rc;
+    if (!offsets_dev || (n_texts == 0 && total_bytes != 0)) return PFAC_EINVAL;
+    Launch L{t, w, texts_dev, total_bytes, offsets_dev, n_texts, 0, out_dev, capacity,
+             n_matches_dev, nullptr, nullptr, (hipStream_t)stream};
+    return enqueue_scan(L, true);
+}
+
+extern "C" int pfac_scan_batch_plain(const pfac_trie *t, pfac_workspace *w,
+                                     const uint8_t *texts_dev, const uint64_t *offsets_host,
+                                     uint32_t n_texts, pfac_match *out_dev, uint64_t capacity,
+                                     uint64_t *n_matches_dev, void *stream) {
+    uint64_t total = (n_texts && offsets_host) ? offsets_host[n_texts] - offsets_host[0] : 0;
+    int rc = check_scan_args(t, w, texts_dev, total, out_dev, capacity, n_matches_dev);
+    if (rc) return rc;
+    if (!offsets_host) return PFAC_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    uint64_t max_tiles = 0;
+    for (uint32_t i = 0; i < n_texts; i++) {
+        if (offsets_host[i + 1] < offsets_host[i]) return PFAC_EINVAL;
+        max_tiles = std::max(max_tiles, tiles_for(offsets_host[i + 1] - offsets_host[i], 15,
+                                                  kWG * t->tuning.bytes_per_lane));
+    }
+    rc = ws_reserve(w, max_tiles, capacity);
+    if (rc) return rc;
+    HIP_TRY(launch_fill_u32((uint32_t *)w->running(), 2, 0, s));
+    for (uint32_t i = 0; i < n_texts; i++) {
+        const uint64_t n = offsets_host[i + 1] - offsets_host[i];
+        if (n == 0) continue;
+        Launch L{t, w, texts_dev + offsets_host[i], n, nullptr, 1, i, out_dev, capacity,
+                 w->tmp_count(), nullptr, w->running(), s};
+        rc = enqueue_scan(L, false);
+        if (rc) return rc;
+        HIP_TRY(launch_add_running(w->running(), w->tmp_count(), s));
+    }
+    HIP_TRY(launch_copy_u64(n_matches_dev, w->running(), s));
+    return PFAC_OK;
+}
+
+// ------------------------------------------------------------------- graphs
+
+extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
+                                       const uint8_t *texts_dev, const uint64_t *offsets_dev,
+                                       uint32_t n_texts, uint64_t total_bytes,
+                                       pfac_match *out_dev, uint64_t capacity,
+                                       uint64_t *n_matches_dev, void *stream, pfac_graph **out) {
+    if (!out) return PFAC_EINVAL;
+    *out = nullptr;
+    int rc = check_scan_args(t, w, texts_dev, total_bytes, out_dev, capacity, n_matches_dev);
+    if (rc) return rc;
+    if (!offsets_dev) return PFAC_EINVAL;
+    const uint32_t tile = kWG * t->tuning.bytes_per_lane;
+    rc = ws_reserve(w, tiles_for(total_bytes, 15, tile), capacity);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    hipStream_t own = nullptr;
+    if (!s) {
+        HIP_TRY(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        s = own;
+    }
+    pfac_graph *g = new (std::nothrow) pfac_graph();
+    if (!g) {
+        if (own) (void)hipStreamDestroy(own);
+        return PFAC_ENOMEM;
+    }
+    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        Launch L{t, w, texts_dev, total_bytes, offsets_dev, n_texts, 0, out_dev, capacity,
+                 n_matches_dev, nullptr, nullptr, s};
+        rc = enqueue_scan(L, false);
+        hipError_t e2 = hipStreamEndCapture(s, &g->graph);
+        if (rc == PFAC_OK && e2 != hipSuccess) rc = hip_fail(e2);
+        if (rc == PFAC_OK) {
+            e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+            if (e != hipSuccess) rc = hip_fail(e);
+        }
+    } else {
+        rc = hip_fail(e);
+    }
+    if (own) (void)hipStreamDestroy(own);
+    if (rc != PFAC_OK) {
+        pfac_graph_free(g);
+        return rc;
+    }
+    *out = g;
+    return PFAC_OK;
+}
+
+extern "C" int pfac_graph_launch(pfac_graph *g, void *stream) {
+    if (!g || !g->exec) return PFAC_EINVAL;
+    HIP_TRY(hipGraphLaunch(g->exec, (hipStream_t)stream));
+    return PFAC_OK;
+}
+
+extern "C" void pfac_graph_free(pfac_graph *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+}
+
+// ----------------------------------------------------------------- autotune
+
+static uint32_t size_bucket(uint64_t n) {
+    uint32_t b = 0;
+    while ((1ull << b) < n && b < 63) b++;
+    return b;
+}
+
+extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev, uint64_t n,
+                             void *stream, pfac_tuning *best) {
+    if (!t || !w || (!text_dev && n) || !best) return PFAC_EINVAL;
+    if (t->host_only) return PFAC_ENODEV;
+    std::lock_guard<std::mutex> lock(t->mu);
+    const uint32_t bucket = size_bucket(n);
+    auto it = t->tuned.find(bucket);
+    if (it != t->tuned.end()) {
+        *best = it->second;
+        return pfac_trie_set_tuning(t, best);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const pfac_tuning start = t->tuning;
+    uint64_t *dcount = w->tmp_count();
+
+    // reference list with the starting parameters
+    uint64_t ref_n = 0;
+    int rc = pfac_scan_sync(t, w, text_dev, n, nullptr, 0, &ref_n, nullptr, stream);
+    if (rc != PFAC_OK && rc != PFAC_ETRUNC) return rc;
+    const uint64_t cap = ref_n;
+    pfac_match *dref = nullptr, *dcand = nullptr;
+    if (cap) {
+        HIP_TRY(hipMalloc(&dref, cap * sizeof(pfac_match)));
+        if (hipMalloc(&dcand, cap * sizeof(pfac_match)) != hipSuccess) {
+            (void)hipFree(dref);
+            return PFAC_ENOMEM;
+        }
+    }
+    std::vector<pfac_match> href(cap), hcand(cap);
+    auto cleanup = [&] {
+        if (dref) (void)hipFree(dref);
+        if (dcand) (void)hipFree(dcand);
+    };
+    uint64_t got = 0;
+    rc = pfac_scan_sync(t, w, text_dev, n, dref, cap, &got, nullptr, stream);
+    if (rc == PFAC_OK && cap)
+        if (hipMemcpy(href.data(), dref, cap * sizeof(pfac_match), hipMemcpyDeviceToHost) != hipSuccess)
+            rc = PFAC_EDEVICE;
+    if (rc != PFAC_OK) {
+        cleanup();
+        return rc;
+    }
+
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    std::vector<pfac_tuning> cands;
+    for (uint32_t bpl : {4u, 8u, 16u})
+        for (uint32_t bits : {12u, 14u, 16u, 18u})
+            for (uint32_t wpc : {0u, 2u, 4u}) cands.push_back({bpl, bits, wpc, 0});
+    float best_ms = 1e30f;
+    pfac_tuning best_t = start;
+    std::vector<uint64_t> seen;  // (bytes per lane, index depth, wg per CU) already timed
+    for (const pfac_tuning &c : cands) {
+        if (pfac_trie_set_tuning(t, &c) != PFAC_OK) continue;
+        // index widths that give the same depth K and symbol width repeat a point
+        const uint64_t key = ((uint64_t)c.bytes_per_lane << 48) | ((uint64_t)t->img.K << 32) |
+                             ((uint64_t)t->img.b << 16) | c.wg_per_cu;
+        if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+        seen.push_back(key);
+        uint64_t cn = 0;
+        if (pfac_scan_sync(t, w, text_dev, n, dcand, cap, &cn, nullptr, stream) != PFAC_OK) continue;
+        if (cn != ref_n) continue;
+        if (cap && (hipMemcpy(hcand.data(), dcand, cap * sizeof(pfac_match), hipMemcpyDeviceToHost) != hipSuccess ||
+                    std::memcmp(hcand.data(), href.data(), cap * sizeof(pfac_match)) != 0))
+            continue;
+        std::vector<float> ms;
+        for (int rep = 0; rep < 5; rep++) {
+            (void)hipEventRecord(e0, s);
+            if (pfac_scan(t, w, text_dev, n, dcand, cap, dcount, nullptr, stream) != PFAC_OK) break;
+            (void)hipEventRecord(e1, s);
+            (void)hipEventSynchronize(e1);
+            float m = 0;
+            (void)hipEventElapsedTime(&m, e0, e1);
+            ms.push_back(m);
+        }
+        if (ms.size() < 5) continue;
+        std::sort(ms.begin(), ms.end());
+        if (ms[2] < best_ms) {
+            best_ms = ms[2];
+            best_t = c;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    cleanup();
+    t->tuned[bucket] = best_t;
+    *best = best_t;
+    return pfac_trie_set_tuning(t, &best_t);
+}

@@ -1,0 +1,637 @@
+// Scan kernels for gfx950: the failure-less Aho-Corasick walk of Background,
+// "Parallel Failure-Less Aho-Corasick" over the CRS trie of Design and
+// Implementation.
+//
+// Work decomposition.  The texts form one byte frame starting at a 16-byte
+// aligned address.  A tile is kWG * BPL consecutive start positions; a
+// persistent workgroup takes tiles round robin and, for each tile,
+//   1. stages the tile plus a halo of >= (longest pattern - 1) bytes into LDS
+//      with 16-byte loads (the overlap rule of Background, "Multi-Pattern
+//      Matching"), and marks every text boundary in the window in an LDS bit
+//      map so that no walk crosses into the next text;
+//   2. filters: each lane holds BPL consecutive start positions and looks
+//      their first K symbols up in the level index (a bitmap over K-symbol
+//      codes of the depth-K nodes, kept in LDS).  A position whose first K
+//      bytes are not a trie prefix cannot match (K < shortest pattern), so it
+//      ends here; survivors are compacted per wave with ballots;
+//   3. walks each survivor from its depth-K node down the CRS trie in global
+//      memory (L2 resident) until a byte has no edge, remembering the deepest
+//      terminal node passed;
+//   4. emits: matched positions are sorted in LDS, their pattern lists counted
+//      and prefix-summed, space is reserved in the staging buffer with one
+//      atomic, and (pos, id) records are written in (pos, id) order.
+// A finisher kernel then orders the tiles: block sums give each tile its
+// output offset and the staged records are copied there.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace pfac {
+
+constexpr uint32_t kNoneD = 0xffffffffu;
+constexpr uint32_t kTermFlagD = 1u << 16;
+
+// ------------------------------------------------------------- wave helpers
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off, 64);
+        if (lane >= (uint32_t)off) x += y;
+    }
+    return x;
+}
+
+__device__ __forceinline__ unsigned long long wave_reduce_u64(unsigned long long x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Exclusive scan over the workgroup in thread order; `tmp` holds kWG/64 words.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t x, uint32_t *tmp, uint32_t &total) {
+    const uint32_t w = threadIdx.x >> 6;
+    uint32_t incl = wave_incl_scan(x);
+    if (lane_id() == 63) tmp[w] = incl;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < kWG / 64; i++) {
+        uint32_t s = tmp[i];
+        before += (i < w) ? s : 0;
+        all += s;
+    }
+    __syncthreads();
+    total = all;
+    return before + incl - x;
+}
+
+// ------------------------------------------------------------------ the walk
+
+struct Tile {
+    const uint8_t *text;      // LDS copy of the window
+    const uint32_t *bnd;      // LDS boundary bits of the window
+    uint64_t lo;              // frame position of window byte 0
+    uint32_t win;             // window bytes in LDS
+    bool dirty;               // some boundary lies in the window
+    uint64_t next_bnd;        // first boundary at or after the window end
+};
+
+// Walk from node v at depth d for the start position at window offset pl;
+// returns the deepest terminal node passed (kNoneD if none).
+__device__ __forceinline__ uint32_t walk(const ImageView &im, const uint8_t *gbase,
+                                         const Tile &T, uint32_t pl, uint32_t v, uint32_t d) {
+    uint32_t vt = kNoneD;
+    for (;;) {
+        const uint4 r = im.node[v];
+        if (r.z & kTermFlagD) vt = v;
+        const uint32_t nc = r.z & 0xffffu;
+        if (nc == 0) break;
+        const uint32_t q = pl + d;
+        uint32_t c;
+        if (q < T.win) {
+            if (T.dirty && ((T.bnd[q >> 5] >> (q & 31)) & 1u)) break;  // next text starts at q
+            c = T.text[q];
+        } else {
+            const uint64_t g = T.lo + q;
+            if (g >= T.next_bnd) break;
+            c = gbase[g];
+        }
+        uint32_t j;
+        if (nc <= 4) {
+            const uint32_t x = r.x ^ (c * 0x01010101u);
+            const uint32_t m = (x - 0x01010101u) & ~x & 0x80808080u;  // lowest flag = first zero byte
+            if (m == 0) break;
+            j = (uint32_t)__builtin_ctz(m) >> 3;
+            if (j >= nc) break;
+        } else {
+            const uint8_t *lab = im.label + (r.y - 1);
+            uint32_t lo = 0, hi = nc;
+            while (lo < hi) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (lab[mid] < c) lo = mid + 1; else hi = mid;
+            }
+            if (lo == nc || lab[lo] != c) break;
+            j = lo;
+        }
+        v = r.y + j;
+        d++;
+    }
+    return vt;
+}
+
+// Text holding frame position g (batch), by binary search over the starts.
+__device__ __forceinline__ uint32_t text_of(const uint64_t *offsets, uint32_t n_texts,
+                                            uint64_t shift, uint64_t g) {
+    uint32_t lo = 0, hi = n_texts;  // answer in [0, n_texts)
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (offsets[mid] + shift <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint32_t pout_count(const ImageView &im, uint32_t vt) {
+    const uint32_t o = im.node[vt].w;
+    return im.pout_ptr[o + 1] - im.pout_ptr[o];
+}
+
+__device__ __forceinline__ void emit(const ScanArgs &a, uint64_t frame_pos, uint32_t vt,
+                                     uint64_t dst) {
+    const ImageView &im = a.im;
+    const uint32_t o = im.node[vt].w;
+    const uint32_t p0 = im.pout_ptr[o], p1 = im.pout_ptr[o + 1];
+    uint32_t tid = 0;
+    uint64_t start = a.shift;
+    if (a.offsets) {
+        tid = text_of(a.offsets, a.n_texts, a.shift, frame_pos);
+        start = a.offsets[tid] + a.shift;
+    }
+    tid += a.text_id0;
+    const uint64_t pos = frame_pos - start;
+    for (uint32_t k = p0; k < p1; k++, dst++) {
+        if (dst < a.stage_cap) {
+            pfac_match m;
+            m.pos = pos;
+            m.pattern_id = im.pout_ids[k];
+            m.text_id = tid;
+            a.stage[dst] = m;
+        }
+    }
+    if (a.counts) a.counts[frame_pos - a.shift] = p1 - p0;
+}
+
+// ------------------------------------------------------------------- scan
+
+template <int BPL, bool IDENT>
+__global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
+    constexpr uint32_t TILE = kWG * BPL;
+    extern __shared__ __align__(16) uint8_t lds[];
+    uint32_t *s_bits = (uint32_t *)(lds + a.off_bits);
+    uint32_t *s_rank = (uint32_t *)(lds + a.off_rank);
+    uint8_t *s_sym = lds + a.off_sym;
+    uint8_t *s_text = lds + a.off_text;
+    uint32_t *s_bnd = (uint32_t *)(lds + a.off_bnd);
+    uint32_t *s_queue = (uint32_t *)(lds + a.off_queue);
+    uint2 *s_match = (uint2 *)(lds + a.off_match);
+    __shared__ uint32_t s_qn[kWG / 64];
+    __shared__ uint32_t s_mn, s_dirty, s_tmp[kWG / 64];
+    __shared__ unsigned long long s_next, s_base;
+
+    const ImageView &im = a.im;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t wave = tid >> 6, lane = tid & 63;
+
+    for (uint32_t i = tid; i < im.lvl_words; i += kWG) {
+        const uint2 e = ((const uint2 *)im.lvl)[i];
+        s_bits[i] = e.x;
+        s_rank[i] = e.y;
+    }
+    if (!IDENT)
+        for (uint32_t i = tid; i < 256; i += kWG) s_sym[i] = im.sym[i];
+
+    const uint32_t win = TILE + a.halo;
+    const uint32_t bnd_words = win / 32 + 2;
+    const uint64_t lo_valid = a.shift, hi_valid = a.shift + a.total;
+    const uint32_t K = im.K;
+    const uint32_t code_mask = (K == 0) ? 0u : ((1u << (im.b * K)) - 1u);
+
+    for (uint64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+        const uint64_t tile_lo = t * TILE;
+        const uint64_t win_end = tile_lo + win;
+        __syncthreads();  // the previous tile is done with LDS
+
+        // ---- 1. stage the window and its boundaries
+        for (uint32_t v = tid; v < win / 16; v += kWG) {
+            const uint64_t g = tile_lo + 16ull * v;
+            uint4 val = make_uint4(0, 0, 0, 0);
+            if (g + 16 > lo_valid && g < hi_valid) {
+                // an aligned 16-byte block holding a text byte lies in a mapped page
+                val = *(const uint4 *)(a.base + g);
+                if (g < lo_valid || g + 16 > hi_valid) {
+                    uint32_t w[4] = {val.x, val.y, val.z, val.w};
+#pragma unroll
+                    for (int q = 0; q < 16; q++) {
+                        const uint64_t p = g + q;
+                        if (p < lo_valid || p >= hi_valid) w[q >> 2] &= ~(0xffu << (8 * (q & 3)));
+                    }
+                    val = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+            }
+            *(uint4 *)(s_text + 16 * v) = val;
+        }
+        for (uint32_t i = tid; i < bnd_words; i += kWG) s_bnd[i] = 0;
+        if (tid == 0) {
+            s_mn = 0;
+            s_dirty = 0;
+            s_next = ~0ull;
+        }
+        __syncthreads();
+        {
+            auto mark = [&](uint64_t bp) -> bool {
+                if (bp >= win_end) {
+                    atomicMin(&s_next, (unsigned long long)bp);
+                    return false;
+                }
+                if (bp >= tile_lo) {
+                    const uint32_t q = (uint32_t)(bp - tile_lo);
+                    atomicOr(&s_bnd[q >> 5], 1u << (q & 31));
+                    s_dirty = 1;
+                }
+                return true;
+            };
+            if (a.offsets == nullptr) {
+                if (tid < 2) mark(tid ? hi_valid : lo_valid);
+            } else {
+                const uint32_t first = a.tile_first_text ? a.tile_first_text[t] : 0u;
+                for (uint32_t r = first;; r += kWG) {
+                    const uint32_t i = r + tid;
+                    bool more = false;
+                    if (i <= a.n_texts) more = mark(a.offsets[i] + a.shift);
+                    if (!__syncthreads_or(more)) break;
+                }
+            }
+        }
+        __syncthreads();
+        Tile T;
+        T.text = s_text;
+        T.bnd = s_bnd;
+        T.lo = tile_lo;
+        T.win = win;
+        T.dirty = s_dirty != 0;
+        T.next_bnd = s_next;
+
+        // ---- 2. filter through the level index; compact survivors per wave
+        uint32_t *wq = s_queue + wave * (64 * BPL);
+        uint32_t qn = 0;  // wave-uniform
+        const uint32_t lb = tid * BPL;
+        if (K == 0) {
+#pragma unroll
+            for (int j = 0; j < BPL; j++) {
+                const uint64_t p = tile_lo + lb + j;
+                const bool ok = p >= lo_valid && p < hi_valid;
+                const unsigned long long m = __ballot(ok);
+                if (ok) {
+                    const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    wq[qn + r] = (lb + j) << 18;
+                }
+                qn += (uint32_t)__popcll(m);
+            }
+        } else {
+            uint32_t w[BPL / 4 + 4];
+#pragma unroll
+            for (int q = 0; q < BPL / 4 + 4; q++) w[q] = *(const uint32_t *)(s_text + lb + 4 * q);
+            unsigned long long brk = 0, inv = 0;
+            if (T.dirty) {
+                const uint32_t b0 = lb >> 5;
+                const unsigned long long bw =
+                    (unsigned long long)s_bnd[b0] | ((unsigned long long)s_bnd[b0 + 1] << 32);
+                brk = bw >> (lb & 31);
+                const uint64_t p0 = tile_lo + lb;
+                if (lo_valid > p0) {
+                    const uint64_t nb = lo_valid - p0;
+                    inv |= nb >= 64 ? ~0ull : ((1ull << nb) - 1);
+                }
+                if (hi_valid < p0 + 64) {
+                    const uint64_t na = hi_valid > p0 ? hi_valid - p0 : 0;
+                    inv |= ~0ull << na;
+                }
+            }
+            const bool plain = IDENT && !T.dirty;
+            const uint32_t b = IDENT ? 8u : im.b;
+            const uint32_t pbase = lb - (K - 1);
+            uint32_t code = 0, run = 0;
+#pragma unroll
+            for (int j = 0; j < BPL + 15; j++) {
+                if ((uint32_t)j >= BPL + K - 1) continue;  // wave-uniform
+                const uint32_t byte = (w[j >> 2] >> (8 * (j & 3))) & 0xffu;
+                uint32_t s = byte;
+                bool ok = true;
+                if (!IDENT) {
+                    s = s_sym[byte];
+                    ok = s != 0xffu;
+                }
+                if (!plain) {
+                    if ((brk >> j) & 1ull) run = 0;
+                    if ((inv >> j) & 1ull) ok = false;
+                    run = ok ? run + 1 : 0;
+                }
+                code = ((code << b) | (s & 0xffu)) & code_mask;
+                if ((uint32_t)j >= K - 1) {
+                    const bool valid = plain || run >= K;
+                    const uint32_t bits = s_bits[code >> 5];
+                    const bool hit = valid && ((bits >> (code & 31)) & 1u);
+                    const unsigned long long m = __ballot(hit);
+                    if (hit) {
+                        const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                           __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        wq[qn + r] = ((pbase + j) << 18) | code;
+                    }
+                    qn += (uint32_t)__popcll(m);
+                }
+            }
+        }
+
+        // ---- 3. walk the survivors of this wave
+        for (uint32_t e = lane; e < qn; e += 64) {
+            const uint32_t ent = wq[e];
+            const uint32_t pl = ent >> 18;
+            uint32_t v = 0, d = 0;
+            if (K) {
+                const uint32_t code = ent & 0x3ffffu;
+                const uint32_t bits = s_bits[code >> 5];
+                const uint32_t below = bits & ((1u << (code & 31)) - 1u);
+                v = im.lvl_start + s_rank[code >> 5] + (uint32_t)__builtin_popcount(below);
+                d = K;
+            }
+            const uint32_t vt = walk(im, a.base, T, pl, v, d);
+            if (vt != kNoneD) {
+                const uint32_t slot = atomicAdd(&s_mn, 1u);
+                if (slot < kMatchCap) s_match[slot] = make_uint2(pl, vt);
+            }
+        }
+        __syncthreads();
+
+        // ---- 4. emit this tile's matches in (pos, id) order
+        const uint32_t mn = s_mn;
+        if (mn == 0) {
+            if (tid == 0) {
+                a.unit_count[t] = 0;
+                a.unit_off[t] = 0;
+            }
+            continue;
+        }
+        if (mn <= kMatchCap) {
+            uint2 *sorted = (uint2 *)s_queue;  // the survivor queues are spent
+            for (uint32_t i = tid; i < mn; i += kWG) {
+                const uint2 e = s_match[i];
+                uint32_t rk = 0;
+                for (uint32_t q = 0; q < mn; q++) rk += s_match[q].x < e.x;
+                sorted[rk] = e;
+            }
+            __syncthreads();
+            const uint32_t per = (mn + kWG - 1) / kWG;
+            const uint32_t i0 = min(tid * per, mn), i1 = min(i0 + per, mn);
+            uint32_t mine = 0;
+            for (uint32_t i = i0; i < i1; i++) mine += pout_count(im, sorted[i].y);
+            uint32_t total;
+            const uint32_t before = block_excl_scan(mine, s_tmp, total);
+            if (tid == 0) {
+                const unsigned long long base = atomicAdd(a.stage_cursor, (unsigned long long)total);
+                a.unit_count[t] = total;
+                a.unit_off[t] = base;
+                atomicAdd(&a.blocksum[t >> kTpbShift], (unsigned long long)total);
+                s_base = base;
+            }
+            __syncthreads();
+            uint64_t dst = s_base + before;
+            for (uint32_t i = i0; i < i1; i++) {
+                const uint2 e = sorted[i];
+                emit(a, tile_lo + e.x, e.y, dst);
+                dst += pout_count(im, e.y);
+            }
+        } else {
+            // Too many matched positions to sort in LDS: walk the tile again
+            // from the root, one position per thread, in position order.
+            uint32_t mine = 0;
+            for (uint32_t r = 0; r < BPL; r++) {
+                const uint32_t pl = r * kWG + tid;
+                const uint64_t p = tile_lo + pl;
+                if (p < lo_valid || p >= hi_valid) continue;
+                const uint32_t vt = walk(im, a.base, T, pl, 0, 0);
+                if (vt != kNoneD) mine += pout_count(im, vt);
+            }
+            uint32_t total;
+            block_excl_scan(mine, s_tmp, total);
+            if (tid == 0) {
+                const unsigned long long base = atomicAdd(a.stage_cursor, (unsigned long long)total);
+                a.unit_count[t] = total;
+                a.unit_off[t] = base;
+                atomicAdd(&a.blocksum[t >> kTpbShift], (unsigned long long)total);
+                s_base = base;
+            }
+            __syncthreads();
+            uint64_t run_off = s_base;
+            for (uint32_t r = 0; r < BPL; r++) {
+                const uint32_t pl = r * kWG + tid;
+                const uint64_t p = tile_lo + pl;
+                uint32_t vt = kNoneD, c = 0;
+                if (p >= lo_valid && p < hi_valid) {
+                    vt = walk(im, a.base, T, pl, 0, 0);
+                    if (vt != kNoneD) c = pout_count(im, vt);
+                }
+                uint32_t round_total;
+                const uint32_t before = block_excl_scan(c, s_tmp, round_total);
+                if (c) emit(a, p, vt, run_off + before);
+                run_off += round_total;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- finisher
+
+__global__ __launch_bounds__(kWG) void finish_tiles(const FinishArgs f) {
+    __shared__ uint32_t s_tmp[kWG / 64];
+    __shared__ unsigned long long s_red[2][kWG / 64];
+    const uint32_t tid = threadIdx.x, b = blockIdx.x;
+    unsigned long long pre = 0, all = 0;
+    for (uint32_t i = tid; i < f.n_blocks; i += kWG) {
+        const unsigned long long s = f.blocksum[i];
+        all += s;
+        if (i < b) pre += s;
+    }
+    pre = wave_reduce_u64(pre);
+    all = wave_reduce_u64(all);
+    if ((tid & 63) == 0) {
+        s_red[0][tid >> 6] = pre;
+        s_red[1][tid >> 6] = all;
+    }
+    __syncthreads();
+    pre = 0;
+    all = 0;
+    for (uint32_t i = 0; i < kWG / 64; i++) {
+        pre += s_red[0][i];
+        all += s_red[1][i];
+    }
+    if (b == 0 && tid == 0) *f.n_matches = all;
+    const uint64_t add = f.base_dev ? *f.base_dev : 0ull;
+    constexpr uint32_t TPB = 1u << kTpbShift, PER = TPB / kWG;
+    const uint64_t t0 = ((uint64_t)b << kTpbShift) + (uint64_t)tid * PER;
+    uint32_t cnt[PER];
+    uint32_t mine = 0;
+#pragma unroll
+    for (uint32_t i = 0; i < PER; i++) {
+        const uint64_t t = t0 + i;
+        cnt[i] = t < f.n_tiles ? f.unit_count[t] : 0u;
+        mine += cnt[i];
+    }
+    uint32_t total;
+    uint64_t off = pre + add + block_excl_scan(mine, s_tmp, total);
+#pragma unroll
+    for (uint32_t i = 0; i < PER; i++) {
+        if (cnt[i]) {
+            const uint64_t src = f.unit_off[t0 + i];
+            if (src + cnt[i] <= f.stage_cap)
+                for (uint32_t k = 0; k < cnt[i]; k++)
+                    if (off + k < f.capacity) f.out[off + k] = f.stage[src + k];
+            off += cnt[i];
+        }
+    }
+}
+
+// ------------------------------------------------------------ small kernels
+
+__global__ void reset_kernel(unsigned long long *cursor, unsigned long long *blocksum,
+                             uint32_t n_blocks) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *cursor = 0;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_blocks;
+         i += gridDim.x * blockDim.x)
+        blocksum[i] = 0;
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// tile_first_text[t] = last text i whose start (in frame coordinates) is at or
+// before the first byte of tile t.
+__global__ void plan_kernel(const uint64_t *offsets, uint32_t n_texts, uint64_t shift,
+                            uint64_t n_tiles, uint32_t tile, uint32_t *tile_first_text) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += stride) {
+        const uint64_t g = t * tile;
+        uint32_t lo = 0, hi = n_texts;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (offsets[mid] + shift <= g) lo = mid; else hi = mid;
+        }
+        tile_first_text[t] = lo;
+    }
+}
+
+__global__ void copy_u64_kernel(uint64_t *dst, const unsigned long long *src) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = *src;
+}
+
+__global__ void add_u64_kernel(unsigned long long *acc, const uint64_t *x) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *acc += *x;
+}
+
+// ------------------------------------------------------------------ launchers
+
+void lds_layout(ScanArgs &a, uint32_t bpl) {
+    const uint32_t tile = kWG * bpl;
+    uint32_t off = 0;
+    auto take = [&](uint32_t bytes) {
+        const uint32_t o = off;
+        off += (bytes + 15u) & ~15u;
+        return o;
+    };
+    a.off_bits = take(4 * a.im.lvl_words);
+    a.off_rank = take(4 * a.im.lvl_words);
+    a.off_sym = take(a.im.identity ? 0 : 256);
+    a.off_text = take(tile + a.halo + 16);
+    a.off_bnd = take(4 * ((tile + a.halo) / 32 + 2));
+    a.off_queue = take(4 * tile);
+    a.off_match = take(8 * kMatchCap);
+    a.lds_total = off;
+}
+
+template <int BPL, bool IDENT>
+static hipError_t launch_scan_t(const ScanArgs &a, uint32_t grid, hipStream_t s) {
+    hipLaunchKernelGGL((scan_tiles<BPL, IDENT>), dim3(grid), dim3(kWG), a.lds_total, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan(const ScanArgs &a, uint32_t bpl, uint32_t grid, hipStream_t s) {
+    const bool id = a.im.identity != 0;
+    switch (bpl) {
+        case 4: return id ? launch_scan_t<4, true>(a, grid, s) : launch_scan_t<4, false>(a, grid, s);
+        case 8: return id ? launch_scan_t<8, true>(a, grid, s) : launch_scan_t<8, false>(a, grid, s);
+        case 16: return id ? launch_scan_t<16, true>(a, grid, s) : launch_scan_t<16, false>(a, grid, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+template <int BPL, bool IDENT>
+static const void *scan_fn() {
+    return (const void *)scan_tiles<BPL, IDENT>;
+}
+
+static const void *scan_fn_for(uint32_t bpl, bool id) {
+    switch (bpl) {
+        case 4: return id ? scan_fn<4, true>() : scan_fn<4, false>();
+        case 8: return id ? scan_fn<8, true>() : scan_fn<8, false>();
+        case 16: return id ? scan_fn<16, true>() : scan_fn<16, false>();
+        default: return nullptr;
+    }
+}
+
+hipError_t prepare_kernels(uint32_t bpl, uint32_t lds_bytes) {
+    for (int id = 0; id < 2; id++) {
+        const void *fn = scan_fn_for(bpl, id != 0);
+        if (!fn) return hipErrorInvalidValue;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int max_wg_per_cu(uint32_t bpl, uint32_t lds_bytes) {
+    int n = 0;
+    const void *fn = scan_fn_for(bpl, true);
+    if (!fn) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kWG, lds_bytes) != hipSuccess || n < 1)
+        n = 1;
+    return n;
+}
+
+hipError_t launch_finish(const FinishArgs &f, hipStream_t s) {
+    hipLaunchKernelGGL(finish_tiles, dim3(f.n_blocks), dim3(kWG), 0, s, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_reset(unsigned long long *cursor, unsigned long long *blocksum,
+                        uint32_t n_blocks, hipStream_t s) {
+    const uint32_t grid = (n_blocks + 255) / 256 + 1;
+    hipLaunchKernelGGL(reset_kernel, dim3(grid), dim3(256), 0, s, cursor, blocksum, n_blocks);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    uint64_t g = (n + 255) / 256;
+    const uint32_t grid = (uint32_t)(g < 65536 ? g : 65536);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan(const uint64_t *offsets, uint32_t n_texts, uint64_t shift,
+                       uint64_t n_tiles, uint32_t tile, uint32_t *tile_first_text,
+                       hipStream_t s) {
+    if (n_tiles == 0) return hipSuccess;
+    uint64_t g = (n_tiles + 255) / 256;
+    const uint32_t grid = (uint32_t)(g < 65536 ? g : 65536);
+    hipLaunchKernelGGL(plan_kernel, dim3(grid), dim3(256), 0, s, offsets, n_texts, shift,
+                       n_tiles, tile, tile_first_text);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_u64(uint64_t *dst, const unsigned long long *src, hipStream_t s) {
+    hipLaunchKernelGGL(copy_u64_kernel, dim3(1), dim3(64), 0, s, dst, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_running(unsigned long long *running, const uint64_t *n, hipStream_t s) {
+    hipLaunchKernelGGL(add_u64_kernel, dim3(1), dim3(64), 0, s, running, n);
+    return hipGetLastError();
+}
+
+}  // namespace pfac

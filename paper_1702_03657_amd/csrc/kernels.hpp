@@ -1,0 +1,85 @@
+// Device-side structures and launchers of the scan kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "../../include/pfac.h"
+
+namespace pfac {
+
+constexpr uint32_t kWG = 256;            // threads per workgroup (4 waves of 64)
+constexpr uint32_t kMatchCap = 256;      // matched positions a tile sorts in LDS
+constexpr uint32_t kTpbShift = 10;       // tiles per block-sum entry = 1024
+constexpr uint32_t kHaloCap = 1024;      // most halo bytes staged in LDS
+
+// Device image as the kernels see it (pointers into one device allocation).
+struct ImageView {
+    const uint4 *node;        // per node: labels4, first child, nc | term flag, terminal ordinal
+    const uint8_t *label;     // per edge
+    const uint32_t *pout_ptr; // per terminal ordinal + 1
+    const uint32_t *pout_ids;
+    const uint32_t *lvl;      // 2 per word: bits, rank before
+    const uint8_t *sym;       // 256
+    uint32_t K, b, identity, lvl_words;
+    uint32_t lvl_start, max_len, n_nodes, pad;
+};
+
+struct ScanArgs {
+    ImageView im;
+    const uint8_t *base;              // text frame: 16-byte aligned address
+    uint64_t shift;                   // frame position of the first text byte (0..15)
+    uint64_t total;                   // bytes of all texts
+    const uint64_t *offsets;          // n_texts + 1 text starts, or NULL for one text
+    const uint32_t *tile_first_text;  // per tile: text holding its first byte (batch only)
+    uint64_t n_tiles;
+    uint32_t n_texts;
+    uint32_t text_id0;                // added to every reported text id
+    uint32_t halo;                    // bytes staged past each tile (multiple of 16)
+    uint32_t pad0;
+    // dynamic LDS layout (byte offsets)
+    uint32_t off_bits, off_rank, off_sym, off_text, off_bnd, off_queue, off_match, lds_total;
+    // outputs
+    pfac_match *stage;
+    uint64_t stage_cap;
+    unsigned long long *stage_cursor;
+    uint32_t *unit_count;             // per tile
+    unsigned long long *unit_off;     // per tile
+    unsigned long long *blocksum;     // per 1 << kTpbShift tiles
+    uint32_t *counts;                 // optional per-position counts
+};
+
+struct FinishArgs {
+    const uint32_t *unit_count;
+    const unsigned long long *unit_off;
+    const unsigned long long *blocksum;
+    const pfac_match *stage;
+    uint64_t stage_cap;
+    uint64_t n_tiles;
+    uint32_t n_blocks;
+    pfac_match *out;
+    uint64_t capacity;
+    uint64_t *n_matches;              // receives this launch's match count
+    const unsigned long long *base_dev;  // optional device value added to every output index
+};
+
+// LDS bytes and section offsets for a tile of `bpl` bytes per lane.
+void lds_layout(ScanArgs &a, uint32_t bpl);
+
+hipError_t launch_reset(unsigned long long *stage_cursor, unsigned long long *blocksum,
+                        uint32_t n_blocks, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_plan(const uint64_t *offsets, uint32_t n_texts, uint64_t shift,
+                       uint64_t n_tiles, uint32_t tile, uint32_t *tile_first_text,
+                       hipStream_t s);
+hipError_t launch_scan(const ScanArgs &a, uint32_t bpl, uint32_t grid, hipStream_t s);
+hipError_t launch_finish(const FinishArgs &f, hipStream_t s);
+hipError_t launch_add_running(unsigned long long *running, const uint64_t *n, hipStream_t s);
+hipError_t launch_copy_u64(uint64_t *dst, const unsigned long long *src, hipStream_t s);
+
+// Largest resident workgroups per CU for this layout.
+int max_wg_per_cu(uint32_t bpl, uint32_t lds_bytes);
+hipError_t prepare_kernels(uint32_t bpl, uint32_t lds_bytes);
+
+}  // namespace pfac

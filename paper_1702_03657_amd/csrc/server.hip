@@ -1,0 +1,437 @@
+// Continuous-batching scan server over one resident trie.
+//
+// Requests are admitted in arrival order into a byte ring in caller-provided
+// device memory while the budget (text bytes in flight) allows.  Their
+// host-to-device copies run on a copy stream; every request whose copy has
+// landed and that is contiguous in the ring joins the next batched scan on
+// the compute stream.  Two batch slots alternate, so a batch is launched
+// while the previous one still runs and new requests keep arriving and
+// copying in the meantime.  When a batch completes its matches are copied
+// back, split per request by text id, and the ring space and budget of its
+// requests are released.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "../../include/pfac.h"
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+enum class St { Queued, Copying, Ready, Scanning, Done };
+
+struct Req {
+    uint64_t id = 0;
+    const uint8_t *host = nullptr;
+    uint64_t n = 0;
+    clk::time_point t_submit, t_done;
+    St st = St::Queued;
+    uint64_t ring_off = 0;    // start of the text in the ring
+    uint64_t ring_len = 0;    // bytes taken in the ring (text + wrap padding)
+    bool wraps = false;       // placed at 0, holding the unused end of the ring
+    hipEvent_t copied = nullptr;
+    std::vector<pfac_match> res;
+    uint64_t n_matches = 0;
+    int rc = PFAC_OK;
+};
+
+struct Slot {
+    uint64_t *offsets_dev = nullptr;   // max_batch + 1
+    pfac_match *out_dev = nullptr;
+    uint64_t out_cap = 0;
+    uint64_t *count_dev = nullptr;
+    uint64_t *offsets_host = nullptr;  // pinned
+    pfac_match *out_host = nullptr;    // pinned
+    uint64_t *count_host = nullptr;    // pinned
+    pfac_workspace *ws = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<Req *> reqs;
+};
+
+}  // namespace
+
+struct pfac_server {
+    const pfac_trie *t = nullptr;
+    uint8_t *ring = nullptr;
+    uint64_t ring_bytes = 0;
+    uint64_t budget = 0;
+    uint32_t max_batch = 1;
+    hipStream_t cs = nullptr, xs = nullptr;
+    int device = 0;
+    Slot slot[2];
+
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    bool stop = false;
+    uint64_t next_id = 1;
+    std::deque<Req *> queue;     // submitted, not admitted (arrival order)
+    std::deque<Req *> in_ring;   // admitted, ring order
+    std::map<uint64_t, Req *> by_id;
+    uint64_t head = 0, tail = 0, used = 0;  // ring state (bytes)
+    uint64_t stat_req = 0, stat_batches = 0, stat_bytes = 0;
+    std::thread worker;
+
+    // Ring of text bytes.  Occupied bytes are [head, tail) when not wrapped,
+    // else [head, ring_bytes) + [0, tail).  A request that does not fit
+    // before the end of the ring starts at 0 and also holds the unused end
+    // bytes until it is released.
+    bool wrapped = false;
+
+    bool ring_take(uint64_t n, uint64_t &off, uint64_t &pad) {
+        if (n > ring_bytes) return false;
+        if (!wrapped) {
+            if (ring_bytes - tail >= n) {
+                off = tail;
+                pad = 0;
+            } else if (head >= n) {
+                off = 0;
+                pad = ring_bytes - tail;
+            } else {
+                return false;
+            }
+        } else {
+            if (head - tail < n) return false;
+            off = tail;
+            pad = 0;
+        }
+        return used + n + pad <= budget;
+    }
+
+    void admit_locked() {
+        while (!queue.empty()) {
+            Req *r = queue.front();
+            uint64_t off = 0, pad = 0;
+            if (!ring_take(r->n, off, pad)) break;
+            queue.pop_front();
+            r->wraps = !wrapped && off == 0 && !in_ring.empty();
+            if (r->wraps) wrapped = true;
+            r->ring_off = off;
+            r->ring_len = r->n + pad;
+            tail = off + r->n;
+            used += r->ring_len;
+            in_ring.push_back(r);
+            r->st = St::Copying;
+            (void)hipMemcpyAsync(ring + off, r->host, r->n, hipMemcpyHostToDevice, xs);
+            (void)hipEventRecord(r->copied, xs);
+        }
+    }
+
+    void release_locked() {
+        while (!in_ring.empty() && in_ring.front()->st == St::Done) {
+            Req *r = in_ring.front();
+            in_ring.pop_front();
+            used -= r->ring_len;
+            if (r->wraps) wrapped = false;
+            head = r->ring_off + r->n;
+            if (in_ring.empty()) {
+                head = tail = used = 0;
+                wrapped = false;
+            }
+        }
+    }
+
+    // Ready requests contiguous in the ring, in ring order, up to max_batch.
+    void form_batch_locked(std::vector<Req *> &b) {
+        b.clear();
+        for (Req *r : in_ring) {
+            if (r->st == St::Copying && hipEventQuery(r->copied) == hipSuccess) r->st = St::Ready;
+            if (r->st == St::Scanning || r->st == St::Done) {
+                if (b.empty()) continue;
+                break;
+            }
+            if (r->st != St::Ready) break;
+            if (!b.empty()) {
+                const Req *p = b.back();
+                if (p->ring_off + p->n != r->ring_off) break;  // ring wrapped
+            }
+            b.push_back(r);
+            if (b.size() >= max_batch) break;
+        }
+    }
+
+    int launch(Slot &S, std::vector<Req *> &b) {
+        const uint64_t base = b.front()->ring_off;
+        S.offsets_host[0] = 0;
+        for (size_t i = 0; i < b.size(); i++)
+            S.offsets_host[i + 1] = S.offsets_host[i] + b[i]->n;
+        const uint64_t total = S.offsets_host[b.size()];
+        hipError_t e = hipMemcpyAsync(S.offsets_dev, S.offsets_host, 8 * (b.size() + 1),
+                                      hipMemcpyHostToDevice, cs);
+        if (e != hipSuccess) return PFAC_EDEVICE;
+        int rc = pfac_scan_batch(t, S.ws, ring + base, S.offsets_dev, (uint32_t)b.size(), total,
+                                 S.out_dev, S.out_cap, S.count_dev, cs);
+        if (rc != PFAC_OK) return rc;
+        if (hipMemcpyAsync(S.count_host, S.count_dev, 8, hipMemcpyDeviceToHost, cs) != hipSuccess)
+            return PFAC_EDEVICE;
+        if (hipEventRecord(S.done, cs) != hipSuccess) return PFAC_EDEVICE;
+        S.reqs = b;
+        S.busy = true;
+        for (Req *r : b) r->st = St::Scanning;
+        stat_batches++;
+        stat_bytes += total;
+        return PFAC_OK;
+    }
+
+    // A request of a batch whose matches overflowed the slot: scan it alone.
+    void rescan_alone(Req *r, pfac_workspace *ws) {
+        uint64_t n = 0;
+        r->rc = pfac_scan_sync(t, ws, ring + r->ring_off, r->n, nullptr, 0, &n, nullptr, cs);
+        if (r->rc != PFAC_OK && r->rc != PFAC_ETRUNC) return;
+        r->rc = PFAC_OK;
+        r->res.resize(n);
+        if (n == 0) return;
+        pfac_match *d = nullptr;
+        if (hipMalloc(&d, n * sizeof(pfac_match)) != hipSuccess) {
+            r->rc = PFAC_ENOMEM;
+            return;
+        }
+        uint64_t n2 = 0;
+        r->rc = pfac_scan_sync(t, ws, ring + r->ring_off, r->n, d, n, &n2, nullptr, cs);
+        if (r->rc == PFAC_OK &&
+            hipMemcpy(r->res.data(), d, n * sizeof(pfac_match), hipMemcpyDeviceToHost) != hipSuccess)
+            r->rc = PFAC_EDEVICE;
+        (void)hipFree(d);
+        r->n_matches = n;
+    }
+
+    void complete(Slot &S) {
+        const uint64_t cnt = *S.count_host;
+        std::vector<uint64_t> start(S.reqs.size() + 1, 0);
+        if (cnt <= S.out_cap) {
+            if (cnt)
+                (void)hipMemcpy(S.out_host, S.out_dev, cnt * sizeof(pfac_match),
+                                hipMemcpyDeviceToHost);
+            // records are sorted by text id: split by a linear sweep
+            uint64_t k = 0;
+            for (size_t i = 0; i < S.reqs.size(); i++) {
+                Req *r = S.reqs[i];
+                uint64_t a = k;
+                while (k < cnt && S.out_host[k].text_id == i) k++;
+                r->res.assign(S.out_host + a, S.out_host + k);
+                for (auto &m : r->res) m.text_id = 0;
+                r->n_matches = k - a;
+                r->rc = PFAC_OK;
+            }
+        } else {
+            for (Req *r : S.reqs) rescan_alone(r, S.ws);
+        }
+        const auto now = clk::now();
+        std::lock_guard<std::mutex> lock(mu);
+        for (Req *r : S.reqs) {
+            r->t_done = now;
+            r->st = St::Done;
+            stat_req++;
+        }
+        S.reqs.clear();
+        S.busy = false;
+        release_locked();
+        cv_done.notify_all();
+    }
+
+    void run() {
+        (void)hipSetDevice(device);
+        std::vector<Req *> b;
+        int turn = 0;
+        for (;;) {
+            bool did = false;
+            for (int q = 0; q < 2; q++) {
+                Slot &S = slot[(turn + q) & 1];
+                if (S.busy && hipEventQuery(S.done) == hipSuccess) {
+                    complete(S);
+                    did = true;
+                }
+            }
+            {
+                std::unique_lock<std::mutex> lock(mu);
+                admit_locked();
+                Slot &S = slot[turn & 1];
+                if (!S.busy) {
+                    form_batch_locked(b);
+                    if (!b.empty()) {
+                        int rc = launch(S, b);
+                        if (rc != PFAC_OK) {
+                            for (Req *r : b) {
+                                r->rc = rc;
+                                r->st = St::Done;
+                                r->t_done = clk::now();
+                            }
+                            release_locked();
+                            cv_done.notify_all();
+                        } else {
+                            turn++;
+                        }
+                        did = true;
+                    }
+                }
+                if (stop && queue.empty() && in_ring.empty() && !slot[0].busy && !slot[1].busy)
+                    break;
+                if (!did) cv_work.wait_for(lock, std::chrono::microseconds(50));
+            }
+        }
+    }
+};
+
+extern "C" int pfac_server_create(const pfac_trie *t, void *arena_dev, uint64_t arena_bytes,
+                                  uint64_t budget_bytes, uint32_t max_batch, void *compute_stream,
+                                  void *copy_stream, pfac_server **out) {
+    if (!out) return PFAC_EINVAL;
+    *out = nullptr;
+    if (!t || !arena_dev || max_batch == 0 || budget_bytes == 0 || budget_bytes > arena_bytes)
+        return PFAC_EINVAL;
+    pfac_stats st;
+    if (pfac_trie_stats(t, &st) != PFAC_OK || st.bytes_device == 0) return PFAC_ENODEV;
+    pfac_server *s = new (std::nothrow) pfac_server();
+    if (!s) return PFAC_ENOMEM;
+    s->t = t;
+    s->max_batch = max_batch;
+    s->cs = (hipStream_t)compute_stream;
+    s->xs = (hipStream_t)copy_stream;
+    (void)hipGetDevice(&s->device);
+    // arena: [ text ring (budget) | slot 0 | slot 1 ]
+    uint8_t *a = (uint8_t *)arena_dev;
+    const uint64_t rest = arena_bytes - budget_bytes;
+    const uint64_t per_slot = rest / 2;
+    const uint64_t off_bytes = ((8ull * (max_batch + 1)) + 255) & ~255ull;
+    if (per_slot < off_bytes + 256 + 64 * sizeof(pfac_match)) {
+        delete s;
+        return PFAC_EINVAL;
+    }
+    s->ring = a;
+    s->ring_bytes = budget_bytes;
+    s->budget = budget_bytes;
+    int rc = PFAC_OK;
+    for (int q = 0; q < 2 && rc == PFAC_OK; q++) {
+        Slot &S = s->slot[q];
+        uint8_t *p = a + budget_bytes + q * per_slot;
+        p = (uint8_t *)(((uintptr_t)p + 255) & ~(uintptr_t)255);
+        S.offsets_dev = (uint64_t *)p;
+        S.count_dev = (uint64_t *)(p + off_bytes);
+        S.out_dev = (pfac_match *)(p + off_bytes + 256);
+        S.out_cap = (per_slot - off_bytes - 512) / sizeof(pfac_match);
+        if (hipHostMalloc((void **)&S.offsets_host, 8 * (max_batch + 1)) != hipSuccess ||
+            hipHostMalloc((void **)&S.out_host, S.out_cap * sizeof(pfac_match)) != hipSuccess ||
+            hipHostMalloc((void **)&S.count_host, 8) != hipSuccess ||
+            hipEventCreateWithFlags(&S.done, hipEventDisableTiming) != hipSuccess)
+            rc = PFAC_ENOMEM;
+        if (rc == PFAC_OK) rc = pfac_workspace_create(&S.ws);
+        if (rc == PFAC_OK) rc = pfac_workspace_reserve(S.ws, budget_bytes, max_batch, S.out_cap);
+    }
+    if (rc != PFAC_OK) {
+        for (auto &S : s->slot) {
+            if (S.offsets_host) (void)hipHostFree(S.offsets_host);
+            if (S.out_host) (void)hipHostFree(S.out_host);
+            if (S.count_host) (void)hipHostFree(S.count_host);
+            if (S.done) (void)hipEventDestroy(S.done);
+            pfac_workspace_free(S.ws);
+        }
+        delete s;
+        return rc;
+    }
+    s->worker = std::thread([s] { s->run(); });
+    *out = s;
+    return PFAC_OK;
+}
+
+extern "C" int pfac_server_submit(pfac_server *s, const uint8_t *text_host, uint64_t n,
+                                  uint64_t *request_id) {
+    if (!s || !request_id || (n && !text_host)) return PFAC_EINVAL;
+    if (n > s->ring_bytes) return PFAC_EINVAL;
+    Req *r = new (std::nothrow) Req();
+    if (!r) return PFAC_ENOMEM;
+    r->host = text_host;
+    r->n = n;
+    r->t_submit = clk::now();
+    if (n && hipEventCreateWithFlags(&r->copied, hipEventDisableTiming) != hipSuccess) {
+        delete r;
+        return PFAC_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(s->mu);
+    if (s->stop) {
+        if (r->copied) (void)hipEventDestroy(r->copied);
+        delete r;
+        return PFAC_EINVAL;
+    }
+    r->id = s->next_id++;
+    s->by_id[r->id] = r;
+    if (n == 0) {
+        r->st = St::Done;
+        r->t_done = r->t_submit;
+        s->stat_req++;
+    } else {
+        s->queue.push_back(r);
+        s->cv_work.notify_one();
+    }
+    *request_id = r->id;
+    return PFAC_OK;
+}
+
+extern "C" int pfac_server_wait(pfac_server *s, uint64_t request_id, int64_t timeout_ms,
+                                pfac_match *out_host, uint64_t capacity, uint64_t *n_matches,
+                                double *latency_s) {
+    if (!s || !n_matches) return PFAC_EINVAL;
+    std::unique_lock<std::mutex> lock(s->mu);
+    auto it = s->by_id.find(request_id);
+    if (it == s->by_id.end()) return PFAC_EINVAL;
+    Req *r = it->second;
+    auto done = [&] { return r->st == St::Done; };
+    if (timeout_ms < 0) {
+        s->cv_done.wait(lock, done);
+    } else if (!s->cv_done.wait_for(lock, std::chrono::milliseconds(timeout_ms), done)) {
+        return PFAC_EBUSY;
+    }
+    s->by_id.erase(it);
+    lock.unlock();
+    int rc = r->rc;
+    *n_matches = r->n_matches;
+    if (rc == PFAC_OK && out_host)
+        std::memcpy(out_host, r->res.data(), std::min(capacity, r->n_matches) * sizeof(pfac_match));
+    if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
+    if (rc == PFAC_OK && r->n_matches > capacity) rc = PFAC_ETRUNC;
+    if (r->copied) (void)hipEventDestroy(r->copied);
+    delete r;
+    return rc;
+}
+
+extern "C" int pfac_server_stats(const pfac_server *s, uint64_t *requests, uint64_t *batches,
+                                 uint64_t *bytes) {
+    if (!s) return PFAC_EINVAL;
+    pfac_server *m = const_cast<pfac_server *>(s);
+    std::lock_guard<std::mutex> lock(m->mu);
+    if (requests) *requests = s->stat_req;
+    if (batches) *batches = s->stat_batches;
+    if (bytes) *bytes = s->stat_bytes;
+    return PFAC_OK;
+}
+
+extern "C" void pfac_server_free(pfac_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lock(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    for (auto &S : s->slot) {
+        if (S.offsets_host) (void)hipHostFree(S.offsets_host);
+        if (S.out_host) (void)hipHostFree(S.out_host);
+        if (S.count_host) (void)hipHostFree(S.count_host);
+        if (S.done) (void)hipEventDestroy(S.done);
+        pfac_workspace_free(S.ws);
+    }
+    for (auto &kv : s->by_id) {
+        if (kv.second->copied) (void)hipEventDestroy(kv.second->copied);
+        delete kv.second;
+    }
+    delete s;
+}

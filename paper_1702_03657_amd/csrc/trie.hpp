@@ -1,0 +1,72 @@
+// Host-side trie structures: the CRS trie and the device image derived from it.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace pfac {
+
+constexpr uint32_t kNone = 0xffffffffu;
+constexpr uint32_t kTermFlag = 1u << 16;   // node record .z: terminal node
+constexpr uint32_t kNcMask = 0xffffu;      // node record .z: number of children
+
+// The CRS trie of Design and Implementation.  Nodes are numbered breadth first
+// (step I), level by level, with children by ascending unsigned label, so the
+// row-major array of step II is simply node order and edge e leads to node e+1.
+struct CrsTrie {
+    uint32_t k = 0;                    // number of patterns
+    std::vector<uint8_t> pat_data;     // patterns back to back (copied in)
+    std::vector<uint64_t> pat_off;     // k + 1
+    uint64_t min_len = 0, max_len = 0;
+
+    std::vector<uint32_t> row_ptr;     // N + 1: edges of node v = [row_ptr[v], row_ptr[v+1])
+    std::vector<uint8_t> labels;       // N - 1: label of edge e (= of node e + 1)
+    std::vector<uint32_t> term_ptr;    // N + 1
+    std::vector<uint32_t> term_ids;    // k, ascending within a node
+    std::vector<uint32_t> level_start; // depth d nodes: [level_start[d], level_start[d+1])
+    std::vector<uint32_t> rep;         // N: one pattern id whose prefix is node v (root: kNone)
+
+    uint32_t n_nodes() const { return (uint32_t)(row_ptr.size() - 1); }
+    uint32_t n_edges() const { return (uint32_t)labels.size(); }
+};
+
+// Builds the trie level by level from the lexicographically sorted patterns
+// (step I).  Returns false on an empty pattern.
+bool build_crs(const uint8_t *data, const uint64_t *off, uint32_t k, CrsTrie &out,
+               std::string &err);
+
+// Everything the scan kernel reads, laid out for the device.
+struct DeviceImageHost {
+    // Per node, 16 bytes: x = labels of the first four children (byte j =
+    // label j), y = first child node id (children are y .. y+nc-1),
+    // z = nc | kTermFlag, w = terminal ordinal or kNone.
+    std::vector<uint32_t> node;        // 4 * N
+    std::vector<uint8_t> label;        // N - 1 (a copy of the CRS labels, padded)
+    // For each terminal node t (in breadth-first order) the ascending ids of
+    // every pattern that ends on its root path: pout_ids[pout_ptr[t] ..
+    // pout_ptr[t+1]).  A walk reports the list of the deepest terminal node it
+    // passed, which is the union of the term lists of all terminal nodes on
+    // the way, already sorted.
+    std::vector<uint32_t> pout_ptr;    // T + 1
+    std::vector<uint32_t> pout_ids;
+    // Level index: the depth-K nodes as a bitmap over K-symbol codes, with
+    // the number of set bits before each 32-bit word.  Breadth-first order
+    // with ascending labels is ascending code order within a level, so the
+    // rank of a code is the node's offset in its level.
+    uint32_t K = 0;                    // index depth (0 = no index)
+    uint32_t b = 8;                    // bits per symbol
+    uint32_t identity = 1;             // 1: symbol = byte (b = 8)
+    uint32_t lvl_words = 0;            // 32-bit words of the bitmap
+    uint32_t lvl_start = 0;            // first node id of depth K
+    std::vector<uint32_t> lvl;         // 2 * lvl_words: {bits, rank before}
+    std::vector<uint8_t> sym;          // 256: symbol code, 0xff = byte unused
+    uint32_t alphabet = 0;
+    uint32_t n_term = 0;
+};
+
+// Derives the device image from the CRS trie for a level index of at most
+// `index_bits` bits.
+void pack_image(const CrsTrie &t, uint32_t index_bits, DeviceImageHost &img);
+
+}  // namespace pfac

@@ -1,0 +1,194 @@
+// Host-side CRS trie builder and device-image packer.
+//
+// Design and Implementation builds the trie breadth first, level by level
+// (step I), keeps it as a row-major ordered array (step II), views it as a
+// node x symbol sparse matrix (step VI) and compresses that matrix with
+// compressed row storage: row_ptr per node, the symbol (edge label) as the
+// column index and the child node as the value.  Steps III-V (truncation and
+// suffix / end-node merging) are not applied: they lose pattern identities,
+// and every (position, pattern id) match must be reported.
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "trie.hpp"
+
+namespace pfac {
+
+bool build_crs(const uint8_t *data, const uint64_t *off, uint32_t k, CrsTrie &T,
+               std::string &err) {
+    T = CrsTrie{};
+    T.k = k;
+    T.pat_off.assign(k + 1, 0);
+    uint64_t base = k ? off[0] : 0;
+    for (uint32_t j = 0; j < k; j++) {
+        if (off[j + 1] < off[j]) { err = "pattern offsets decrease"; return false; }
+        if (off[j + 1] == off[j]) { err = "empty pattern"; return false; }
+        T.pat_off[j + 1] = off[j + 1] - base;
+    }
+    uint64_t total = T.pat_off[k];
+    T.pat_data.assign(data ? data + base : nullptr, data ? data + base + total : nullptr);
+    T.min_len = k ? UINT64_MAX : 0;
+    for (uint32_t j = 0; j < k; j++) {
+        uint64_t L = T.pat_off[j + 1] - T.pat_off[j];
+        T.min_len = std::min(T.min_len, L);
+        T.max_len = std::max(T.max_len, L);
+    }
+    const uint8_t *P = T.pat_data.data();
+    auto len = [&](uint32_t j) { return T.pat_off[j + 1] - T.pat_off[j]; };
+    auto at = [&](uint32_t j, uint64_t d) { return P[T.pat_off[j] + d]; };
+
+    // Lexicographic order (unsigned bytes); a proper prefix sorts before its
+    // extensions; equal patterns by id.  Every trie node is then a contiguous
+    // run of this order, and its children are consecutive sub-runs.
+    std::vector<uint32_t> ord(k);
+    std::iota(ord.begin(), ord.end(), 0u);
+    std::sort(ord.begin(), ord.end(), [&](uint32_t a, uint32_t b) {
+        uint64_t la = len(a), lb = len(b);
+        int c = std::memcmp(P + T.pat_off[a], P + T.pat_off[b], std::min(la, lb));
+        if (c != 0) return c < 0;
+        if (la != lb) return la < lb;
+        return a < b;
+    });
+
+    struct Run { uint32_t a, b; };
+    std::vector<Run> cur{{0, k}}, nxt;
+    T.row_ptr.push_back(0);
+    T.term_ptr.push_back(0);
+    T.level_start.push_back(0);
+    T.rep.push_back(kNone);
+    uint64_t depth = 0;
+    while (!cur.empty()) {
+        nxt.clear();
+        for (const Run &r : cur) {
+            uint32_t a = r.a;
+            // patterns that end here come first in the run
+            while (a < r.b && len(ord[a]) == depth) T.term_ids.push_back(ord[a++]);
+            T.term_ptr.push_back((uint32_t)T.term_ids.size());
+            while (a < r.b) {
+                uint8_t c = at(ord[a], depth);
+                uint32_t e = a + 1;
+                while (e < r.b && at(ord[e], depth) == c) e++;
+                T.labels.push_back(c);
+                T.rep.push_back(ord[a]);
+                nxt.push_back({a, e});
+                a = e;
+            }
+            T.row_ptr.push_back((uint32_t)T.labels.size());
+        }
+        T.level_start.push_back(T.level_start.back() + (uint32_t)cur.size());
+        cur.swap(nxt);
+        depth++;
+    }
+    return true;
+}
+
+static uint32_t ceil_log2(uint32_t x) {
+    uint32_t b = 0;
+    while ((1u << b) < x) b++;
+    return b;
+}
+
+void pack_image(const CrsTrie &T, uint32_t index_bits, DeviceImageHost &I) {
+    I = DeviceImageHost{};
+    const uint32_t N = T.n_nodes();
+    const uint32_t E = T.n_edges();
+
+    // node records and terminal ordinals
+    I.node.assign(4ull * N, 0);
+    std::vector<uint32_t> ord_of(N, kNone);
+    for (uint32_t v = 0; v < N; v++)
+        if (T.term_ptr[v + 1] > T.term_ptr[v]) ord_of[v] = I.n_term++;
+    for (uint32_t v = 0; v < N; v++) {
+        uint32_t e0 = T.row_ptr[v], nc = T.row_ptr[v + 1] - e0;
+        uint32_t x = 0;
+        for (uint32_t j = 0; j < 4; j++) {
+            // unused bytes repeat the last label; the kernel ignores j >= nc
+            uint32_t lab = nc ? T.labels[e0 + std::min(j, nc - 1)] : 0;
+            x |= lab << (8 * j);
+        }
+        I.node[4 * v + 0] = x;
+        I.node[4 * v + 1] = e0 + 1;
+        I.node[4 * v + 2] = nc | (ord_of[v] != kNone ? kTermFlag : 0);
+        I.node[4 * v + 3] = ord_of[v];
+    }
+    I.label = T.labels;
+    if (I.label.empty()) I.label.push_back(0);
+
+    // root-path pattern lists of terminal nodes
+    std::vector<uint32_t> parent(N, kNone), near_term(N, kNone);
+    for (uint32_t v = 0; v < N; v++)
+        for (uint32_t e = T.row_ptr[v]; e < T.row_ptr[v + 1]; e++) parent[e + 1] = v;
+    I.pout_ptr.assign(I.n_term + 1, 0);
+    std::vector<uint32_t> tmp;
+    for (uint32_t v = 1; v < N; v++) {
+        uint32_t up = near_term[parent[v]];
+        if (ord_of[v] == kNone) { near_term[v] = up; continue; }
+        near_term[v] = v;
+        tmp.clear();
+        const uint32_t *own = T.term_ids.data() + T.term_ptr[v];
+        uint32_t n_own = T.term_ptr[v + 1] - T.term_ptr[v];
+        if (up != kNone) {
+            uint32_t o = ord_of[up];
+            const uint32_t *anc = I.pout_ids.data() + I.pout_ptr[o];
+            uint32_t n_anc = I.pout_ptr[o + 1] - I.pout_ptr[o];
+            tmp.resize(n_own + n_anc);
+            std::merge(own, own + n_own, anc, anc + n_anc, tmp.begin());
+        } else {
+            tmp.assign(own, own + n_own);
+        }
+        I.pout_ids.insert(I.pout_ids.end(), tmp.begin(), tmp.end());
+        I.pout_ptr[ord_of[v] + 1] = (uint32_t)I.pout_ids.size();
+    }
+    if (I.pout_ids.empty()) I.pout_ids.push_back(0);
+
+    // alphabet and level index
+    bool used[256] = {false};
+    for (uint32_t e = 0; e < E; e++) used[T.labels[e]] = true;
+    for (int c = 0; c < 256; c++) I.alphabet += used[c];
+    index_bits = std::max(1u, std::min(index_bits, 18u));
+    uint32_t b_comp = std::max(1u, ceil_log2(std::max(I.alphabet, 1u)));
+    uint32_t depth = (uint32_t)T.max_len;
+    uint32_t k_cap = T.k ? (uint32_t)std::min<uint64_t>(T.min_len - 1, depth) : 0;
+    k_cap = std::min(k_cap, 16u);
+    uint32_t K8 = std::min(index_bits / 8, k_cap);
+    uint32_t Kc = std::min(index_bits / b_comp, k_cap);
+    I.sym.assign(256, 0xff);
+    if (Kc > K8 && b_comp < 8) {
+        I.identity = 0;
+        I.b = b_comp;
+        I.K = Kc;
+        uint32_t s = 0;
+        for (int c = 0; c < 256; c++)
+            if (used[c]) I.sym[c] = (uint8_t)s++;
+    } else {
+        I.identity = 1;
+        I.b = 8;
+        I.K = K8;
+        for (int c = 0; c < 256; c++) I.sym[c] = (uint8_t)c;
+    }
+    if (I.K == 0) {
+        I.lvl_words = 0;
+        I.lvl_start = 0;
+        return;
+    }
+    uint32_t code_bits = I.b * I.K;
+    uint64_t n_codes = 1ull << code_bits;
+    I.lvl_words = (uint32_t)std::max<uint64_t>(1, n_codes / 32);
+    I.lvl.assign(2ull * I.lvl_words, 0);
+    I.lvl_start = T.level_start[I.K];
+    const uint32_t v0 = T.level_start[I.K], v1 = T.level_start[I.K + 1];
+    for (uint32_t v = v0; v < v1; v++) {
+        const uint8_t *p = T.pat_data.data() + T.pat_off[T.rep[v]];
+        uint32_t code = 0;
+        for (uint32_t d = 0; d < I.K; d++) code = (code << I.b) | I.sym[p[d]];
+        I.lvl[2 * (code >> 5)] |= 1u << (code & 31);
+    }
+    uint32_t run = 0;
+    for (uint32_t w = 0; w < I.lvl_words; w++) {
+        I.lvl[2 * w + 1] = run;
+        run += (uint32_t)__builtin_popcount(I.lvl[2 * w]);
+    }
+}
+
+}  // namespace pfac

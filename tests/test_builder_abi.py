@@ -1,0 +1,127 @@
+"""CPU tests of the host side of the library: the CRS builder (against the
+oracle's trie definition), footprint arithmetic, C-ABI argument checks and
+that every symbol of include/pfac.h is exported.  No GPU call is made."""
+
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1702_03657_amd as pf
+from synth import workloads
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfac.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pf._pfac.LIB_PATH):
+        from paper_1702_03657_amd import build
+        build.build()
+    return pf.load()
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(pfac_[a-z_0-9]+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_symbols_are_exported(lib):
+    declared = _declared_functions()
+    assert len(declared) >= 20
+    out = subprocess.check_output(["nm", "-D", "--defined-only", pf._pfac.LIB_PATH], text=True)
+    exported = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    missing = [n for n in declared if n not in exported]
+    assert not missing, missing
+    # and the binding knows every one of them
+    assert sorted(n for n, _, _ in pf.SIGNATURES) == declared
+
+
+@pytest.mark.parametrize("make", [
+    lambda: workloads.c1_plain_small(n_text=64, k=100, n_plants=0).patterns.as_list(),
+    lambda: workloads.c2_signature_set(n_text=64, k=800).patterns.as_list(),
+    lambda: workloads.c3_dna(n_text=64, k=3000, n_plants=0).patterns.as_list(),
+    lambda: [b"a", b"ab", b"abc", b"ab", b"b", b"\x00", b"\xff\x00", b"a"],
+    lambda: [],
+])
+def test_builder_equals_canonical_trie(lib, make):
+    pats = make()
+    t = pf.Trie(pats, host_only=True)
+    got = t.export()
+    want = oracle.canonical_trie(pats)
+    for key in ("row_ptr", "labels", "child", "term_ptr", "term_ids"):
+        assert np.array_equal(got[key], want[key]), key
+    st = t.stats()
+    N = len(want["row_ptr"]) - 1
+    fp = oracle.footprint(N, len(pats))
+    assert st["nodes"] == N and st["edges"] == max(N - 1, 0)
+    assert st["bytes_dense256"] == fp["dense"]
+    assert st["bytes_bitmap36"] == fp["bitmap36"]
+    assert st["crs_elements"] == fp["crs_elements"]
+    assert st["bytes_crs"] == fp["crs_bytes"]
+    if pats:
+        assert st["max_len"] == max(len(p) for p in pats)
+        assert st["min_len"] == min(len(p) for p in pats)
+    assert st["bytes_device"] == 0  # host-only build
+
+
+def test_level_index_choice(lib):
+    # full-byte alphabet: K = 2 at 16 bits; DNA: 2-bit symbols, K = 8
+    t = pf.Trie(workloads.c1_plain_small(n_text=64, k=100, n_plants=0).patterns, host_only=True)
+    s = t.stats()
+    assert (s["symbol_bits"], s["index_depth"]) == (8, 2)
+    t = pf.Trie(workloads.c3_dna(n_text=64, k=3000, n_plants=0).patterns, host_only=True)
+    s = t.stats()
+    assert (s["alphabet_size"], s["symbol_bits"], s["index_depth"]) == (4, 2, 8)
+    t.set_tuning(16, 18, 0)
+    assert t.stats()["index_depth"] == 9
+    # the index never reaches a pattern end: K <= shortest - 1
+    t = pf.Trie([b"abc", b"abcdef"], host_only=True)
+    assert t.stats()["index_depth"] == 2
+    t = pf.Trie([b"a", b"abcdef"], host_only=True)
+    assert t.stats()["index_depth"] == 0
+
+
+def test_error_codes(lib):
+    import ctypes
+    h = ctypes.c_void_p()
+    data = np.frombuffer(b"abcd", dtype=np.uint8).copy()
+    offs = np.array([0, 2, 2, 4], dtype=np.uint64)  # second pattern empty
+    rc = lib.pfac_build_packed(data.ctypes.data, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                               3, pf.PFAC_BUILD_HOST_ONLY, ctypes.byref(h))
+    assert rc == pf.PFAC_EEMPTY
+    assert lib.pfac_build_packed(None, None, 1, pf.PFAC_BUILD_HOST_ONLY, ctypes.byref(h)) == pf.PFAC_EINVAL
+    assert lib.pfac_build_packed(data.ctypes.data, offs.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                 0, 1 << 5, ctypes.byref(h)) == pf.PFAC_EINVAL
+    assert lib.pfac_trie_stats(None, None) == pf.PFAC_EINVAL
+    lib.pfac_trie_free(None)
+    lib.pfac_workspace_free(None)
+    lib.pfac_graph_free(None)
+    lib.pfac_server_free(None)
+    t = pf.Trie([b"abc"], host_only=True)
+    # a host-only trie cannot scan
+    rc = lib.pfac_scan(t.handle, None, None, 0, None, 0, None, None, None)
+    assert rc == pf.PFAC_EINVAL
+    with pytest.raises(pf.PfacError):
+        t.set_tuning(bytes_per_lane=5)
+    assert pf.strerror(pf.PFAC_ETRUNC) == "more matches than capacity"
+
+
+def test_pattern_pointer_build(lib):
+    import ctypes
+    pats = [b"he", b"she", b"his", b"hers"]
+    bufs = [ctypes.create_string_buffer(p, len(p)) for p in pats]
+    ptrs = (ctypes.c_void_p * len(pats))(*[ctypes.addressof(b) for b in bufs])
+    lens = (ctypes.c_uint64 * len(pats))(*[len(p) for p in pats])
+    h = ctypes.c_void_p()
+    assert lib.pfac_build(ptrs, lens, len(pats), pf.PFAC_BUILD_HOST_ONLY, ctypes.byref(h)) == 0
+    st = pf._pfac.pfac_stats()
+    assert lib.pfac_trie_stats(h, ctypes.byref(st)) == 0
+    assert st.nodes == len(oracle.canonical_trie(pats)["row_ptr"]) - 1
+    lib.pfac_trie_free(h)

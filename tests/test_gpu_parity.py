@@ -1,0 +1,222 @@
+"""GPU parity: the HIP scan through the C ABI against the CPU oracle, bit-exact
+on the sorted (text, pos, pattern_id) list and on per-position counts."""
+
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1702_03657_amd as pf
+from synth import PatternSet, workloads
+from tests.gpu_util import assert_same, gpu_scan, gpu_scan_batch, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    pf.load()
+
+
+def test_c1_full_size_against_brute_force():
+    wl = workloads.c1_plain_small()
+    say(f"c1 full: {wl.text.size} bytes, {len(wl.patterns)} patterns")
+    trie = pf.Trie(wl.patterns)
+    got, counts = gpu_scan(trie, wl.text)
+    want = oracle.brute(wl.text, wl.patterns, threads=8)
+    assert want.n >= 900
+    assert_same(got, want)
+    assert np.array_equal(counts, oracle.counts(wl.text.size, want))
+
+
+@pytest.mark.parametrize("bpl", [4, 8, 16])
+@pytest.mark.parametrize("bits", [8, 12, 16, 18])
+def test_every_tuning_point_c1(bpl, bits):
+    wl = workloads.c1_plain_small(n_text=(1 << 18) + 77, k=100, n_plants=400)
+    trie = pf.Trie(wl.patterns)
+    trie.set_tuning(bpl, bits, 0)
+    say(f"tuning bpl={bpl} bits={bits} K={trie.stats()['index_depth']}")
+    got, counts = gpu_scan(trie, wl.text)
+    want = oracle.brute(wl.text, wl.patterns, threads=8)
+    assert_same(got, want)
+    assert np.array_equal(counts, oracle.counts(wl.text.size, want))
+
+
+@pytest.mark.parametrize("bpl,bits,wpc", [(16, 16, 0), (8, 18, 2), (4, 12, 1), (16, 8, 4)])
+def test_dna_tuning_points(bpl, bits, wpc):
+    wl = workloads.c3_dna(n_text=(1 << 20) + 5, k=20_000, n_plants=2000)
+    trie = pf.Trie(wl.patterns)
+    trie.set_tuning(bpl, bits, wpc)
+    st = trie.stats()
+    say(f"dna bpl={bpl} bits={bits} wpc={wpc} K={st['index_depth']} b={st['symbol_bits']}")
+    got, counts = gpu_scan(trie, wl.text)
+    want = oracle.bucketed(wl.text, wl.patterns, threads=8)
+    assert want.n >= 2000
+    assert_same(got, want)
+    assert np.array_equal(counts, oracle.counts(wl.text.size, want))
+
+
+def test_c2_scaled_full_pattern_set():
+    wl = workloads.c2_signature_set(n_text=16 << 20, k=10_000)
+    say(f"c2 scaled: {wl.text.size} bytes")
+    trie = pf.Trie(wl.patterns)
+    got, counts = gpu_scan(trie, wl.text)
+    want = oracle.bucketed(wl.text, wl.patterns, threads=8)
+    assert_same(got, want)
+    assert np.array_equal(counts, oracle.counts(wl.text.size, want))
+
+
+@pytest.mark.parametrize("pad", [1, 3, 7, 8, 13, 15])
+def test_misaligned_text_addresses(pad):
+    wl = workloads.c1_plain_small(n_text=50_001, k=100, n_plants=200)
+    trie = pf.Trie(wl.patterns)
+    got, counts = gpu_scan(trie, wl.text, pad_front=pad)
+    want = oracle.brute(wl.text, wl.patterns, threads=8)
+    assert_same(got, want)
+    assert np.array_equal(counts, oracle.counts(wl.text.size, want))
+
+
+@pytest.mark.parametrize("case", [
+    "empty_text", "short_text", "no_patterns", "length_one", "duplicates", "nested_runs",
+    "all_windows", "sigma1_long", "long_patterns", "match_at_end",
+])
+def test_edge_cases(case):
+    rng = np.random.default_rng(hash(case) & 0xffff)
+    if case == "empty_text":
+        pats, text = [b"abc", b"x"], b""
+    elif case == "short_text":
+        pats, text = [b"abcdef", b"bcdefg"], b"abcde"
+    elif case == "no_patterns":
+        pats, text = [], bytes(rng.integers(0, 256, 10_000).astype(np.uint8))
+    elif case == "length_one":
+        pats = [bytes([c]) for c in rng.choice(256, 30, replace=False)] + [b"\x01\x02"]
+        text = bytes(rng.integers(0, 256, 70_000).astype(np.uint8))
+    elif case == "duplicates":
+        pats = [b"ab", b"xyz", b"ab", b"b", b"ab", b"abxyz", b"xyz"]
+        text = bytes(rng.choice(list(b"abxyz"), 30_000).astype(np.uint8))
+    elif case == "nested_runs":
+        # every position matches many patterns: the dense-tile path
+        pats = [b"a" * d for d in range(1, 40)]
+        text = b"a" * 20_000 + b"b" + b"a" * 5000
+    elif case == "all_windows":
+        pats = [bytes(t) for t in itertools.product(b"ACGT", repeat=5)]
+        text = bytes(rng.choice(list(b"ACGT"), 100_000).astype(np.uint8))
+    elif case == "sigma1_long":
+        pats = [b"\x00" * 17, b"\x00" * 3]
+        text = b"\x00" * 9999
+    elif case == "long_patterns":
+        # longer than the LDS halo: walks continue in global memory
+        base = bytes(rng.integers(0, 4, 5000).astype(np.uint8))
+        pats = [base[:3000], base[:2000] + b"\xff", base[1000:4500], base[4000:4003]]
+        text = (base * 7)[: 30_000]
+    else:  # match_at_end
+        pats = [b"tail!", b"l!"]
+        text = bytes(rng.integers(0, 200, 8191).astype(np.uint8)) + b"tail!"
+    text = np.frombuffer(text, dtype=np.uint8).copy()
+    trie = pf.Trie(pats)
+    say(f"edge {case}: n={text.size} k={len(pats)} K={trie.stats()['index_depth']}")
+    got, counts = gpu_scan(trie, text)
+    want = oracle.brute(text, pats, threads=8)
+    assert_same(got, want)
+    if text.size:
+        assert np.array_equal(counts, oracle.counts(text.size, want))
+
+
+def test_capacity_overflow_reports_exact_count():
+    wl = workloads.c1_plain_small(n_text=200_000, k=100, n_plants=2000)
+    trie = pf.Trie(wl.patterns)
+    want = oracle.brute(wl.text, wl.patterns, threads=8)
+    ws = pf.Workspace()
+    import torch
+    t = torch.from_numpy(wl.text).cuda()
+    out = torch.empty(16 * 100, dtype=torch.uint8, device="cuda")
+    rc, cnt = pf.pfac_scan_sync(trie, ws, t, t.numel(), out, 100)
+    assert rc == pf.PFAC_ETRUNC and cnt == want.n
+    rc, cnt = pf.pfac_scan_sync(trie, ws, t, t.numel(), None, 0)
+    assert rc == pf.PFAC_ETRUNC and cnt == want.n
+    # the same workspace then serves a full scan
+    got, _ = gpu_scan(trie, wl.text, ws=ws, counts=False, capacity=want.n)
+    assert_same(got, want)
+
+
+def _random_batch(rng, n_texts, max_len, alphabet):
+    lens = rng.integers(0, max_len + 1, n_texts)
+    lens[rng.integers(0, n_texts, max(1, n_texts // 10))] = 0   # some empty texts
+    offs = np.zeros(n_texts + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(lens)
+    text = rng.choice(alphabet, int(offs[-1])).astype(np.uint8)
+    return text, offs
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_batch_matches_oracle_and_plain(seed):
+    rng = np.random.default_rng(seed)
+    alphabet = np.frombuffer(b"abcd", dtype=np.uint8)
+    text, offs = _random_batch(rng, 3000, 700, alphabet)
+    pats = [bytes(rng.choice(alphabet, int(rng.integers(2, 9))).astype(np.uint8)) for _ in range(300)]
+    trie = pf.Trie(pats)
+    say(f"batch seed={seed}: {len(offs) - 1} texts, {offs[-1]} bytes")
+    want = oracle.brute(text, pats, offsets=offs, threads=8)
+    got, n = gpu_scan_batch(trie, text, offs, pad_front=seed * 5)
+    assert n == want.n
+    assert_same(got, want, with_text=True)
+    got_plain, n2 = gpu_scan_batch(trie, text, offs, plain=True)
+    assert n2 == want.n
+    assert_same(got_plain, want, with_text=True)
+
+
+def test_batch_graph_replays_are_identical():
+    rng = np.random.default_rng(9)
+    wl = workloads.c4_batched(n_small=2000, n_large=3, large_lo=1 << 16, large_hi=1 << 18,
+                              k=2000, rate=1 / 512)
+    trie = pf.Trie(wl.patterns)
+    want = oracle.bucketed(wl.text, wl.patterns, offsets=wl.offsets, threads=8)
+    say(f"graph: {wl.n_texts} texts {wl.text.size} bytes, {want.n} matches")
+    results, n = gpu_scan_batch(trie, wl.text, wl.offsets, graph_replays=4)
+    assert n == want.n
+    for r in results:
+        assert_same(r, want, with_text=True)
+    del rng
+
+
+def test_exhaustive_binary_alphabet_batched():
+    """All multisets of <= 3 patterns of length 1..3 over {0,1}, every text of
+    length 0..8, one batched launch per pattern set."""
+    strs = [bytes(t) for L in range(1, 4) for t in itertools.product(b"\x00\x01", repeat=L)]
+    texts = [bytes(t) for L in range(0, 9) for t in itertools.product(b"\x00\x01", repeat=L)]
+    offs = np.zeros(len(texts) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum([len(t) for t in texts])
+    text = np.frombuffer(b"".join(texts), dtype=np.uint8).copy()
+    sets = []
+    for r in (1, 2, 3):
+        sets.extend(itertools.combinations_with_replacement(range(len(strs)), r))
+    assert len(sets) == 679
+    ws = pf.Workspace()
+    say(f"exhaustive: {len(sets)} pattern sets x {len(texts)} texts")
+    for s in sets:
+        pats = [strs[i] for i in s]
+        trie = pf.Trie(pats)
+        got, n = gpu_scan_batch(trie, text, offs, ws=ws, capacity=4096)
+        want = oracle.brute(text, pats, offsets=offs)
+        assert n == want.n, pats
+        assert_same(got, want, with_text=True)
+        trie.close()
+
+
+def test_autotune_keeps_results():
+    wl = workloads.c2_signature_set(n_text=4 << 20, k=2000)
+    trie = pf.Trie(wl.patterns)
+    import torch
+    t = torch.from_numpy(wl.text).cuda()
+    ws = pf.Workspace()
+    best = pf.pfac_autotune(trie, ws, t, t.numel())
+    say(f"autotune best: {best}")
+    assert best["bytes_per_lane"] in (4, 8, 16)
+    got, _ = gpu_scan(trie, wl.text, ws=ws, counts=False)
+    want = oracle.bucketed(wl.text, wl.patterns, threads=8)
+    assert_same(got, want)
