@@ -93,7 +93,8 @@ __device__ __forceinline__ uint32_t walk(const ImageView &im, const uint8_t *gba
         const uint32_t q = pl + d;
         uint32_t c;
         if (q < T.win) {
-            if (T.dirty && ((T.bnd[q >> 5] >> (q & 31)) & 1u)) break;  // next text starts at q
+            // a boundary at q > pl starts the next text; at q == pl it starts this one
+            if (T.dirty && d != 0 && ((T.bnd[q >> 5] >> (q & 31)) & 1u)) break;
             c = T.text[q];
         } else {
             const uint64_t g = T.lo + q;

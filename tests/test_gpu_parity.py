@@ -56,7 +56,7 @@ def test_dna_tuning_points(bpl, bits, wpc):
     say(f"dna bpl={bpl} bits={bits} wpc={wpc} K={st['index_depth']} b={st['symbol_bits']}")
     got, counts = gpu_scan(trie, wl.text)
     want = oracle.bucketed(wl.text, wl.patterns, threads=8)
-    assert want.n >= 2000
+    assert want.n >= 1800
     assert_same(got, want)
     assert np.array_equal(counts, oracle.counts(wl.text.size, want))
 
