@@ -61,7 +61,7 @@ def tuning_cache_path():
 def choose_tuning(pf, trie, ws, text_dev, n, workload, device_name, retune):
     """Autotune once per (workload, device); later runs reuse the cached choice."""
     path = tuning_cache_path()
-    key = f"{workload}|{n}|{device_name}"
+    key = f"{workload}|{n}"
     cache = {}
     if os.path.exists(path):
         try:
@@ -71,7 +71,7 @@ def choose_tuning(pf, trie, ws, text_dev, n, workload, device_name, retune):
             cache = {}
     if key in cache and not retune:
         t = cache[key]
-        trie.set_tuning(t["bytes_per_lane"], t["index_bits"], t["wg_per_cu"])
+        trie.set_tuning(**t)
         return t, False
     t0 = time.time()
     best = pf.pfac_autotune(trie, ws, text_dev, n)
@@ -182,7 +182,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--retune", action="store_true", help="ignore the cached autotune choice")
-    ap.add_argument("--tuning", default=None, help="bytes_per_lane,index_bits,wg_per_cu")
+    ap.add_argument("--tuning", default=None,
+                    help="kernel,bytes_per_lane,index_bits,fold_bits,wg_per_cu,waves_per_wg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--extras", action="store_true", help="add batched-vs-plain (c4)")
@@ -227,8 +228,8 @@ def main():
     h2d_ms = h0.elapsed_time(h1)
 
     if args.tuning:
-        b, i, w = (int(x) for x in args.tuning.split(","))
-        trie.set_tuning(b, i, w)
+        names = ["kernel", "bytes_per_lane", "index_bits", "fold_bits", "wg_per_cu", "waves_per_wg"]
+        trie.set_tuning(**dict(zip(names, (int(x) for x in args.tuning.split(",")))))
         tuning, tuned_now = trie.tuning(), False
     else:
         tuning, tuned_now = choose_tuning(pf, trie, ws, text, n, args.workload, dev_name,
@@ -295,7 +296,7 @@ def main():
             "text_bytes": n,
             "patterns": len(wl.patterns),
             "matches": n_matches,
-            "tuning": {k: int(v) for k, v in tuning.items() if k != "reserved"},
+            "tuning": {k: int(v) for k, v in tuning.items()},
             "autotuned_this_run": tuned_now,
             "index_depth": int(st["index_depth"]),
             "symbol_bits": int(st["symbol_bits"]),

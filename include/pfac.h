@@ -86,10 +86,12 @@ typedef struct {
 
 /* Launch parameters chosen by hand or by pfac_autotune. */
 typedef struct {
-    uint32_t bytes_per_lane;   /* start positions per lane per tile: 4, 8 or 16 */
-    uint32_t index_bits;       /* level-index width in bits (8..18); depth K = bits / symbol_bits */
-    uint32_t wg_per_cu;        /* persistent workgroups per compute unit (1..8, 0 = occupancy max) */
-    uint32_t reserved;
+    uint32_t kernel;           /* 0 = tile kernel (workgroup tiles), 1 = wave kernel */
+    uint32_t bytes_per_lane;   /* tile kernel: start positions per lane per tile: 4, 8 or 16 */
+    uint32_t index_bits;       /* level-index width in bits (1..18); depth K = bits / symbol_bits */
+    uint32_t fold_bits;        /* wave kernel prefix filter: 0 (level bitmap), 8 or 16 bits per node */
+    uint32_t wg_per_cu;        /* resident workgroups per compute unit (0 = occupancy max) */
+    uint32_t waves_per_wg;     /* wave kernel: 4, 8 or 16 waves per workgroup */
 } pfac_tuning;
 
 /* ----------------------------------------------------------------- errors */

@@ -23,7 +23,7 @@ HIP_FLAGS = [
 ]
 CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall"]
 
-HIP_SOURCES = ["kernels.hip", "api.hip", "server.hip"]
+HIP_SOURCES = ["kernels.hip", "scan_wave.hip", "api.hip", "server.hip"]
 CXX_SOURCES = ["trie_build.cpp"]
 
 

@@ -57,7 +57,8 @@ struct DeviceBuf {
 struct pfac_trie {
     CrsTrie crs;
     DeviceImageHost img;
-    pfac_tuning tuning{16, 16, 0, 0};
+    pfac_tuning tuning{1, 16, 16, 8, 0, 16};
+    uint32_t lds_limit = 64 * 1024;  // dynamic LDS a workgroup may use
     bool host_only = false;
     int device = -1;
     int n_cu = 0;
@@ -111,7 +112,9 @@ static int upload_image(pfac_trie *t) {
     size_t o_pids = align256(o_pptr + I.pout_ptr.size() * 4);
     size_t o_lvl = align256(o_pids + I.pout_ids.size() * 4);
     size_t o_sym = align256(o_lvl + std::max<size_t>(I.lvl.size(), 2) * 4);
-    size_t total = align256(o_sym + 256);
+    size_t o_ftab = align256(o_sym + 256);
+    size_t o_root = align256(o_ftab + std::max<size_t>(I.ftab.size(), 16));
+    size_t total = align256(o_root + std::max<size_t>(I.root_bits.size(), 1) * 4);
     auto t0 = std::chrono::steady_clock::now();
     t->dev.release();
     HIP_TRY(t->dev.reserve(total));
@@ -123,6 +126,10 @@ static int upload_image(pfac_trie *t) {
     if (!I.lvl.empty())
         HIP_TRY(hipMemcpy(b + o_lvl, I.lvl.data(), I.lvl.size() * 4, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(b + o_sym, I.sym.data(), 256, hipMemcpyHostToDevice));
+    if (!I.ftab.empty())
+        HIP_TRY(hipMemcpy(b + o_ftab, I.ftab.data(), I.ftab.size(), hipMemcpyHostToDevice));
+    if (!I.root_bits.empty())
+        HIP_TRY(hipMemcpy(b + o_root, I.root_bits.data(), I.root_bits.size() * 4, hipMemcpyHostToDevice));
     ImageView &v = t->view;
     v.node = (const uint4 *)(b + o_node);
     v.label = b + o_label;
@@ -130,6 +137,9 @@ static int upload_image(pfac_trie *t) {
     v.pout_ids = (const uint32_t *)(b + o_pids);
     v.lvl = (const uint32_t *)(b + o_lvl);
     v.sym = b + o_sym;
+    v.ftab = b + o_ftab;
+    v.root_bits = (const uint32_t *)(b + o_root);
+    v.fold_syms = I.fold_syms;
     v.K = I.K;
     v.b = I.b;
     v.identity = I.identity;
@@ -167,7 +177,7 @@ static int build_common(const uint8_t *data, const uint64_t *offsets, uint32_t k
             delete t;
             return PFAC_EINVAL;
         }
-        pack_image(t->crs, t->tuning.index_bits, t->img);
+        pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->img);
     } catch (const std::bad_alloc &) {
         delete t;
         return PFAC_ENOMEM;
@@ -178,6 +188,11 @@ static int build_common(const uint8_t *data, const uint64_t *offsets, uint32_t k
     if (!t->host_only) {
         hipError_t e = hipGetDevice(&t->device);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&t->n_cu, hipDeviceAttributeMultiprocessorCount, t->device);
+        int lds = 0;
+        if (e == hipSuccess &&
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, t->device) == hipSuccess &&
+            lds > 0)
+            t->lds_limit = (uint32_t)lds;
         if (e != hipSuccess) {
             delete t;
             return hip_fail(e);
@@ -220,14 +235,22 @@ extern "C" int pfac_build(const uint8_t *const *patterns, const uint64_t *length
     return build_common(data.data(), off.data(), n_patterns, flags, out);
 }
 
-static uint32_t lds_bytes_for(const pfac_trie *t, uint32_t bpl) {
+static ScanArgs layout_for(const pfac_trie *t) {
     ScanArgs a{};
     a.im = t->view;
     a.im.lvl_words = t->img.lvl_words;
     a.im.identity = t->img.identity;
+    a.im.K = t->img.K;
+    a.im.b = t->img.b;
+    a.im.fold_syms = t->img.fold_syms;
     a.halo = t->halo;
-    lds_layout(a, bpl);
-    return a.lds_total;
+    if (t->tuning.kernel == 1) {
+        a.fold = t->img.fold_bits;
+        wave_lds_layout(a, t->tuning.waves_per_wg, t->lds_limit);
+    } else {
+        lds_layout(a, t->tuning.bytes_per_lane);
+    }
+    return a;
 }
 
 extern "C" int pfac_trie_stats(const pfac_trie *t, pfac_stats *o) {
@@ -249,7 +272,7 @@ extern "C" int pfac_trie_stats(const pfac_trie *t, pfac_stats *o) {
     o->alphabet_size = t->img.alphabet;
     o->symbol_bits = t->img.b;
     o->index_depth = t->img.K;
-    o->lds_bytes = lds_bytes_for(t, t->tuning.bytes_per_lane);
+    o->lds_bytes = layout_for(t).lds_total;
     o->build_seconds = t->build_s;
     o->upload_seconds = t->upload_s;
     return PFAC_OK;
@@ -281,17 +304,20 @@ extern "C" int pfac_trie_get_tuning(const pfac_trie *t, pfac_tuning *out) {
 }
 
 static bool valid_tuning(const pfac_tuning *p) {
-    return (p->bytes_per_lane == 4 || p->bytes_per_lane == 8 || p->bytes_per_lane == 16) &&
-           p->index_bits >= 1 && p->index_bits <= 18 && p->wg_per_cu <= 8;
+    return p->kernel <= 1 &&
+           (p->bytes_per_lane == 4 || p->bytes_per_lane == 8 || p->bytes_per_lane == 16) &&
+           p->index_bits >= 1 && p->index_bits <= 18 &&
+           (p->fold_bits == 0 || p->fold_bits == 8 || p->fold_bits == 16) && p->wg_per_cu <= 8 &&
+           (p->waves_per_wg == 4 || p->waves_per_wg == 8 || p->waves_per_wg == 16);
 }
 
 extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
     if (!t || !tn || !valid_tuning(tn)) return PFAC_EINVAL;
-    const bool repack = tn->index_bits != t->tuning.index_bits;
+    const bool repack = tn->index_bits != t->tuning.index_bits || tn->fold_bits != t->tuning.fold_bits;
     t->tuning = *tn;
     if (repack) {
         try {
-            pack_image(t->crs, t->tuning.index_bits, t->img);
+            pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->img);
         } catch (const std::bad_alloc &) {
             return PFAC_ENOMEM;
         }
@@ -375,10 +401,45 @@ static uint64_t tiles_for(uint64_t total, uint64_t shift, uint32_t tile) {
     return total ? (shift + total + tile - 1) / tile : 0;
 }
 
+static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out);
+
+static uint32_t unit_bytes(const pfac_trie *t) {
+    return use_wave_kernel(t, nullptr) ? kWaveChunk : kWG * t->tuning.bytes_per_lane;
+}
+
+// Opt a kernel into more than 64 KiB of dynamic LDS (once per size).
+static hipError_t grant_lds(int slot, uint32_t bytes, hipError_t (*fn)(int, uint32_t), int arg) {
+    static std::mutex mu;
+    static uint32_t granted[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    std::lock_guard<std::mutex> lock(mu);
+    if (granted[slot] >= bytes) return hipSuccess;
+    hipError_t e = fn(arg, bytes);
+    if (e == hipSuccess) granted[slot] = bytes;
+    return e;
+}
+
+static hipError_t prep_tile(int bpl, uint32_t bytes) { return prepare_kernels((uint32_t)bpl, bytes); }
+static hipError_t prep_wave(int mode, uint32_t bytes) { return prepare_wave_kernel(mode, bytes); }
+
+// Wave kernel when asked for and its LDS layout fits; the tile kernel otherwise.
+static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out) {
+    if (t->tuning.kernel != 1) return false;
+    ScanArgs a = layout_for(t);
+    uint32_t waves = t->tuning.waves_per_wg;
+    while (a.lds_total > t->lds_limit && waves > 4) {
+        waves /= 2;
+        wave_lds_layout(a, waves, t->lds_limit);
+    }
+    if (waves_out) *waves_out = waves;
+    return a.lds_total <= t->lds_limit;
+}
+
 static int enqueue_scan(const Launch &L, bool reserve) {
     const pfac_trie *t = L.t;
+    uint32_t waves = t->tuning.waves_per_wg;
+    const bool wave_kernel = use_wave_kernel(t, &waves);
     const uint32_t bpl = t->tuning.bytes_per_lane;
-    const uint32_t tile = kWG * bpl;
+    const uint32_t tile = wave_kernel ? kWaveChunk : kWG * bpl;
     const uintptr_t addr = (uintptr_t)L.text;
     const uint64_t shift = addr & 15;
     uint64_t n_tiles = tiles_for(L.total, shift, tile);
@@ -392,6 +453,13 @@ static int enqueue_scan(const Launch &L, bool reserve) {
 
     ScanArgs a{};
     a.im = t->view;
+    a.halo = t->halo;
+    if (wave_kernel) {
+        a.fold = t->img.fold_bits;
+        wave_lds_layout(a, waves, t->lds_limit);
+    } else {
+        lds_layout(a, bpl);
+    }
     a.base = (const uint8_t *)(addr - shift);
     a.shift = shift;
     a.total = L.total;
@@ -400,8 +468,6 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     a.text_id0 = L.text_id0;
     a.tile_first_text = L.offsets ? (const uint32_t *)w->tile_first.p : nullptr;
     a.n_tiles = n_tiles;
-    a.halo = t->halo;
-    lds_layout(a, bpl);
     a.stage = (pfac_match *)w->stage.p;
     a.stage_cap = std::min<uint64_t>(L.capacity, w->stage.bytes / sizeof(pfac_match));
     a.stage_cursor = w->cursor();
@@ -409,6 +475,7 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     a.unit_off = (unsigned long long *)w->unit_off.p;
     a.blocksum = (unsigned long long *)w->blocksum.p;
     a.counts = L.counts;
+    if (a.lds_total > t->lds_limit) return PFAC_EINVAL;
 
     HIP_TRY(launch_reset(a.stage_cursor, a.blocksum, n_blocks, L.s));
     if (L.counts) HIP_TRY(launch_fill_u32(L.counts, L.total, 0, L.s));
@@ -416,24 +483,28 @@ static int enqueue_scan(const Launch &L, bool reserve) {
         if (L.offsets)
             HIP_TRY(launch_plan(L.offsets, L.n_texts, shift, n_tiles, tile,
                                 (uint32_t *)w->tile_first.p, L.s));
-        if (a.lds_total > 64 * 1024) {
-            // kernels need an explicit opt-in above 64 KiB of dynamic LDS
-            static std::mutex mu;
-            static uint32_t granted[3] = {0, 0, 0};
-            const int slot = bpl == 4 ? 0 : bpl == 8 ? 1 : 2;
-            std::lock_guard<std::mutex> lock(mu);
-            if (granted[slot] < a.lds_total) {
-                HIP_TRY(prepare_kernels(bpl, a.lds_total));
-                granted[slot] = a.lds_total;
-            }
-        }
         int per_cu = (int)t->tuning.wg_per_cu;
-        const int occ = max_wg_per_cu(bpl, a.lds_total);
+        int occ;
+        uint64_t want;
+        if (wave_kernel) {
+            const int mode = wave_mode(a);
+            if (a.lds_total > 64 * 1024) HIP_TRY(grant_lds(4 + mode, a.lds_total, prep_wave, mode));
+            occ = max_wave_wg_per_cu(a, waves);
+            want = (n_tiles + waves - 1) / waves;
+        } else {
+            const int slot = bpl == 4 ? 0 : bpl == 8 ? 1 : 2;
+            if (a.lds_total > 64 * 1024) HIP_TRY(grant_lds(slot, a.lds_total, prep_tile, (int)bpl));
+            occ = max_wg_per_cu(bpl, a.lds_total);
+            want = n_tiles;
+        }
         if (per_cu == 0 || per_cu > occ) per_cu = occ;
         const uint64_t resident = (uint64_t)std::max(1, t->n_cu) * (uint64_t)per_cu;
-        const uint32_t grid = (uint32_t)std::min<uint64_t>(n_tiles, resident);
+        const uint32_t grid = (uint32_t)std::min<uint64_t>(want, resident);
         if (w->ev_start) HIP_TRY(hipEventRecord(w->ev_start, L.s));
-        HIP_TRY(launch_scan(a, bpl, grid, L.s));
+        if (wave_kernel)
+            HIP_TRY(launch_scan_waves(a, waves, grid, L.s));
+        else
+            HIP_TRY(launch_scan(a, bpl, grid, L.s));
         if (w->ev_stop) HIP_TRY(hipEventRecord(w->ev_stop, L.s));
     }
     FinishArgs f{};
@@ -508,7 +579,7 @@ extern "C" int pfac_scan_batch_plain(const pfac_trie *t, pfac_workspace *w,
     for (uint32_t i = 0; i < n_texts; i++) {
         if (offsets_host[i + 1] < offsets_host[i]) return PFAC_EINVAL;
         max_tiles = std::max(max_tiles, tiles_for(offsets_host[i + 1] - offsets_host[i], 15,
-                                                  kWG * t->tuning.bytes_per_lane));
+                                                  unit_bytes(t)));
     }
     rc = ws_reserve(w, max_tiles, capacity);
     if (rc) return rc;
@@ -538,8 +609,7 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
     int rc = check_scan_args(t, w, texts_dev, total_bytes, out_dev, capacity, n_matches_dev);
     if (rc) return rc;
     if (!offsets_dev) return PFAC_EINVAL;
-    const uint32_t tile = kWG * t->tuning.bytes_per_lane;
-    rc = ws_reserve(w, tiles_for(total_bytes, 15, tile), capacity);
+    rc = ws_reserve(w, tiles_for(total_bytes, 15, unit_bytes(t)), capacity);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     hipStream_t own = nullptr;
@@ -643,17 +713,21 @@ extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *tex
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     std::vector<pfac_tuning> cands;
-    for (uint32_t bpl : {4u, 8u, 16u})
-        for (uint32_t bits : {12u, 14u, 16u, 18u})
-            for (uint32_t wpc : {0u, 2u, 4u}) cands.push_back({bpl, bits, wpc, 0});
+    for (uint32_t bits : {12u, 16u, 18u}) {
+        for (uint32_t fold : {8u, 16u, 0u})
+            for (uint32_t waves : {8u, 16u}) cands.push_back({1, 16, bits, fold, 0, waves});
+        for (uint32_t bpl : {8u, 16u}) cands.push_back({0, bpl, bits, 8, 0, 16});
+    }
     float best_ms = 1e30f;
     pfac_tuning best_t = start;
     std::vector<uint64_t> seen;  // (bytes per lane, index depth, wg per CU) already timed
     for (const pfac_tuning &c : cands) {
         if (pfac_trie_set_tuning(t, &c) != PFAC_OK) continue;
         // index widths that give the same depth K and symbol width repeat a point
-        const uint64_t key = ((uint64_t)c.bytes_per_lane << 48) | ((uint64_t)t->img.K << 32) |
-                             ((uint64_t)t->img.b << 16) | c.wg_per_cu;
+        const uint64_t key = ((uint64_t)c.kernel << 60) | ((uint64_t)c.bytes_per_lane << 48) |
+                             ((uint64_t)t->img.K << 40) | ((uint64_t)t->img.b << 32) |
+                             ((uint64_t)t->img.fold_bits << 24) | ((uint64_t)c.waves_per_wg << 8) |
+                             c.wg_per_cu;
         if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
         seen.push_back(key);
         uint64_t cn = 0;

@@ -22,8 +22,10 @@ struct ImageView {
     const uint32_t *pout_ids;
     const uint32_t *lvl;      // 2 per word: bits, rank before
     const uint8_t *sym;       // 256
+    const uint8_t *ftab;      // prefix filter: folded child bitmaps of depth-K nodes
+    const uint32_t *root_bits;  // codes of the root's children
     uint32_t K, b, identity, lvl_words;
-    uint32_t lvl_start, max_len, n_nodes, pad;
+    uint32_t lvl_start, max_len, n_nodes, fold_syms;
 };
 
 struct ScanArgs {
@@ -40,6 +42,10 @@ struct ScanArgs {
     uint32_t pad0;
     // dynamic LDS layout (byte offsets)
     uint32_t off_bits, off_rank, off_sym, off_text, off_bnd, off_queue, off_match, lds_total;
+    // wave kernel: shared tables, then one area per wave
+    uint32_t fold;                    // prefix-filter bits per entry (0, 8, 16)
+    uint32_t ftab_bytes, off_ftab, root_words, off_root;
+    uint32_t off_wave, wave_bytes, woff_bnd, woff_queue, woff_match, qcap, mcap, pad1;
     // outputs
     pfac_match *stage;
     uint64_t stage_cap;
@@ -77,6 +83,15 @@ hipError_t launch_scan(const ScanArgs &a, uint32_t bpl, uint32_t grid, hipStream
 hipError_t launch_finish(const FinishArgs &f, hipStream_t s);
 hipError_t launch_add_running(unsigned long long *running, const uint64_t *n, hipStream_t s);
 hipError_t launch_copy_u64(uint64_t *dst, const unsigned long long *src, hipStream_t s);
+
+// Wave kernel: LDS layout for `waves` waves within `lds_limit` bytes, launch,
+// and occupancy.
+constexpr uint32_t kWaveChunk = 1024;
+void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit);
+int wave_mode(const ScanArgs &a);
+hipError_t prepare_wave_kernel(int mode, uint32_t lds_bytes);
+hipError_t launch_scan_waves(const ScanArgs &a, uint32_t waves, uint32_t grid, hipStream_t s);
+int max_wave_wg_per_cu(const ScanArgs &a, uint32_t waves);
 
 // Largest resident workgroups per CU for this layout.
 int max_wg_per_cu(uint32_t bpl, uint32_t lds_bytes);

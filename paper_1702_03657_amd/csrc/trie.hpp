@@ -63,10 +63,22 @@ struct DeviceImageHost {
     std::vector<uint8_t> sym;          // 256: symbol code, 0xff = byte unused
     uint32_t alphabet = 0;
     uint32_t n_term = 0;
+    // Prefix filter of the wave kernel.  With K >= 1 it is a table of E-bit
+    // entries indexed by the K-symbol code of a depth-K node: bit
+    // (code of the next m symbols) & (E - 1) is set for each of its
+    // depth-(K+m) descendants, i.e. a child bitmap of the node folded to E
+    // bits (exact when b * m <= log2 E).  A start position whose first K + m
+    // symbols miss it cannot match (K + m <= shortest pattern).  With K = 0
+    // the filter is the root's child bitmap over the first symbol.
+    uint32_t fold_bits = 0;            // E: 8 or 16 (0 = no table)
+    uint32_t fold_syms = 0;            // m
+    std::vector<uint8_t> ftab;         // 2^(b K) entries of E bits
+    std::vector<uint32_t> root_bits;   // 2^b bits: codes of the root's children
 };
 
 // Derives the device image from the CRS trie for a level index of at most
-// `index_bits` bits.
-void pack_image(const CrsTrie &t, uint32_t index_bits, DeviceImageHost &img);
+// `index_bits` bits and a prefix filter of `fold_bits` (0, 8 or 16) bits per
+// entry.
+void pack_image(const CrsTrie &t, uint32_t index_bits, uint32_t fold_bits, DeviceImageHost &img);
 
 }  // namespace pfac

@@ -89,7 +89,8 @@ static uint32_t ceil_log2(uint32_t x) {
     return b;
 }
 
-void pack_image(const CrsTrie &T, uint32_t index_bits, DeviceImageHost &I) {
+void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
+                DeviceImageHost &I) {
     I = DeviceImageHost{};
     const uint32_t N = T.n_nodes();
     const uint32_t E = T.n_edges();
@@ -150,7 +151,7 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, DeviceImageHost &I) {
     uint32_t b_comp = std::max(1u, ceil_log2(std::max(I.alphabet, 1u)));
     uint32_t depth = (uint32_t)T.max_len;
     uint32_t k_cap = T.k ? (uint32_t)std::min<uint64_t>(T.min_len - 1, depth) : 0;
-    k_cap = std::min(k_cap, 16u);
+    k_cap = std::min(k_cap, 12u);
     uint32_t K8 = std::min(index_bits / 8, k_cap);
     uint32_t Kc = std::min(index_bits / b_comp, k_cap);
     I.sym.assign(256, 0xff);
@@ -166,6 +167,12 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, DeviceImageHost &I) {
         I.b = 8;
         I.K = K8;
         for (int c = 0; c < 256; c++) I.sym[c] = (uint8_t)c;
+    }
+    // codes of the root's children (the filter when K = 0)
+    I.root_bits.assign(std::max(1u, (1u << I.b) / 32), 0);
+    for (uint32_t e = T.row_ptr[0]; e < T.row_ptr[1]; e++) {
+        const uint32_t s = I.sym[T.labels[e]];
+        I.root_bits[s >> 5] |= 1u << (s & 31);
     }
     if (I.K == 0) {
         I.lvl_words = 0;
@@ -188,6 +195,29 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, DeviceImageHost &I) {
     for (uint32_t w = 0; w < I.lvl_words; w++) {
         I.lvl[2 * w + 1] = run;
         run += (uint32_t)__builtin_popcount(I.lvl[2 * w]);
+    }
+
+    // prefix filter over the depth-(K+m) nodes
+    if (fold_bits != 8 && fold_bits != 16) return;
+    const uint32_t log2e = fold_bits == 8 ? 3 : 4;
+    uint32_t m = std::max(1u, log2e / I.b);
+    m = (uint32_t)std::min<uint64_t>(std::min(m, 4u), T.min_len - I.K);
+    if (I.K + m + 1 > T.level_start.size()) return;
+    I.fold_bits = fold_bits;
+    I.fold_syms = m;
+    I.ftab.assign((size_t)n_codes * (fold_bits / 8), 0);
+    const uint32_t d = I.K + m;
+    const uint32_t w0 = T.level_start[d], w1 = T.level_start[d + 1];
+    for (uint32_t w = w0; w < w1; w++) {
+        const uint8_t *p = T.pat_data.data() + T.pat_off[T.rep[w]];
+        uint32_t code = 0, next = 0;
+        for (uint32_t q = 0; q < I.K; q++) code = (code << I.b) | I.sym[p[q]];
+        for (uint32_t q = I.K; q < d; q++) next = (next << I.b) | I.sym[p[q]];
+        const uint32_t bit = next & (fold_bits - 1);
+        if (fold_bits == 8)
+            I.ftab[code] |= (uint8_t)(1u << bit);
+        else
+            reinterpret_cast<uint16_t *>(I.ftab.data())[code] |= (uint16_t)(1u << bit);
     }
 }
 

@@ -73,7 +73,9 @@ def gpu_scan_batch(trie, text: np.ndarray, offsets: np.ndarray, ws=None, pad_fro
         pf.pfac_scan_batch(trie, ws, t if total else None, offs, n_texts, total, out, cap, cnt_dev)
     torch.cuda.synchronize()
     n = int(cnt_dev.item())
-    return pf.matches_to_numpy(out, min(n, cap)), n
+    if n > cap:  # grow the output and scan again: the count is exact either way
+        return gpu_scan_batch(trie, text, offsets, ws, pad_front, n, plain, graph_replays)
+    return pf.matches_to_numpy(out, n), n
 
 
 def assert_same(got: np.ndarray, want: "oracle.Matches", with_text=False):

@@ -79,7 +79,7 @@ def test_level_index_choice(lib):
     t = pf.Trie(workloads.c3_dna(n_text=64, k=3000, n_plants=0).patterns, host_only=True)
     s = t.stats()
     assert (s["alphabet_size"], s["symbol_bits"], s["index_depth"]) == (4, 2, 8)
-    t.set_tuning(16, 18, 0)
+    t.set_tuning(index_bits=18)
     assert t.stats()["index_depth"] == 9
     # the index never reaches a pattern end: K <= shortest - 1
     t = pf.Trie([b"abc", b"abcdef"], host_only=True)

@@ -34,26 +34,45 @@ def test_c1_full_size_against_brute_force():
     assert np.array_equal(counts, oracle.counts(wl.text.size, want))
 
 
-@pytest.mark.parametrize("bpl", [4, 8, 16])
-@pytest.mark.parametrize("bits", [8, 12, 16, 18])
-def test_every_tuning_point_c1(bpl, bits):
+TUNINGS = (
+    [dict(kernel=0, bytes_per_lane=bpl, index_bits=bits) for bpl in (4, 8, 16) for bits in (8, 12, 16, 18)]
+    + [dict(kernel=1, index_bits=bits, fold_bits=fold, waves_per_wg=w)
+       for bits in (8, 12, 16, 18) for fold in (0, 8, 16) for w in (4, 16)]
+)
+
+
+def _tid(t):
+    return "-".join(f"{k[0]}{v}" for k, v in t.items())
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=_tid)
+def test_every_tuning_point_c1(tuning):
     wl = workloads.c1_plain_small(n_text=(1 << 18) + 77, k=100, n_plants=400)
     trie = pf.Trie(wl.patterns)
-    trie.set_tuning(bpl, bits, 0)
-    say(f"tuning bpl={bpl} bits={bits} K={trie.stats()['index_depth']}")
+    trie.set_tuning(**tuning)
+    say(f"tuning {tuning} K={trie.stats()['index_depth']}")
     got, counts = gpu_scan(trie, wl.text)
     want = oracle.brute(wl.text, wl.patterns, threads=8)
     assert_same(got, want)
     assert np.array_equal(counts, oracle.counts(wl.text.size, want))
 
 
-@pytest.mark.parametrize("bpl,bits,wpc", [(16, 16, 0), (8, 18, 2), (4, 12, 1), (16, 8, 4)])
-def test_dna_tuning_points(bpl, bits, wpc):
+DNA_TUNINGS = [
+    dict(kernel=0, bytes_per_lane=16, index_bits=16), dict(kernel=0, bytes_per_lane=8, index_bits=18, wg_per_cu=2),
+    dict(kernel=0, bytes_per_lane=4, index_bits=12, wg_per_cu=1), dict(kernel=0, bytes_per_lane=16, index_bits=8, wg_per_cu=4),
+    dict(kernel=1, index_bits=16, fold_bits=8), dict(kernel=1, index_bits=16, fold_bits=16),
+    dict(kernel=1, index_bits=12, fold_bits=16, waves_per_wg=8), dict(kernel=1, index_bits=18, fold_bits=0),
+    dict(kernel=1, index_bits=14, fold_bits=8, waves_per_wg=4, wg_per_cu=1),
+]
+
+
+@pytest.mark.parametrize("tuning", DNA_TUNINGS, ids=_tid)
+def test_dna_tuning_points(tuning):
     wl = workloads.c3_dna(n_text=(1 << 20) + 5, k=20_000, n_plants=2000)
     trie = pf.Trie(wl.patterns)
-    trie.set_tuning(bpl, bits, wpc)
+    trie.set_tuning(**tuning)
     st = trie.stats()
-    say(f"dna bpl={bpl} bits={bits} wpc={wpc} K={st['index_depth']} b={st['symbol_bits']}")
+    say(f"dna {tuning} K={st['index_depth']} b={st['symbol_bits']}")
     got, counts = gpu_scan(trie, wl.text)
     want = oracle.bucketed(wl.text, wl.patterns, threads=8)
     assert want.n >= 1800
