@@ -71,7 +71,7 @@ struct pfac_trie {
 };
 
 struct pfac_workspace {
-    DeviceBuf stage, unit_count, unit_off, blocksum, tile_first, misc;
+    DeviceBuf stage, unit_count, unit_off, blocksum, tile_first, inline_stage, misc;
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // optional kernel timing
     // misc: [0] stage cursor, [1] running total, [2] per-launch count
     unsigned long long *cursor() { return (unsigned long long *)misc.p; }
@@ -114,7 +114,8 @@ static int upload_image(pfac_trie *t) {
     size_t o_sym = align256(o_lvl + std::max<size_t>(I.lvl.size(), 2) * 4);
     size_t o_ftab = align256(o_sym + 256);
     size_t o_root = align256(o_ftab + std::max<size_t>(I.ftab.size(), 16));
-    size_t total = align256(o_root + std::max<size_t>(I.root_bits.size(), 1) * 4);
+    size_t o_chain = align256(o_root + std::max<size_t>(I.root_bits.size(), 1) * 4);
+    size_t total = align256(o_chain + std::max<size_t>(I.chain.size(), 64));
     auto t0 = std::chrono::steady_clock::now();
     t->dev.release();
     HIP_TRY(t->dev.reserve(total));
@@ -128,6 +129,8 @@ static int upload_image(pfac_trie *t) {
     HIP_TRY(hipMemcpy(b + o_sym, I.sym.data(), 256, hipMemcpyHostToDevice));
     if (!I.ftab.empty())
         HIP_TRY(hipMemcpy(b + o_ftab, I.ftab.data(), I.ftab.size(), hipMemcpyHostToDevice));
+    if (!I.chain.empty())
+        HIP_TRY(hipMemcpy(b + o_chain, I.chain.data(), I.chain.size(), hipMemcpyHostToDevice));
     if (!I.root_bits.empty())
         HIP_TRY(hipMemcpy(b + o_root, I.root_bits.data(), I.root_bits.size() * 4, hipMemcpyHostToDevice));
     ImageView &v = t->view;
@@ -139,6 +142,7 @@ static int upload_image(pfac_trie *t) {
     v.sym = b + o_sym;
     v.ftab = b + o_ftab;
     v.root_bits = (const uint32_t *)(b + o_root);
+    v.chain = b + o_chain;
     v.fold_syms = I.fold_syms;
     v.K = I.K;
     v.b = I.b;
@@ -350,6 +354,7 @@ extern "C" void pfac_workspace_free(pfac_workspace *w) {
     w->unit_off.release();
     w->blocksum.release();
     w->tile_first.release();
+    w->inline_stage.release();
     w->misc.release();
     delete w;
 }
@@ -361,6 +366,7 @@ static int ws_reserve(pfac_workspace *w, uint64_t n_tiles, uint64_t capacity) {
     HIP_TRY(w->tile_first.reserve(std::max<uint64_t>(n_tiles, 1) * 4));
     HIP_TRY(w->blocksum.reserve(n_blocks * 8));
     HIP_TRY(w->stage.reserve(std::max<uint64_t>(capacity, 1) * sizeof(pfac_match)));
+    HIP_TRY(w->inline_stage.reserve(std::max<uint64_t>(n_tiles, 1) * kInlineCap * sizeof(pfac_match)));
     return PFAC_OK;
 }
 
@@ -475,6 +481,8 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     a.unit_off = (unsigned long long *)w->unit_off.p;
     a.blocksum = (unsigned long long *)w->blocksum.p;
     a.counts = L.counts;
+    a.inline_stage = (pfac_match *)w->inline_stage.p;
+    a.inline_cap = wave_kernel ? kInlineCap : 0;
     if (a.lds_total > t->lds_limit) return PFAC_EINVAL;
 
     HIP_TRY(launch_reset(a.stage_cursor, a.blocksum, n_blocks, L.s));
@@ -519,6 +527,8 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     f.capacity = L.out ? L.capacity : 0;
     f.n_matches = L.n_matches;
     f.base_dev = L.base_dev;
+    f.inline_stage = a.inline_stage;
+    f.inline_cap = a.inline_cap;
     HIP_TRY(launch_finish(f, L.s));
     return PFAC_OK;
 }

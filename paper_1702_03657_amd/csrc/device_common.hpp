@@ -10,6 +10,10 @@ namespace pfac {
 
 constexpr uint32_t kNoneD = 0xffffffffu;
 constexpr uint32_t kTermFlagD = 1u << 16;
+constexpr uint32_t kSkipFlagD = 1u << 17;
+constexpr uint32_t kSkipShiftD = 18;
+constexpr uint32_t kCountShiftD = 18;
+constexpr uint32_t kCountEscD = (1u << 14) - 1;
 
 // ------------------------------------------------------------- wave helpers
 
@@ -60,17 +64,72 @@ struct Tile {
     uint64_t next_bnd;        // first boundary at or after the window end
 };
 
-// Walk from node v at depth d for the start position at window offset pl;
-// returns the deepest terminal node passed (kNoneD if none).
-__device__ __forceinline__ uint32_t walk(const ImageView &im, const uint8_t *gbase,
-                                         const Tile &T, uint32_t pl, uint32_t v, uint32_t d) {
-    uint32_t vt = kNoneD;
+// True when text[q .. q+len) (LDS window) equals chain[o .. o+len) (global).
+// Both sides are read as aligned words and realigned with alignbyte; eight
+// chain words are requested before any is compared, so a run costs about one
+// memory round trip per 32 bytes.
+__device__ __forceinline__ bool chain_equal(const uint8_t *text, uint32_t q, const uint8_t *chain,
+                                            uint32_t o, uint32_t len) {
+    const uint32_t *t32 = (const uint32_t *)text;
+    const uint32_t *c32 = (const uint32_t *)chain;
+    uint32_t diff = 0;
+    for (uint32_t i = 0; i < len; i += 32) {
+        uint32_t cw[9], tw[9];
+        const uint32_t cb = (o + i) >> 2, tb = (q + i) >> 2;
+#pragma unroll
+        for (int k = 0; k < 9; k++) cw[k] = c32[cb + k];
+#pragma unroll
+        for (int k = 0; k < 9; k++) tw[k] = t32[tb + k];
+        const uint32_t cs = (o + i) & 3, ts = (q + i) & 3;
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const uint32_t rem = len - i - 4 * k;  // may wrap: masked below
+            const int32_t r = (int32_t)(len - i) - 4 * k;
+            const uint32_t mask = r >= 4 ? 0xffffffffu : (r <= 0 ? 0u : ((1u << (8 * rem)) - 1u));
+            const uint32_t c = __builtin_amdgcn_alignbyte(cw[k + 1], cw[k], cs);
+            const uint32_t t = __builtin_amdgcn_alignbyte(tw[k + 1], tw[k], ts);
+            diff |= (c ^ t) & mask;
+        }
+    }
+    return diff == 0;
+}
+
+// True when no boundary bit is set in [a, b) of the window bit map.
+__device__ __forceinline__ bool range_clear(const uint32_t *bnd, uint32_t a, uint32_t b) {
+    uint32_t any = 0;
+    for (uint32_t w = a >> 5; w <= ((b - 1) >> 5) && a < b; w++) {
+        uint32_t m = 0xffffffffu;
+        if (w == (a >> 5)) m &= 0xffffffffu << (a & 31);
+        if (w == ((b - 1) >> 5)) m &= 0xffffffffu >> (31 - ((b - 1) & 31));
+        any |= bnd[w] & m;
+    }
+    return any == 0;
+}
+
+// Walk from node v at depth d for the start position at window offset pl.
+// Returns the pattern list of the deepest terminal node passed as
+// (offset, stored length); length 0 means no pattern ends on the walk.
+__device__ __forceinline__ uint2 walk(const ImageView &im, const uint8_t *gbase,
+                                      const Tile &T, uint32_t pl, uint32_t v, uint32_t d) {
+    uint2 hit = make_uint2(0, 0);
     for (;;) {
         const uint4 r = im.node[v];
-        if (r.z & kTermFlagD) vt = v;
+        if (r.z & kTermFlagD) hit = make_uint2(r.w, r.z >> kCountShiftD);
         const uint32_t nc = r.z & 0xffffu;
         if (nc == 0) break;
         const uint32_t q = pl + d;
+        const bool skip = (r.z & kSkipFlagD) != 0;
+        if (skip) {
+            // compressed run: compare its labels with the text in bulk when
+            // they lie in the window and no text boundary falls inside them
+            const uint32_t len = r.z >> kSkipShiftD;
+            if (q + len <= T.win && (!T.dirty || range_clear(T.bnd, q + (d == 0), q + len))) {
+                if (!chain_equal(T.text, q, im.chain, r.x, len)) break;
+                v = r.w;
+                d += len;
+                continue;
+            }
+        }
         uint32_t c;
         if (q < T.win) {
             // a boundary at q > pl starts the next text; at q == pl it starts this one
@@ -82,7 +141,10 @@ __device__ __forceinline__ uint32_t walk(const ImageView &im, const uint8_t *gba
             c = gbase[g];
         }
         uint32_t j;
-        if (nc <= 4) {
+        if (skip) {
+            if (c != im.label[r.y - 1]) break;
+            j = 0;
+        } else if (nc <= 4) {
             const uint32_t x = r.x ^ (c * 0x01010101u);
             const uint32_t m = (x - 0x01010101u) & ~x & 0x80808080u;  // lowest flag = first zero byte
             if (m == 0) break;
@@ -101,7 +163,7 @@ __device__ __forceinline__ uint32_t walk(const ImageView &im, const uint8_t *gba
         v = r.y + j;
         d++;
     }
-    return vt;
+    return hit;
 }
 
 // Text holding frame position g (batch), by binary search over the starts.
@@ -115,16 +177,18 @@ __device__ __forceinline__ uint32_t text_of(const uint64_t *offsets, uint32_t n_
     return lo;
 }
 
-__device__ __forceinline__ uint32_t pout_count(const ImageView &im, uint32_t vt) {
-    const uint32_t o = im.node[vt].w;
-    return im.pout_ptr[o + 1] - im.pout_ptr[o];
+// (first id offset, number of ids) of a walk's pattern list.
+__device__ __forceinline__ uint2 hit_list(const ImageView &im, uint2 h) {
+    if (h.y == kCountEscD) return make_uint2(h.x + 1, im.pout_ids[h.x]);
+    return h;
 }
 
-__device__ __forceinline__ void emit(const ScanArgs &a, uint64_t frame_pos, uint32_t vt,
-                                     uint64_t dst) {
+// Write the matches of one start position (frame position `frame_pos`, the
+// pattern list `ids` = (offset, count)) to dst[idx ..], dropping records at
+// or beyond `cap`; also its per-position count when requested.
+__device__ __forceinline__ void emit(const ScanArgs &a, uint64_t frame_pos, uint2 ids,
+                                     pfac_match *dst, uint64_t idx, uint64_t cap) {
     const ImageView &im = a.im;
-    const uint32_t o = im.node[vt].w;
-    const uint32_t p0 = im.pout_ptr[o], p1 = im.pout_ptr[o + 1];
     uint32_t tid = 0;
     uint64_t start = a.shift;
     if (a.offsets) {
@@ -133,16 +197,16 @@ __device__ __forceinline__ void emit(const ScanArgs &a, uint64_t frame_pos, uint
     }
     tid += a.text_id0;
     const uint64_t pos = frame_pos - start;
-    for (uint32_t k = p0; k < p1; k++, dst++) {
-        if (dst < a.stage_cap) {
+    for (uint32_t k = 0; k < ids.y; k++, idx++) {
+        if (idx < cap) {
             pfac_match m;
             m.pos = pos;
-            m.pattern_id = im.pout_ids[k];
+            m.pattern_id = im.pout_ids[ids.x + k];
             m.text_id = tid;
-            a.stage[dst] = m;
+            dst[idx] = m;
         }
     }
-    if (a.counts) a.counts[frame_pos - a.shift] = p1 - p0;
+    if (a.counts) a.counts[frame_pos - a.shift] = ids.y;
 }
 
 }  // namespace pfac

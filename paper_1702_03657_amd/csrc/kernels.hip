@@ -212,10 +212,10 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
                 v = im.lvl_start + s_rank[code >> 5] + (uint32_t)__builtin_popcount(below);
                 d = K;
             }
-            const uint32_t vt = walk(im, a.base, T, pl, v, d);
-            if (vt != kNoneD) {
+            const uint2 h = walk(im, a.base, T, pl, v, d);
+            if (h.y) {
                 const uint32_t slot = atomicAdd(&s_mn, 1u);
-                if (slot < kMatchCap) s_match[slot] = make_uint2(pl, vt);
+                if (slot < kMatchCap) s_match[slot] = make_uint2(pl | (h.y << 16), h.x);
             }
         }
         __syncthreads();
@@ -234,14 +234,15 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
             for (uint32_t i = tid; i < mn; i += kWG) {
                 const uint2 e = s_match[i];
                 uint32_t rk = 0;
-                for (uint32_t q = 0; q < mn; q++) rk += s_match[q].x < e.x;
+                for (uint32_t q = 0; q < mn; q++) rk += (s_match[q].x & 0xffffu) < (e.x & 0xffffu);
                 sorted[rk] = e;
             }
             __syncthreads();
             const uint32_t per = (mn + kWG - 1) / kWG;
             const uint32_t i0 = min(tid * per, mn), i1 = min(i0 + per, mn);
             uint32_t mine = 0;
-            for (uint32_t i = i0; i < i1; i++) mine += pout_count(im, sorted[i].y);
+            for (uint32_t i = i0; i < i1; i++)
+                mine += hit_list(im, make_uint2(sorted[i].y, sorted[i].x >> 16)).y;
             uint32_t total;
             const uint32_t before = block_excl_scan(mine, s_tmp, total);
             if (tid == 0) {
@@ -255,8 +256,9 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
             uint64_t dst = s_base + before;
             for (uint32_t i = i0; i < i1; i++) {
                 const uint2 e = sorted[i];
-                emit(a, tile_lo + e.x, e.y, dst);
-                dst += pout_count(im, e.y);
+                const uint2 ids = hit_list(im, make_uint2(e.y, e.x >> 16));
+                emit(a, tile_lo + (e.x & 0xffffu), ids, a.stage, dst, a.stage_cap);
+                dst += ids.y;
             }
         } else {
             // Too many matched positions to sort in LDS: walk the tile again
@@ -266,8 +268,8 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
                 const uint32_t pl = r * kWG + tid;
                 const uint64_t p = tile_lo + pl;
                 if (p < lo_valid || p >= hi_valid) continue;
-                const uint32_t vt = walk(im, a.base, T, pl, 0, 0);
-                if (vt != kNoneD) mine += pout_count(im, vt);
+                const uint2 h = walk(im, a.base, T, pl, 0, 0);
+                if (h.y) mine += hit_list(im, h).y;
             }
             uint32_t total;
             block_excl_scan(mine, s_tmp, total);
@@ -283,14 +285,15 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
             for (uint32_t r = 0; r < BPL; r++) {
                 const uint32_t pl = r * kWG + tid;
                 const uint64_t p = tile_lo + pl;
-                uint32_t vt = kNoneD, c = 0;
+                uint2 ids = make_uint2(0, 0);
                 if (p >= lo_valid && p < hi_valid) {
-                    vt = walk(im, a.base, T, pl, 0, 0);
-                    if (vt != kNoneD) c = pout_count(im, vt);
+                    const uint2 h = walk(im, a.base, T, pl, 0, 0);
+                    if (h.y) ids = hit_list(im, h);
                 }
+                const uint32_t c = ids.y;
                 uint32_t round_total;
                 const uint32_t before = block_excl_scan(c, s_tmp, round_total);
-                if (c) emit(a, p, vt, run_off + before);
+                if (c) emit(a, p, ids, a.stage, run_off + before, a.stage_cap);
                 run_off += round_total;
             }
         }
@@ -340,9 +343,14 @@ __global__ __launch_bounds__(kWG) void finish_tiles(const FinishArgs f) {
     for (uint32_t i = 0; i < PER; i++) {
         if (cnt[i]) {
             const uint64_t src = f.unit_off[t0 + i];
-            if (src + cnt[i] <= f.stage_cap)
+            const pfac_match *from = nullptr;
+            if (src == ~0ull)
+                from = f.inline_stage + (t0 + i) * f.inline_cap;
+            else if (src + cnt[i] <= f.stage_cap)
+                from = f.stage + src;
+            if (from)
                 for (uint32_t k = 0; k < cnt[i]; k++)
-                    if (off + k < f.capacity) f.out[off + k] = f.stage[src + k];
+                    if (off + k < f.capacity) f.out[off + k] = from[k];
             off += cnt[i];
         }
     }

@@ -13,6 +13,7 @@ constexpr uint32_t kWG = 256;            // threads per workgroup (4 waves of 64
 constexpr uint32_t kMatchCap = 256;      // matched positions a tile sorts in LDS
 constexpr uint32_t kTpbShift = 10;       // tiles per block-sum entry = 1024
 constexpr uint32_t kHaloCap = 1024;      // most halo bytes staged in LDS
+constexpr uint32_t kInlineCap = 4;       // records a wave chunk stages without an atomic
 
 // Device image as the kernels see it (pointers into one device allocation).
 struct ImageView {
@@ -24,6 +25,7 @@ struct ImageView {
     const uint8_t *sym;       // 256
     const uint8_t *ftab;      // prefix filter: folded child bitmaps of depth-K nodes
     const uint32_t *root_bits;  // codes of the root's children
+    const uint8_t *chain;     // labels of compressed single-child runs
     uint32_t K, b, identity, lvl_words;
     uint32_t lvl_start, max_len, n_nodes, fold_syms;
 };
@@ -54,6 +56,8 @@ struct ScanArgs {
     unsigned long long *unit_off;     // per tile
     unsigned long long *blocksum;     // per 1 << kTpbShift tiles
     uint32_t *counts;                 // optional per-position counts
+    pfac_match *inline_stage;         // wave kernel: inline_cap records per chunk
+    uint64_t inline_cap;
 };
 
 struct FinishArgs {
@@ -68,6 +72,8 @@ struct FinishArgs {
     uint64_t capacity;
     uint64_t *n_matches;              // receives this launch's match count
     const unsigned long long *base_dev;  // optional device value added to every output index
+    const pfac_match *inline_stage;   // units with unit_off == ~0 keep their records here
+    uint64_t inline_cap;
 };
 
 // LDS bytes and section offsets for a tile of `bpl` bytes per lane.

@@ -54,48 +54,65 @@ __device__ __forceinline__ uint32_t wbyte(const uint32_t *w, int j) {
     return (w[j >> 2] >> (8 * (j & 3))) & 0xffu;
 }
 
-// Stage the matches of one chunk: sort by position, count, reserve, write.
+// Stage the matches of one chunk in (pos, id) order.  wm[i] = (window
+// position | stored list length << 16, list offset).  A chunk with at most
+// inline_cap records writes them to its own inline slots (no atomic with a
+// return value); larger ones reserve staging space with one atomic.
 __device__ __forceinline__ void emit_chunk(const ScanArgs &a, uint64_t c, uint64_t chunk_lo,
                                            uint2 *wm, uint32_t mn, uint2 *sorted) {
     const ImageView &im = a.im;
     const uint32_t lane = lane_id();
     if (mn == 0) {
-        if (lane == 0) {
-            a.unit_count[c] = 0;
-            a.unit_off[c] = 0;
-        }
+        if (lane == 0) a.unit_count[c] = 0;
         return;
     }
     for (uint32_t i = lane; i < mn; i += 64) {
         const uint2 e = wm[i];
         uint32_t rk = 0;
-        for (uint32_t q = 0; q < mn; q++) rk += wm[q].x < e.x;
+        for (uint32_t q = 0; q < mn; q++) rk += (wm[q].x & 0xffffu) < (e.x & 0xffffu);
         sorted[rk] = e;
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    uint32_t cnt[2], off[2], total = 0;
+    uint2 ids[2];
+    uint32_t off[2], total = 0;
 #pragma unroll
     for (int r = 0; r < 2; r++) {
         const uint32_t i = lane + 64u * r;
-        cnt[r] = i < mn ? pout_count(im, sorted[i].y) : 0u;
+        ids[r] = make_uint2(0, 0);
+        if (i < mn) ids[r] = hit_list(im, make_uint2(sorted[i].y, sorted[i].x >> 16));
         uint32_t t;
-        off[r] = total + wave_excl_scan(cnt[r], t);
+        off[r] = total + wave_excl_scan(ids[r].y, t);
         total += t;
     }
-    unsigned long long base = 0;
-    if (lane == 0) {
-        base = atomicAdd(a.stage_cursor, (unsigned long long)total);
-        a.unit_count[c] = total;
-        a.unit_off[c] = base;
-        atomicAdd(&a.blocksum[c >> kTpbShift], (unsigned long long)total);
+    pfac_match *dst;
+    uint64_t base, cap;
+    if (total <= a.inline_cap) {
+        dst = a.inline_stage + c * a.inline_cap;
+        base = 0;
+        cap = a.inline_cap;
+        if (lane == 0) {
+            a.unit_count[c] = total;
+            a.unit_off[c] = ~0ull;
+            atomicAdd(&a.blocksum[c >> kTpbShift], (unsigned long long)total);
+        }
+    } else {
+        unsigned long long b = 0;
+        if (lane == 0) {
+            b = atomicAdd(a.stage_cursor, (unsigned long long)total);
+            a.unit_count[c] = total;
+            a.unit_off[c] = b;
+            atomicAdd(&a.blocksum[c >> kTpbShift], (unsigned long long)total);
+        }
+        base = __shfl(b, 0, 64);
+        dst = a.stage;
+        cap = a.stage_cap;
     }
-    base = __shfl(base, 0, 64);
 #pragma unroll
     for (int r = 0; r < 2; r++) {
         const uint32_t i = lane + 64u * r;
-        if (i < mn) emit(a, chunk_lo + sorted[i].x, sorted[i].y, base + off[r]);
+        if (i < mn) emit(a, chunk_lo + (sorted[i].x & 0xffffu), ids[r], dst, base + off[r], cap);
     }
 }
 
@@ -110,8 +127,8 @@ __device__ __forceinline__ void chunk_from_root(const ScanArgs &a, const Tile &T
         const uint64_t p = T.lo + pl;
         uint32_t cnt = 0;
         if (p >= lo_valid && p < hi_valid) {
-            const uint32_t vt = walk(im, a.base, T, pl, 0, 0);
-            if (vt != kNoneD) cnt = pout_count(im, vt);
+            const uint2 h = walk(im, a.base, T, pl, 0, 0);
+            if (h.y) cnt = hit_list(im, h).y;
         }
         uint32_t t;
         wave_excl_scan(cnt, t);
@@ -128,14 +145,14 @@ __device__ __forceinline__ void chunk_from_root(const ScanArgs &a, const Tile &T
     for (uint32_t r = 0; r < kChunk / 64; r++) {
         const uint32_t pl = r * 64 + lane;
         const uint64_t p = T.lo + pl;
-        uint32_t cnt = 0, vt = kNoneD;
+        uint2 ids = make_uint2(0, 0);
         if (p >= lo_valid && p < hi_valid) {
-            vt = walk(im, a.base, T, pl, 0, 0);
-            if (vt != kNoneD) cnt = pout_count(im, vt);
+            const uint2 h = walk(im, a.base, T, pl, 0, 0);
+            if (h.y) ids = hit_list(im, h);
         }
         uint32_t t;
-        const uint32_t before = wave_excl_scan(cnt, t);
-        if (cnt) emit(a, p, vt, base + before);
+        const uint32_t before = wave_excl_scan(ids.y, t);
+        if (ids.y) emit(a, p, ids, a.stage, base + before, a.stage_cap);
         base += t;
     }
 }
@@ -294,7 +311,8 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             const uint32_t m = (K >= 1 && a.fold) ? im.fold_syms : 0u;
             const uint32_t L = K >= 1 ? K + m : 1u;
             const uint32_t full_mask = (b * L >= 32) ? 0xffffffffu : ((1u << (b * L)) - 1u);
-            const uint32_t fmask = a.fold - 1u;
+            // the folded bit reads only the last m symbols of the window
+            const uint32_t fmask = (a.fold - 1u) & ((b * m >= 32) ? 0xffffffffu : ((1u << (b * m)) - 1u));
             uint32_t full = 0, run = 0;
 #pragma unroll
             for (int j = 0; j < 31; j++) {
@@ -338,12 +356,19 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         if (!overflow) {
             for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
                 const uint32_t e = r0 + lane;
-                uint32_t vt = kNoneD, pl = 0;
+                uint2 h = make_uint2(0, 0);
+                uint32_t pl = 0;
                 if (e < qn) {
                     const uint32_t ent = wq[e];
                     pl = ent >> 20;
                     const uint64_t p = chunk_lo + pl;
-                    if (p >= lo_valid && p < hi_valid) {
+                    // the filter read K symbols without looking at text
+                    // boundaries: none may start inside them
+                    bool crosses = false;
+                    if (dirty)
+                        for (uint32_t q = pl + 1; q < pl + K; q++)
+                            crosses = crosses || ((wbnd[q >> 5] >> (q & 31)) & 1u);
+                    if (p >= lo_valid && p < hi_valid && !crosses) {
                         uint32_t v = 0, d = 0;
                         if (K) {
                             const uint32_t code = ent & 0xfffffu;
@@ -352,14 +377,14 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                             v = im.lvl_start + s_rank[code >> 5] + (uint32_t)__builtin_popcount(below);
                             d = K;
                         }
-                        vt = walk(im, a.base, T, pl, v, d);
+                        h = walk(im, a.base, T, pl, v, d);
                     }
                 }
-                const bool got = vt != kNoneD;
+                const bool got = h.y != 0;
                 const unsigned long long mk = __ballot(got);
                 if (got) {
                     const uint32_t slot = mn + mbcnt(mk);
-                    if (slot < mcap) wm[slot] = make_uint2(pl, vt);
+                    if (slot < mcap) wm[slot] = make_uint2(pl | (h.y << 16), h.x);
                 }
                 mn += (uint32_t)__popcll(mk);
             }

@@ -10,6 +10,11 @@ namespace pfac {
 constexpr uint32_t kNone = 0xffffffffu;
 constexpr uint32_t kTermFlag = 1u << 16;   // node record .z: terminal node
 constexpr uint32_t kNcMask = 0xffffu;      // node record .z: number of children
+constexpr uint32_t kSkipFlag = 1u << 17;   // node record .z: compressed single-child run
+constexpr uint32_t kSkipShift = 18;        // node record .z: run length above this bit
+constexpr uint32_t kSkipMax = (1u << 14) - 1;
+constexpr uint32_t kCountShift = 18;       // terminal record .z: pattern-list length above this bit
+constexpr uint32_t kCountEsc = (1u << 14) - 1;  // length stored before the list
 
 // The CRS trie of Design and Implementation.  Nodes are numbered breadth first
 // (step I), level by level, with children by ascending unsigned label, so the
@@ -40,15 +45,14 @@ bool build_crs(const uint8_t *data, const uint64_t *off, uint32_t k, CrsTrie &ou
 struct DeviceImageHost {
     // Per node, 16 bytes: x = labels of the first four children (byte j =
     // label j), y = first child node id (children are y .. y+nc-1),
-    // z = nc | kTermFlag, w = terminal ordinal or kNone.
+    // z = nc | kTermFlag | list length << kCountShift, w = offset of the
+    // node's pattern list in pout_ids (terminal nodes).  Skip nodes use
+    // x = chain offset, z = 1 | kSkipFlag | run length << kSkipShift,
+    // w = node reached after the run.
     std::vector<uint32_t> node;        // 4 * N
     std::vector<uint8_t> label;        // N - 1 (a copy of the CRS labels, padded)
-    // For each terminal node t (in breadth-first order) the ascending ids of
-    // every pattern that ends on its root path: pout_ids[pout_ptr[t] ..
-    // pout_ptr[t+1]).  A walk reports the list of the deepest terminal node it
-    // passed, which is the union of the term lists of all terminal nodes on
-    // the way, already sorted.
-    std::vector<uint32_t> pout_ptr;    // T + 1
+    std::vector<uint8_t> chain;        // labels of single-child runs (skip nodes)
+    std::vector<uint32_t> pout_ptr;    // unused (kept empty)
     std::vector<uint32_t> pout_ids;
     // Level index: the depth-K nodes as a bitmap over K-symbol codes, with
     // the number of set bits before each 32-bit word.  Breadth-first order

@@ -111,36 +111,92 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
         I.node[4 * v + 0] = x;
         I.node[4 * v + 1] = e0 + 1;
         I.node[4 * v + 2] = nc | (ord_of[v] != kNone ? kTermFlag : 0);
-        I.node[4 * v + 3] = ord_of[v];
+        I.node[4 * v + 3] = kNone;
     }
     I.label = T.labels;
     if (I.label.empty()) I.label.push_back(0);
 
-    // root-path pattern lists of terminal nodes
+    // Path compression for the walk: a maximal run u_0 -> u_1 -> ... -> u_s
+    // of non-terminal single-child nodes ending at w = u_s stores its labels
+    // once in `chain`; every u_i with at least two labels left becomes a skip
+    // node (x = offset of its remaining labels, z = 1 | kSkipFlag | len << 18,
+    // w = the node reached after len labels).  No pattern ends strictly
+    // inside the run, so comparing the text with the stored labels in bulk
+    // reaches the same node as walking them one by one, and a mismatch ends
+    // the walk with nothing reported.
+    {
+        std::vector<uint32_t> parent0(N, kNone);
+        for (uint32_t v = 0; v < N; v++)
+            for (uint32_t e = T.row_ptr[v]; e < T.row_ptr[v + 1]; e++) parent0[e + 1] = v;
+        auto chain_node = [&](uint32_t v) {
+            return T.row_ptr[v + 1] - T.row_ptr[v] == 1 && T.term_ptr[v + 1] == T.term_ptr[v];
+        };
+        std::vector<uint32_t> run;
+        for (uint32_t v = 0; v < N; v++) {
+            if (!chain_node(v)) continue;
+            if (v != 0 && chain_node(parent0[v])) continue;  // not the top of its run
+            run.assign(1, v);
+            const uint32_t off0 = (uint32_t)I.chain.size();
+            uint32_t u = v;
+            while (chain_node(u)) {
+                const uint32_t e = T.row_ptr[u];
+                I.chain.push_back(T.labels[e]);
+                u = e + 1;
+                run.push_back(u);
+            }
+            const uint32_t s = (uint32_t)run.size() - 1;
+            for (uint32_t i = 0; i + 2 <= s; i++) {
+                const uint32_t len = std::min(s - i, kSkipMax);
+                uint32_t *rec = &I.node[4ull * run[i]];
+                rec[0] = off0 + i;
+                rec[2] = 1u | kSkipFlag | (len << kSkipShift);
+                rec[3] = run[i + len];
+            }
+        }
+        I.chain.resize(I.chain.size() + 40, 0);  // the kernels read whole words past the end
+    }
+
+    // Root-path pattern lists of terminal nodes: for a terminal node t, the
+    // ascending ids of every pattern that ends on the path from the root to t
+    // (t's own ids merged with the list of its nearest terminal ancestor).  A
+    // walk reports the list of the deepest terminal node it passed.  The
+    // record of t holds the list's offset (w) and length (z bits 18..31); a
+    // length of kCountEsc or more is stored as kCountEsc and the true length
+    // precedes the ids.
     std::vector<uint32_t> parent(N, kNone), near_term(N, kNone);
     for (uint32_t v = 0; v < N; v++)
         for (uint32_t e = T.row_ptr[v]; e < T.row_ptr[v + 1]; e++) parent[e + 1] = v;
-    I.pout_ptr.assign(I.n_term + 1, 0);
+    std::vector<uint32_t> list_at(N, kNone), list_len(N, 0);
     std::vector<uint32_t> tmp;
     for (uint32_t v = 1; v < N; v++) {
-        uint32_t up = near_term[parent[v]];
+        const uint32_t up = near_term[parent[v]];
         if (ord_of[v] == kNone) { near_term[v] = up; continue; }
         near_term[v] = v;
-        tmp.clear();
         const uint32_t *own = T.term_ids.data() + T.term_ptr[v];
-        uint32_t n_own = T.term_ptr[v + 1] - T.term_ptr[v];
+        const uint32_t n_own = T.term_ptr[v + 1] - T.term_ptr[v];
+        tmp.clear();
         if (up != kNone) {
-            uint32_t o = ord_of[up];
-            const uint32_t *anc = I.pout_ids.data() + I.pout_ptr[o];
-            uint32_t n_anc = I.pout_ptr[o + 1] - I.pout_ptr[o];
+            const uint32_t *anc = I.pout_ids.data() + list_at[up];
+            const uint32_t n_anc = list_len[up];
             tmp.resize(n_own + n_anc);
             std::merge(own, own + n_own, anc, anc + n_anc, tmp.begin());
         } else {
             tmp.assign(own, own + n_own);
         }
+        const uint32_t n = (uint32_t)tmp.size();
+        uint32_t *rec = &I.node[4ull * v];
+        rec[3] = (uint32_t)I.pout_ids.size();
+        if (n >= kCountEsc) {
+            I.pout_ids.push_back(n);
+            rec[2] |= kCountEsc << kCountShift;
+        } else {
+            rec[2] |= n << kCountShift;
+        }
+        list_at[v] = (uint32_t)I.pout_ids.size();
+        list_len[v] = n;
         I.pout_ids.insert(I.pout_ids.end(), tmp.begin(), tmp.end());
-        I.pout_ptr[ord_of[v] + 1] = (uint32_t)I.pout_ids.size();
     }
+    I.pout_ptr.assign(1, 0);
     if (I.pout_ids.empty()) I.pout_ids.push_back(0);
 
     // alphabet and level index
