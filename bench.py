@@ -183,7 +183,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--retune", action="store_true", help="ignore the cached autotune choice")
     ap.add_argument("--tuning", default=None,
-                    help="kernel,bytes_per_lane,index_bits,fold_bits,wg_per_cu,waves_per_wg")
+                    help="kernel,bytes_per_lane,index_bits,fold_bits,wg_per_cu,waves_per_wg,chunks_per_unit,child_check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--extras", action="store_true", help="add batched-vs-plain (c4)")
@@ -228,7 +228,8 @@ def main():
     h2d_ms = h0.elapsed_time(h1)
 
     if args.tuning:
-        names = ["kernel", "bytes_per_lane", "index_bits", "fold_bits", "wg_per_cu", "waves_per_wg"]
+        names = ["kernel", "bytes_per_lane", "index_bits", "fold_bits", "wg_per_cu", "waves_per_wg",
+                 "chunks_per_unit", "child_check"]
         trie.set_tuning(**dict(zip(names, (int(x) for x in args.tuning.split(",")))))
         tuning, tuned_now = trie.tuning(), False
     else:

@@ -91,7 +91,11 @@ typedef struct {
     uint32_t index_bits;       /* level-index width in bits (1..18); depth K = bits / symbol_bits */
     uint32_t fold_bits;        /* wave kernel prefix filter: 0 (level bitmap), 8 or 16 bits per node */
     uint32_t wg_per_cu;        /* resident workgroups per compute unit (0 = occupancy max) */
-    uint32_t waves_per_wg;     /* wave kernel: 4, 8 or 16 waves per workgroup */
+    uint32_t waves_per_wg;     /* wave kernel: 4, 8, 12 or 16 waves per workgroup (fewer when
+                                  the LDS tables leave no room) */
+    uint32_t chunks_per_unit;  /* wave kernel: 1 KiB chunks per output unit, 1..64 */
+    uint32_t child_check;      /* wave kernel: 1 = check the byte after the level index against
+                                  the depth-K node's child labels in LDS when they fit */
 } pfac_tuning;
 
 /* ----------------------------------------------------------------- errors */

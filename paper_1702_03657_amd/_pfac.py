@@ -56,7 +56,8 @@ class pfac_stats(ctypes.Structure):
 class pfac_tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_uint32), ("bytes_per_lane", ctypes.c_uint32),
                 ("index_bits", ctypes.c_uint32), ("fold_bits", ctypes.c_uint32),
-                ("wg_per_cu", ctypes.c_uint32), ("waves_per_wg", ctypes.c_uint32)]
+                ("wg_per_cu", ctypes.c_uint32), ("waves_per_wg", ctypes.c_uint32),
+                ("chunks_per_unit", ctypes.c_uint32), ("child_check", ctypes.c_uint32)]
 
 
 class PfacError(RuntimeError):
@@ -229,8 +230,9 @@ class Trie:
         return {n: getattr(t, n) for n, _ in t._fields_}
 
     def set_tuning(self, kernel=1, bytes_per_lane=16, index_bits=16, fold_bits=8, wg_per_cu=0,
-                   waves_per_wg=16):
-        t = pfac_tuning(kernel, bytes_per_lane, index_bits, fold_bits, wg_per_cu, waves_per_wg)
+                   waves_per_wg=16, chunks_per_unit=16, child_check=1):
+        t = pfac_tuning(kernel, bytes_per_lane, index_bits, fold_bits, wg_per_cu, waves_per_wg,
+                        chunks_per_unit, child_check)
         check("pfac_trie_set_tuning", load().pfac_trie_set_tuning(self.handle, ctypes.byref(t)))
 
 

@@ -57,7 +57,7 @@ struct DeviceBuf {
 struct pfac_trie {
     CrsTrie crs;
     DeviceImageHost img;
-    pfac_tuning tuning{1, 16, 16, 8, 0, 16};
+    pfac_tuning tuning{1, 16, 16, 8, 0, 16, 16, 1};
     uint32_t lds_limit = 64 * 1024;  // dynamic LDS a workgroup may use
     bool host_only = false;
     int device = -1;
@@ -115,7 +115,8 @@ static int upload_image(pfac_trie *t) {
     size_t o_ftab = align256(o_sym + 256);
     size_t o_root = align256(o_ftab + std::max<size_t>(I.ftab.size(), 16));
     size_t o_chain = align256(o_root + std::max<size_t>(I.root_bits.size(), 1) * 4);
-    size_t total = align256(o_chain + std::max<size_t>(I.chain.size(), 64));
+    size_t o_krec = align256(o_chain + std::max<size_t>(I.chain.size(), 64));
+    size_t total = align256(o_krec + std::max<size_t>(I.krec.size(), 1) * 4);
     auto t0 = std::chrono::steady_clock::now();
     t->dev.release();
     HIP_TRY(t->dev.reserve(total));
@@ -129,6 +130,8 @@ static int upload_image(pfac_trie *t) {
     HIP_TRY(hipMemcpy(b + o_sym, I.sym.data(), 256, hipMemcpyHostToDevice));
     if (!I.ftab.empty())
         HIP_TRY(hipMemcpy(b + o_ftab, I.ftab.data(), I.ftab.size(), hipMemcpyHostToDevice));
+    if (!I.krec.empty())
+        HIP_TRY(hipMemcpy(b + o_krec, I.krec.data(), I.krec.size() * 4, hipMemcpyHostToDevice));
     if (!I.chain.empty())
         HIP_TRY(hipMemcpy(b + o_chain, I.chain.data(), I.chain.size(), hipMemcpyHostToDevice));
     if (!I.root_bits.empty())
@@ -143,6 +146,7 @@ static int upload_image(pfac_trie *t) {
     v.ftab = b + o_ftab;
     v.root_bits = (const uint32_t *)(b + o_root);
     v.chain = b + o_chain;
+    v.krec = (const uint32_t *)(b + o_krec);
     v.fold_syms = I.fold_syms;
     v.K = I.K;
     v.b = I.b;
@@ -239,7 +243,10 @@ extern "C" int pfac_build(const uint8_t *const *patterns, const uint64_t *length
     return build_common(data.data(), off.data(), n_patterns, flags, out);
 }
 
-static ScanArgs layout_for(const pfac_trie *t) {
+// LDS layout of the kernel the tuning asks for.  The wave kernel drops to
+// fewer waves per workgroup, then drops the LDS child records, until its
+// tables and per-wave areas fit.
+static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr) {
     ScanArgs a{};
     a.im = t->view;
     a.im.lvl_words = t->img.lvl_words;
@@ -248,12 +255,22 @@ static ScanArgs layout_for(const pfac_trie *t) {
     a.im.b = t->img.b;
     a.im.fold_syms = t->img.fold_syms;
     a.halo = t->halo;
+    uint32_t waves = t->tuning.waves_per_wg;
     if (t->tuning.kernel == 1) {
         a.fold = t->img.fold_bits;
-        wave_lds_layout(a, t->tuning.waves_per_wg, t->lds_limit);
+        a.group = t->tuning.chunks_per_unit;
+        for (int with_rec = (t->tuning.child_check && t->img.K) ? 1 : 0; with_rec >= 0; with_rec--) {
+            a.krec_words = with_rec ? (uint32_t)t->img.krec.size() : 0u;
+            for (waves = t->tuning.waves_per_wg; waves >= 4; waves -= 4) {
+                wave_lds_layout(a, waves, t->lds_limit);
+                if (a.lds_total <= t->lds_limit) break;
+            }
+            if (a.lds_total <= t->lds_limit) break;
+        }
     } else {
         lds_layout(a, t->tuning.bytes_per_lane);
     }
+    if (waves_out) *waves_out = std::max(4u, waves);
     return a;
 }
 
@@ -312,7 +329,9 @@ static bool valid_tuning(const pfac_tuning *p) {
            (p->bytes_per_lane == 4 || p->bytes_per_lane == 8 || p->bytes_per_lane == 16) &&
            p->index_bits >= 1 && p->index_bits <= 18 &&
            (p->fold_bits == 0 || p->fold_bits == 8 || p->fold_bits == 16) && p->wg_per_cu <= 8 &&
-           (p->waves_per_wg == 4 || p->waves_per_wg == 8 || p->waves_per_wg == 16);
+           (p->waves_per_wg == 4 || p->waves_per_wg == 8 || p->waves_per_wg == 12 ||
+            p->waves_per_wg == 16) &&
+           p->chunks_per_unit >= 1 && p->chunks_per_unit <= 64 && p->child_check <= 1;
 }
 
 extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
@@ -410,7 +429,8 @@ static uint64_t tiles_for(uint64_t total, uint64_t shift, uint32_t tile) {
 static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out);
 
 static uint32_t unit_bytes(const pfac_trie *t) {
-    return use_wave_kernel(t, nullptr) ? kWaveChunk : kWG * t->tuning.bytes_per_lane;
+    return use_wave_kernel(t, nullptr) ? kWaveChunk * t->tuning.chunks_per_unit
+                                       : kWG * t->tuning.bytes_per_lane;
 }
 
 // Opt a kernel into more than 64 KiB of dynamic LDS (once per size).
@@ -430,13 +450,8 @@ static hipError_t prep_wave(int mode, uint32_t bytes) { return prepare_wave_kern
 // Wave kernel when asked for and its LDS layout fits; the tile kernel otherwise.
 static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out) {
     if (t->tuning.kernel != 1) return false;
-    ScanArgs a = layout_for(t);
-    uint32_t waves = t->tuning.waves_per_wg;
-    while (a.lds_total > t->lds_limit && waves > 4) {
-        waves /= 2;
-        wave_lds_layout(a, waves, t->lds_limit);
-    }
-    if (waves_out) *waves_out = waves;
+    if (t->crs.max_len > 0xffff) return false;  // walk limits are 16-bit
+    const ScanArgs a = layout_for(t, waves_out);
     return a.lds_total <= t->lds_limit;
 }
 
@@ -445,27 +460,23 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     uint32_t waves = t->tuning.waves_per_wg;
     const bool wave_kernel = use_wave_kernel(t, &waves);
     const uint32_t bpl = t->tuning.bytes_per_lane;
-    const uint32_t tile = wave_kernel ? kWaveChunk : kWG * bpl;
+    const uint32_t tile = wave_kernel ? kWaveChunk * t->tuning.chunks_per_unit : kWG * bpl;
     const uintptr_t addr = (uintptr_t)L.text;
     const uint64_t shift = addr & 15;
     uint64_t n_tiles = tiles_for(L.total, shift, tile);
     if (t->crs.k == 0) n_tiles = 0;  // nothing can match
+    // the batch plan is per 1 KiB chunk for the wave kernel, per tile otherwise
+    const uint32_t plan_unit = wave_kernel ? kWaveChunk : tile;
+    const uint64_t n_plan = n_tiles ? tiles_for(L.total, shift, plan_unit) : 0;
     if (reserve) {
-        int rc = ws_reserve(L.w, n_tiles, L.capacity);
+        int rc = ws_reserve(L.w, std::max(n_tiles, n_plan), L.capacity);
         if (rc != PFAC_OK) return rc;
     }
     pfac_workspace *w = L.w;
     const uint32_t n_blocks = (uint32_t)std::max<uint64_t>(1, (n_tiles + (1u << kTpbShift) - 1) >> kTpbShift);
 
-    ScanArgs a{};
+    ScanArgs a = layout_for(t, &waves);
     a.im = t->view;
-    a.halo = t->halo;
-    if (wave_kernel) {
-        a.fold = t->img.fold_bits;
-        wave_lds_layout(a, waves, t->lds_limit);
-    } else {
-        lds_layout(a, bpl);
-    }
     a.base = (const uint8_t *)(addr - shift);
     a.shift = shift;
     a.total = L.total;
@@ -489,7 +500,7 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     if (L.counts) HIP_TRY(launch_fill_u32(L.counts, L.total, 0, L.s));
     if (n_tiles) {
         if (L.offsets)
-            HIP_TRY(launch_plan(L.offsets, L.n_texts, shift, n_tiles, tile,
+            HIP_TRY(launch_plan(L.offsets, L.n_texts, shift, n_plan, plan_unit,
                                 (uint32_t *)w->tile_first.p, L.s));
         int per_cu = (int)t->tuning.wg_per_cu;
         int occ;
@@ -589,7 +600,7 @@ extern "C" int pfac_scan_batch_plain(const pfac_trie *t, pfac_workspace *w,
     for (uint32_t i = 0; i < n_texts; i++) {
         if (offsets_host[i + 1] < offsets_host[i]) return PFAC_EINVAL;
         max_tiles = std::max(max_tiles, tiles_for(offsets_host[i + 1] - offsets_host[i], 15,
-                                                  unit_bytes(t)));
+                                                  std::min(unit_bytes(t), kWaveChunk)));
     }
     rc = ws_reserve(w, max_tiles, capacity);
     if (rc) return rc;
@@ -619,7 +630,7 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
     int rc = check_scan_args(t, w, texts_dev, total_bytes, out_dev, capacity, n_matches_dev);
     if (rc) return rc;
     if (!offsets_dev) return PFAC_EINVAL;
-    rc = ws_reserve(w, tiles_for(total_bytes, 15, unit_bytes(t)), capacity);
+    rc = ws_reserve(w, tiles_for(total_bytes, 15, std::min(unit_bytes(t), kWaveChunk)), capacity);
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     hipStream_t own = nullptr;
@@ -725,8 +736,10 @@ extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *tex
     std::vector<pfac_tuning> cands;
     for (uint32_t bits : {12u, 16u, 18u}) {
         for (uint32_t fold : {8u, 16u, 0u})
-            for (uint32_t waves : {8u, 16u}) cands.push_back({1, 16, bits, fold, 0, waves});
-        for (uint32_t bpl : {8u, 16u}) cands.push_back({0, bpl, bits, 8, 0, 16});
+            for (uint32_t waves : {8u, 16u})
+                for (uint32_t g : {4u, 16u})
+                    for (uint32_t cc : {0u, 1u}) cands.push_back({1, 16, bits, fold, 0, waves, g, cc});
+        for (uint32_t bpl : {8u, 16u}) cands.push_back({0, bpl, bits, 8, 0, 16, 16, 1});
     }
     float best_ms = 1e30f;
     pfac_tuning best_t = start;
@@ -736,7 +749,8 @@ extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *tex
         // index widths that give the same depth K and symbol width repeat a point
         const uint64_t key = ((uint64_t)c.kernel << 60) | ((uint64_t)c.bytes_per_lane << 48) |
                              ((uint64_t)t->img.K << 40) | ((uint64_t)t->img.b << 32) |
-                             ((uint64_t)t->img.fold_bits << 24) | ((uint64_t)c.waves_per_wg << 8) |
+                             ((uint64_t)t->img.fold_bits << 24) | ((uint64_t)c.waves_per_wg << 16) |
+                             ((uint64_t)c.chunks_per_unit << 8) | ((uint64_t)c.child_check << 4) |
                              c.wg_per_cu;
         if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
         seen.push_back(key);

@@ -13,7 +13,7 @@ constexpr uint32_t kWG = 256;            // threads per workgroup (4 waves of 64
 constexpr uint32_t kMatchCap = 256;      // matched positions a tile sorts in LDS
 constexpr uint32_t kTpbShift = 10;       // tiles per block-sum entry = 1024
 constexpr uint32_t kHaloCap = 1024;      // most halo bytes staged in LDS
-constexpr uint32_t kInlineCap = 4;       // records a wave chunk stages without an atomic
+constexpr uint32_t kInlineCap = 8;       // records a wave unit stages without an atomic
 
 // Device image as the kernels see it (pointers into one device allocation).
 struct ImageView {
@@ -26,6 +26,7 @@ struct ImageView {
     const uint8_t *ftab;      // prefix filter: folded child bitmaps of depth-K nodes
     const uint32_t *root_bits;  // codes of the root's children
     const uint8_t *chain;     // labels of compressed single-child runs
+    const uint32_t *krec;     // per depth-K node: up to three child labels, count in the top byte
     uint32_t K, b, identity, lvl_words;
     uint32_t lvl_start, max_len, n_nodes, fold_syms;
 };
@@ -47,7 +48,8 @@ struct ScanArgs {
     // wave kernel: shared tables, then one area per wave
     uint32_t fold;                    // prefix-filter bits per entry (0, 8, 16)
     uint32_t ftab_bytes, off_ftab, root_words, off_root;
-    uint32_t off_wave, wave_bytes, woff_bnd, woff_queue, woff_match, qcap, mcap, pad1;
+    uint32_t off_wave, wave_bytes, woff_bnd, woff_queue, woff_cand, woff_match, ccap, mcap;
+    uint32_t krec_words, off_krec, group, pad1;   // LDS child records, chunks per unit
     // outputs
     pfac_match *stage;
     uint64_t stage_cap;

@@ -1,34 +1,41 @@
 // Wave-independent scan kernel for gfx950.
 //
-// The same failure-less walk as the tile kernel (one start position per
-// lane-slot, walk from the root until the first byte without an edge, report
-// every pattern ending on the way), organised so that no step waits for the
-// whole workgroup:
+// The failure-less walk of the paper (one start position per lane slot, walk
+// the trie from the root until the first byte without an edge, report every
+// pattern that ends on the way), organised so that no step waits for the
+// whole workgroup and so that the memory latency of walks is paid once per
+// unit of several KiB rather than once per position:
 //
 //   * a workgroup only cooperates to load the shared tables into LDS once;
-//   * each wave then owns chunks of 1024 consecutive start positions (16 per
-//     lane), round robin over the grid, and loads the next chunk's 16-byte
-//     vectors while it processes the current one;
-//   * a prefix filter rejects most positions with one LDS lookup: the table is
+//   * each wave owns units of G consecutive 1 KiB chunks (round robin over the
+//     grid) and loads the next chunk's 16-byte vectors while it filters the
+//     current one;
+//   * stage 1 rejects most start positions with one LDS lookup: the table is
 //     indexed by the first K symbols (the code of a depth-K trie node) and
 //     holds that node's child bitmap folded to 8 or 16 bits, tested with the
-//     next symbol, so K + 1 symbols are checked at once (the bitmapped node of
-//     Design and Implementation, with the bitmap narrowed as that section
-//     allows);
-//   * survivors are compacted with ballots into a per-wave queue and walked
-//     from their depth-K node (found by rank in the level bitmap) through the
-//     CRS records in global memory (L2 resident);
-//   * matches of a chunk are sorted by position in the wave's LDS area and
-//     staged with one atomic per chunk; the shared finisher orders chunks.
-// A chunk whose survivors or matches overflow the per-wave buffers is redone
-// from the root, 64 positions at a time, in position order.
+//     next symbol (the bitmapped node of Design and Implementation, with the
+//     bitmap narrowed as that section allows);
+//   * stage 2 (optional) checks the next byte exactly against the child
+//     labels of the depth-K node, kept in LDS when they fit;
+//   * survivors become walk candidates (start, depth-K node, distance to the
+//     end of their text); a unit's candidates are walked together, reading
+//     the text and the CRS records from global memory (L2 resident), with
+//     single-child runs compared in bulk;
+//   * matches of a unit are sorted by position in the wave's LDS area and
+//     staged in the unit's inline slots (or with one atomic when there are
+//     more); the shared finisher orders units.
+// A unit whose matches overflow the per-wave list is redone from the root,
+// 64 positions at a time, in position order.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"
 
 namespace pfac {
 
-constexpr uint32_t kChunk = 1024;   // start positions per wave chunk (16 per lane)
+constexpr uint32_t kChunk = 1024;   // start positions per chunk (16 per lane)
+constexpr uint32_t kWin = kChunk + 16;  // chunk bytes staged in LDS (+ one vector)
+constexpr uint32_t kPPL = 4;        // start positions per lane per filter pass
+constexpr uint32_t kQ1 = 64 * kPPL; // stage-1 survivors of one pass
 
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t &total) {
     const uint32_t incl = wave_incl_scan(x);
@@ -49,21 +56,157 @@ __device__ __forceinline__ uint32_t mbcnt(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Byte j (0..31) of the 32-byte lane window w[0..7].
 __device__ __forceinline__ uint32_t wbyte(const uint32_t *w, int j) {
     return (w[j >> 2] >> (8 * (j & 3))) & 0xffu;
 }
 
-// Stage the matches of one chunk in (pos, id) order.  wm[i] = (window
-// position | stored list length << 16, list offset).  A chunk with at most
-// inline_cap records writes them to its own inline slots (no atomic with a
-// return value); larger ones reserve staging space with one atomic.
-__device__ __forceinline__ void emit_chunk(const ScanArgs &a, uint64_t c, uint64_t chunk_lo,
-                                           uint2 *wm, uint32_t mn, uint2 *sorted) {
+// True when text[g .. g+len) (global) equals chain[o .. o+len); the caller
+// guarantees g + len + 36 <= the end of the valid text.
+__device__ __forceinline__ bool chain_equal_g(const uint8_t *base, uint64_t g, const uint8_t *chain,
+                                              uint32_t o, uint32_t len) {
+    const uint32_t *c32 = (const uint32_t *)chain;
+    uint32_t diff = 0;
+    for (uint32_t i = 0; i < len; i += 32) {
+        uint32_t cw[9], tw[9];
+        const uint32_t cb = (o + i) >> 2;
+        const uint32_t *t32 = (const uint32_t *)(base + ((g + i) & ~3ull));
+#pragma unroll
+        for (int k = 0; k < 9; k++) cw[k] = c32[cb + k];
+#pragma unroll
+        for (int k = 0; k < 9; k++) tw[k] = t32[k];
+        const uint32_t cs = (o + i) & 3, ts = (uint32_t)((g + i) & 3);
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+            const int32_t r = (int32_t)(len - i) - 4 * k;
+            const uint32_t mask = r >= 4 ? 0xffffffffu : (r <= 0 ? 0u : ((1u << (8 * r)) - 1u));
+            const uint32_t c = __builtin_amdgcn_alignbyte(cw[k + 1], cw[k], cs);
+            const uint32_t t = __builtin_amdgcn_alignbyte(tw[k + 1], tw[k], ts);
+            diff |= (c ^ t) & mask;
+        }
+    }
+    return diff == 0;
+}
+
+// Walk for the start position at frame position p from node v at depth d,
+// reading the text from global memory; the text ends lim bytes after p.
+// Returns the pattern list of the deepest terminal node passed.
+__device__ __forceinline__ uint2 walk_g(const ImageView &im, const uint8_t *base, uint64_t p,
+                                        uint32_t lim, uint32_t v, uint32_t d, uint64_t hi_valid) {
+    uint2 hit = make_uint2(0, 0);
+    for (;;) {
+        const uint4 r = im.node[v];
+        if (r.z & kTermFlagD) hit = make_uint2(r.w, r.z >> kCountShiftD);
+        const uint32_t nc = r.z & 0xffffu;
+        if (nc == 0 || d >= lim) break;
+        const bool skip = (r.z & kSkipFlagD) != 0;
+        if (skip) {
+            // no pattern ends inside a single-child run: it matches whole or
+            // the walk ends with nothing more to report
+            const uint32_t len = r.z >> kSkipShiftD;
+            if (d + len > lim) break;
+            if (p + d + len + 36 <= hi_valid) {
+                if (!chain_equal_g(base, p + d, im.chain, r.x, len)) break;
+                v = r.w;
+                d += len;
+                continue;
+            }
+        }
+        const uint32_t c = base[p + d];
+        uint32_t j;
+        if (skip) {
+            if (c != im.label[r.y - 1]) break;
+            j = 0;
+        } else if (nc <= 4) {
+            const uint32_t x = r.x ^ (c * 0x01010101u);
+            const uint32_t m = (x - 0x01010101u) & ~x & 0x80808080u;  // lowest flag = first zero byte
+            if (m == 0) break;
+            j = (uint32_t)__builtin_ctz(m) >> 3;
+            if (j >= nc) break;
+        } else {
+            const uint8_t *lab = im.label + (r.y - 1);
+            uint32_t lo = 0, hi = nc;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (lab[mid] < c) lo = mid + 1; else hi = mid;
+            }
+            if (lo == nc || lab[lo] != c) break;
+            j = lo;
+        }
+        v = r.y + j;
+        d++;
+    }
+    return hit;
+}
+
+// Text boundaries of the chunk window [lo, lo + kWin): bits in `bnd`,
+// `dirty` when any lies in it, and the first boundary at or past its end.
+__device__ __forceinline__ void chunk_bounds(const ScanArgs &a, uint64_t chunk, uint64_t lo,
+                                             uint32_t *bnd, bool &dirty,
+                                             unsigned long long &next_bnd) {
+    const uint32_t lane = lane_id();
+    const uint64_t lo_valid = a.shift, hi_valid = a.shift + a.total;
+    const uint64_t end = lo + kWin;
+    constexpr uint32_t nbw = kWin / 32 + 2;
+    if (a.offsets == nullptr) {
+        const bool lo_in = lo_valid >= lo && lo_valid < end;
+        const bool hi_in = hi_valid >= lo && hi_valid < end;
+        dirty = lo_in || hi_in;
+        next_bnd = hi_valid >= end ? hi_valid : ~0ull;
+        if (dirty) {
+            if (lane < nbw) bnd[lane] = 0;
+            wave_sync();
+            if (lane == 0 && lo_in) atomicOr(&bnd[(lo_valid - lo) >> 5], 1u << ((lo_valid - lo) & 31));
+            if (lane == 1 && hi_in) atomicOr(&bnd[(hi_valid - lo) >> 5], 1u << ((hi_valid - lo) & 31));
+        }
+    } else {
+        if (lane < nbw) bnd[lane] = 0;
+        wave_sync();
+        dirty = false;
+        next_bnd = ~0ull;
+        for (uint32_t i = a.tile_first_text[chunk] + lane;; i += 64) {
+            const unsigned long long bp = i <= a.n_texts ? a.offsets[i] + a.shift : ~0ull;
+            const bool in = bp >= lo && bp < end;
+            if (in) atomicOr(&bnd[(bp - lo) >> 5], 1u << ((bp - lo) & 31));
+            dirty = dirty || __ballot(in) != 0;
+            next_bnd = wave_min_u64(bp >= end ? bp : next_bnd);
+            if (__ballot(bp >= end) != 0) break;
+        }
+    }
+    wave_sync();
+}
+
+// Distance from window position pl to the next text boundary after it.
+__device__ __forceinline__ uint32_t limit_after(const uint32_t *bnd, bool dirty, uint64_t lo,
+                                                uint32_t pl, unsigned long long next_bnd) {
+    unsigned long long nb = next_bnd;
+    if (dirty) {
+        constexpr uint32_t nbw = kWin / 32 + 2;
+        const uint32_t q = pl + 1;
+        uint32_t w = q >> 5;
+        uint32_t bits = bnd[w] & (0xffffffffu << (q & 31));
+        while (bits == 0 && ++w < nbw) bits = bnd[w];
+        if (bits) nb = lo + (w << 5) + (uint32_t)__builtin_ctz(bits);
+    }
+    const unsigned long long d = nb - (lo + pl);
+    return d > 0xffffull ? 0xffffu : (uint32_t)d;
+}
+
+// Stage the matches of unit u in (pos, id) order.  wm[i] = (unit position |
+// stored list length << 16, list offset).  At most inline_cap records go to
+// the unit's inline slots; more reserve staging space with one atomic.
+__device__ __forceinline__ void emit_unit(const ScanArgs &a, uint64_t u, uint64_t unit_lo,
+                                          const uint2 *wm, uint32_t mn, uint2 *sorted) {
     const ImageView &im = a.im;
     const uint32_t lane = lane_id();
     if (mn == 0) {
-        if (lane == 0) a.unit_count[c] = 0;
+        if (lane == 0) a.unit_count[u] = 0;
         return;
     }
     for (uint32_t i = lane; i < mn; i += 64) {
@@ -72,88 +215,88 @@ __device__ __forceinline__ void emit_chunk(const ScanArgs &a, uint64_t c, uint64
         for (uint32_t q = 0; q < mn; q++) rk += (wm[q].x & 0xffffu) < (e.x & 0xffffu);
         sorted[rk] = e;
     }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    uint2 ids[2];
-    uint32_t off[2], total = 0;
-#pragma unroll
-    for (int r = 0; r < 2; r++) {
-        const uint32_t i = lane + 64u * r;
-        ids[r] = make_uint2(0, 0);
-        if (i < mn) ids[r] = hit_list(im, make_uint2(sorted[i].y, sorted[i].x >> 16));
+    wave_sync();
+    uint32_t total = 0;
+    for (uint32_t r0 = 0; r0 < mn; r0 += 64) {
+        const uint32_t i = r0 + lane;
+        const uint32_t n = i < mn ? hit_list(im, make_uint2(sorted[i].y, sorted[i].x >> 16)).y : 0u;
         uint32_t t;
-        off[r] = total + wave_excl_scan(ids[r].y, t);
+        wave_excl_scan(n, t);
         total += t;
     }
     pfac_match *dst;
-    uint64_t base, cap;
+    uint64_t base = 0, cap;
     if (total <= a.inline_cap) {
-        dst = a.inline_stage + c * a.inline_cap;
-        base = 0;
+        dst = a.inline_stage + u * a.inline_cap;
         cap = a.inline_cap;
         if (lane == 0) {
-            a.unit_count[c] = total;
-            a.unit_off[c] = ~0ull;
-            atomicAdd(&a.blocksum[c >> kTpbShift], (unsigned long long)total);
+            a.unit_count[u] = total;
+            a.unit_off[u] = ~0ull;
+            atomicAdd(&a.blocksum[u >> kTpbShift], (unsigned long long)total);
         }
     } else {
         unsigned long long b = 0;
         if (lane == 0) {
             b = atomicAdd(a.stage_cursor, (unsigned long long)total);
-            a.unit_count[c] = total;
-            a.unit_off[c] = b;
-            atomicAdd(&a.blocksum[c >> kTpbShift], (unsigned long long)total);
+            a.unit_count[u] = total;
+            a.unit_off[u] = b;
+            atomicAdd(&a.blocksum[u >> kTpbShift], (unsigned long long)total);
         }
         base = __shfl(b, 0, 64);
         dst = a.stage;
         cap = a.stage_cap;
     }
-#pragma unroll
-    for (int r = 0; r < 2; r++) {
-        const uint32_t i = lane + 64u * r;
-        if (i < mn) emit(a, chunk_lo + (sorted[i].x & 0xffffu), ids[r], dst, base + off[r], cap);
+    for (uint32_t r0 = 0; r0 < mn; r0 += 64) {
+        const uint32_t i = r0 + lane;
+        uint2 ids = make_uint2(0, 0);
+        if (i < mn) ids = hit_list(im, make_uint2(sorted[i].y, sorted[i].x >> 16));
+        uint32_t t;
+        const uint32_t before = wave_excl_scan(ids.y, t);
+        if (i < mn) emit(a, unit_lo + (sorted[i].x & 0xffffu), ids, dst, base + before, cap);
+        base += t;
     }
 }
 
-// Redo a chunk from the root, in position order, when its buffers overflow.
-__device__ __forceinline__ void chunk_from_root(const ScanArgs &a, const Tile &T, uint64_t c) {
+// Redo unit u from the root, in position order, when its match list overflows.
+__device__ __forceinline__ void unit_from_root(const ScanArgs &a, uint64_t u, uint64_t unit_lo,
+                                               uint32_t n_chunks, uint32_t *bnd) {
     const ImageView &im = a.im;
     const uint32_t lane = lane_id();
     const uint64_t lo_valid = a.shift, hi_valid = a.shift + a.total;
     uint32_t total = 0;
-    for (uint32_t r = 0; r < kChunk / 64; r++) {
-        const uint32_t pl = r * 64 + lane;
-        const uint64_t p = T.lo + pl;
-        uint32_t cnt = 0;
-        if (p >= lo_valid && p < hi_valid) {
-            const uint2 h = walk(im, a.base, T, pl, 0, 0);
-            if (h.y) cnt = hit_list(im, h).y;
-        }
-        uint32_t t;
-        wave_excl_scan(cnt, t);
-        total += t;
-    }
     unsigned long long base = 0;
-    if (lane == 0) {
-        base = atomicAdd(a.stage_cursor, (unsigned long long)total);
-        a.unit_count[c] = total;
-        a.unit_off[c] = base;
-        if (total) atomicAdd(&a.blocksum[c >> kTpbShift], (unsigned long long)total);
-    }
-    base = __shfl(base, 0, 64);
-    for (uint32_t r = 0; r < kChunk / 64; r++) {
-        const uint32_t pl = r * 64 + lane;
-        const uint64_t p = T.lo + pl;
-        uint2 ids = make_uint2(0, 0);
-        if (p >= lo_valid && p < hi_valid) {
-            const uint2 h = walk(im, a.base, T, pl, 0, 0);
-            if (h.y) ids = hit_list(im, h);
+    for (int pass = 0; pass < 2; pass++) {
+        for (uint32_t g = 0; g < n_chunks; g++) {
+            const uint64_t lo = unit_lo + (uint64_t)g * kChunk;
+            bool dirty;
+            unsigned long long next_bnd;
+            chunk_bounds(a, lo / kChunk, lo, bnd, dirty, next_bnd);
+            for (uint32_t r = 0; r < kChunk / 64; r++) {
+                const uint32_t pl = r * 64 + lane;
+                const uint64_t p = lo + pl;
+                uint2 ids = make_uint2(0, 0);
+                if (p >= lo_valid && p < hi_valid) {
+                    const uint32_t lim = limit_after(bnd, dirty, lo, pl, next_bnd);
+                    const uint2 h = walk_g(im, a.base, p, lim, 0, 0, hi_valid);
+                    if (h.y) ids = hit_list(im, h);
+                }
+                uint32_t t;
+                const uint32_t before = wave_excl_scan(ids.y, t);
+                if (pass == 1 && ids.y) emit(a, p, ids, a.stage, base + before, a.stage_cap);
+                if (pass == 0) total += t; else base += t;
+            }
+            wave_sync();
         }
-        uint32_t t;
-        const uint32_t before = wave_excl_scan(ids.y, t);
-        if (ids.y) emit(a, p, ids, a.stage, base + before, a.stage_cap);
-        base += t;
+        if (pass == 0) {
+            unsigned long long b = 0;
+            if (lane == 0) {
+                b = atomicAdd(a.stage_cursor, (unsigned long long)total);
+                a.unit_count[u] = total;
+                a.unit_off[u] = b;
+                if (total) atomicAdd(&a.blocksum[u >> kTpbShift], (unsigned long long)total);
+            }
+            base = __shfl(b, 0, 64);
+        }
     }
 }
 
@@ -173,37 +316,37 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     uint32_t *s_bits = (uint32_t *)(lds + a.off_bits);
     uint32_t *s_rank = (uint32_t *)(lds + a.off_rank);
     uint32_t *s_root = (uint32_t *)(lds + a.off_root);
+    uint32_t *s_krec = (uint32_t *)(lds + a.off_krec);
     uint8_t *s_sym = lds + a.off_sym;
 
     // ---- shared tables, once per workgroup
-    {
-        const uint32_t fbytes = a.ftab_bytes;
-        for (uint32_t i = tid; i < fbytes / 16; i += nthreads)
-            ((uint4 *)s_ftab)[i] = ((const uint4 *)im.ftab)[i];
-        for (uint32_t i = tid; i < im.lvl_words; i += nthreads) {
-            const uint2 e = ((const uint2 *)im.lvl)[i];
-            s_bits[i] = e.x;
-            s_rank[i] = e.y;
-        }
-        for (uint32_t i = tid; i < a.root_words; i += nthreads) s_root[i] = im.root_bits[i];
-        if (MODE == 0 && !im.identity)
-            for (uint32_t i = tid; i < 256; i += nthreads) s_sym[i] = im.sym[i];
+    for (uint32_t i = tid; i < a.ftab_bytes / 16; i += nthreads)
+        ((uint4 *)s_ftab)[i] = ((const uint4 *)im.ftab)[i];
+    for (uint32_t i = tid; i < im.lvl_words; i += nthreads) {
+        const uint2 e = ((const uint2 *)im.lvl)[i];
+        s_bits[i] = e.x;
+        s_rank[i] = e.y;
     }
+    for (uint32_t i = tid; i < a.root_words; i += nthreads) s_root[i] = im.root_bits[i];
+    for (uint32_t i = tid; i < a.krec_words; i += nthreads) s_krec[i] = im.krec[i];
+    if (MODE == 0 && !im.identity)
+        for (uint32_t i = tid; i < 256; i += nthreads) s_sym[i] = im.sym[i];
     __syncthreads();
 
     uint8_t *wbase = lds + a.off_wave + wave * a.wave_bytes;
-    uint8_t *wtext = wbase;                                         // kChunk + halo + 16
+    uint8_t *wtext = wbase;
     uint32_t *wbnd = (uint32_t *)(wbase + a.woff_bnd);
     uint32_t *wq = (uint32_t *)(wbase + a.woff_queue);
+    uint2 *wc = (uint2 *)(wbase + a.woff_cand);
     uint2 *wm = (uint2 *)(wbase + a.woff_match);
 
     const uint64_t lo_valid = a.shift, hi_valid = a.shift + a.total;
-    const uint32_t halo = a.halo;
-    const uint32_t win = kChunk + halo;
-    const uint32_t nbw = win / 32 + 2;
+    const uint64_t n_units = a.n_tiles;
+    const uint32_t G = a.group;
     const uint64_t stride = (uint64_t)gridDim.x * waves;
     const uint32_t K = im.K;
-    const uint32_t qcap = a.qcap, mcap = a.mcap;
+    const uint32_t ccap = a.ccap, mcap = a.mcap;
+    const bool krec = a.krec_words != 0;
 
     auto load_vec = [&](uint64_t g) -> uint4 {
         uint4 v = make_uint4(0, 0, 0, 0);
@@ -211,200 +354,196 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         if (g + 16 > lo_valid && g < hi_valid) v = *(const uint4 *)(a.base + g);
         return v;
     };
+    // chunks of a unit that hold text
+    auto unit_chunks = [&](uint64_t u) -> uint32_t {
+        const uint64_t lo = u * G * kChunk;
+        const uint64_t left = hi_valid > lo ? hi_valid - lo : 0;
+        return (uint32_t)min((uint64_t)G, (left + kChunk - 1) / kChunk);
+    };
 
-    uint64_t c = (uint64_t)blockIdx.x * waves + wave;
+    uint64_t u = (uint64_t)blockIdx.x * waves + wave;
     uint4 cur = make_uint4(0, 0, 0, 0), cur_h = make_uint4(0, 0, 0, 0);
-    if (c < a.n_tiles) {
-        cur = load_vec(c * kChunk + 16ull * lane);
-        if (lane < halo / 16) cur_h = load_vec(c * kChunk + kChunk + 16ull * lane);
+    if (u < n_units) {
+        const uint64_t lo = u * G * kChunk;
+        cur = load_vec(lo + 16ull * lane);
+        if (lane == 0) cur_h = load_vec(lo + kChunk);
     }
-    for (; c < a.n_tiles; c += stride) {
-        const uint64_t chunk_lo = c * kChunk;
-        const uint64_t win_end = chunk_lo + win;
-        // next chunk's text, in flight while this one is processed
-        uint4 nxt = make_uint4(0, 0, 0, 0), nxt_h = make_uint4(0, 0, 0, 0);
-        const uint64_t cn = c + stride;
-        if (cn < a.n_tiles) {
-            nxt = load_vec(cn * kChunk + 16ull * lane);
-            if (lane < halo / 16) nxt_h = load_vec(cn * kChunk + kChunk + 16ull * lane);
-        }
+    for (; u < n_units; u += stride) {
+        const uint64_t unit_lo = u * G * kChunk;
+        const uint32_t nch = unit_chunks(u);
+        uint32_t cn = 0, mn = 0;   // candidates, matches (wave-uniform)
 
-        // ---- 1. window into the wave's LDS area
-        *(uint4 *)(wtext + 16 * lane) = cur;
-        if (lane < halo / 16) *(uint4 *)(wtext + kChunk + 16 * lane) = cur_h;
-
-        // ---- 2. text boundaries in the window
-        bool dirty;
-        unsigned long long next_bnd;
-        if (a.offsets == nullptr) {
-            const bool lo_in = lo_valid >= chunk_lo && lo_valid < win_end;
-            const bool hi_in = hi_valid >= chunk_lo && hi_valid < win_end;
-            dirty = lo_in || hi_in;
-            next_bnd = hi_valid >= win_end ? hi_valid : ~0ull;
-            if (dirty) {
-                for (uint32_t i = lane; i < nbw; i += 64) wbnd[i] = 0;
-                __builtin_amdgcn_wave_barrier();
-                if (lane == 0 && lo_in) atomicOr(&wbnd[(lo_valid - chunk_lo) >> 5], 1u << ((lo_valid - chunk_lo) & 31));
-                if (lane == 1 && hi_in) atomicOr(&wbnd[(hi_valid - chunk_lo) >> 5], 1u << ((hi_valid - chunk_lo) & 31));
-            }
-        } else {
-            for (uint32_t i = lane; i < nbw; i += 64) wbnd[i] = 0;
-            __builtin_amdgcn_wave_barrier();
-            dirty = false;
-            next_bnd = ~0ull;
-            for (uint32_t i = a.tile_first_text[c] + lane;; i += 64) {
-                const unsigned long long bp = i <= a.n_texts ? a.offsets[i] + a.shift : ~0ull;
-                const bool in = bp >= chunk_lo && bp < win_end;
-                if (in) atomicOr(&wbnd[(bp - chunk_lo) >> 5], 1u << ((bp - chunk_lo) & 31));
-                dirty = dirty || __ballot(in) != 0;
-                next_bnd = wave_min_u64(bp >= win_end ? bp : next_bnd);
-                if (__ballot(bp >= win_end) != 0) break;
-            }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-        Tile T;
-        T.text = wtext;
-        T.bnd = wbnd;
-        T.lo = chunk_lo;
-        T.win = win;
-        T.dirty = dirty;
-        T.next_bnd = next_bnd;
-
-        // ---- 3. prefix filter over this lane's 16 start positions
-        uint32_t w[8];
-        {
-            w[0] = cur.x; w[1] = cur.y; w[2] = cur.z; w[3] = cur.w;
-            const uint4 x = *(const uint4 *)(wtext + 16 * lane + 16);
-            w[4] = x.x; w[5] = x.y; w[6] = x.z; w[7] = x.w;
-        }
-        uint32_t qn = 0;
-        bool overflow = false;
-        auto push = [&](bool hit, uint32_t entry) {
-            const unsigned long long m = __ballot(hit);
-            if (hit) {
-                const uint32_t slot = qn + mbcnt(m);
-                if (slot < qcap) wq[slot] = entry;
-            }
-            qn += (uint32_t)__popcll(m);
-        };
-        if (MODE == 1 || MODE == 2) {
-#pragma unroll
-            for (int j = 0; j < 16; j++) {
-                // code = (B[j] << 8) | B[j+1]; next = B[j+2]
-                const uint32_t lo = w[j >> 2], hi = w[(j >> 2) + 1];
-                const uint32_t r = j & 3;
-                const uint32_t sel = 0x0c0c0000u | (r << 8) | (r + 1);
-                const uint32_t code = __builtin_amdgcn_perm(hi, lo, sel);
-                const uint32_t nx = wbyte(w, j + 2);
-                uint32_t hit;
-                if (MODE == 1)
-                    hit = (s_ftab[code] >> (nx & 7)) & 1u;
-                else
-                    hit = (((const uint16_t *)s_ftab)[code] >> (nx & 15)) & 1u;
-                push(hit != 0, ((16 * lane + j) << 20) | code);
-            }
-        } else {
-            const uint32_t b = im.b;
-            const uint32_t m = (K >= 1 && a.fold) ? im.fold_syms : 0u;
-            const uint32_t L = K >= 1 ? K + m : 1u;
-            const uint32_t full_mask = (b * L >= 32) ? 0xffffffffu : ((1u << (b * L)) - 1u);
-            // the folded bit reads only the last m symbols of the window
-            const uint32_t fmask = (a.fold - 1u) & ((b * m >= 32) ? 0xffffffffu : ((1u << (b * m)) - 1u));
-            uint32_t full = 0, run = 0;
-#pragma unroll
-            for (int j = 0; j < 31; j++) {
-                if ((uint32_t)j >= 15 + L) continue;  // wave-uniform
-                const uint32_t byte = wbyte(w, j);
-                uint32_t s = byte;
-                bool ok = true;
-                if (!im.identity) {
-                    s = s_sym[byte];
-                    ok = s != 0xffu;
-                }
-                run = ok ? run + 1 : 0u;
-                full = ((full << b) | (s & 0xffu)) & full_mask;
-                if ((uint32_t)j + 1 >= L) {
-                    const uint32_t pos = j + 1 - L;
-                    uint32_t hit = 0, code = 0;
-                    if (run >= L) {
-                        if (K == 0) {
-                            hit = (s_root[full >> 5] >> (full & 31)) & 1u;
-                        } else if (a.fold) {
-                            code = full >> (b * m);
-                            const uint32_t bit = full & fmask;
-                            hit = a.fold == 8 ? (s_ftab[code] >> bit) & 1u
-                                              : (((const uint16_t *)s_ftab)[code] >> bit) & 1u;
-                        } else {
-                            code = full;
-                            hit = (s_bits[code >> 5] >> (code & 31)) & 1u;
-                        }
-                    }
-                    push(hit != 0, ((16 * lane + pos) << 20) | code);
-                }
-            }
-        }
-        overflow = qn > qcap;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-        // ---- 4. walk the survivors
-        uint32_t mn = 0;
-        if (!overflow) {
-            for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
+        // walk every queued candidate; matches go to wm
+        auto flush = [&]() {
+            for (uint32_t r0 = 0; r0 < cn; r0 += 64) {
                 const uint32_t e = r0 + lane;
                 uint2 h = make_uint2(0, 0);
-                uint32_t pl = 0;
-                if (e < qn) {
-                    const uint32_t ent = wq[e];
-                    pl = ent >> 20;
-                    const uint64_t p = chunk_lo + pl;
-                    // the filter read K symbols without looking at text
-                    // boundaries: none may start inside them
-                    bool crosses = false;
-                    if (dirty)
-                        for (uint32_t q = pl + 1; q < pl + K; q++)
-                            crosses = crosses || ((wbnd[q >> 5] >> (q & 31)) & 1u);
-                    if (p >= lo_valid && p < hi_valid && !crosses) {
-                        uint32_t v = 0, d = 0;
-                        if (K) {
-                            const uint32_t code = ent & 0xfffffu;
-                            const uint32_t bits = s_bits[code >> 5];
-                            const uint32_t below = bits & ((1u << (code & 31)) - 1u);
-                            v = im.lvl_start + s_rank[code >> 5] + (uint32_t)__builtin_popcount(below);
-                            d = K;
-                        }
-                        h = walk(im, a.base, T, pl, v, d);
-                    }
+                uint32_t pr = 0;
+                if (e < cn) {
+                    const uint2 c = wc[e];
+                    pr = c.x & 0xffffu;
+                    h = walk_g(im, a.base, unit_lo + pr, c.x >> 16, c.y, K, hi_valid);
                 }
                 const bool got = h.y != 0;
                 const unsigned long long mk = __ballot(got);
                 if (got) {
                     const uint32_t slot = mn + mbcnt(mk);
-                    if (slot < mcap) wm[slot] = make_uint2(pl | (h.y << 16), h.x);
+                    if (slot < mcap) wm[slot] = make_uint2(pr | (h.y << 16), h.x);
                 }
                 mn += (uint32_t)__popcll(mk);
             }
-            overflow = mn > mcap;
+            cn = 0;
+        };
+
+        for (uint32_t g = 0; g < nch; g++) {
+            const uint64_t chunk_lo = unit_lo + (uint64_t)g * kChunk;
+            // next chunk's text, in flight while this one is filtered
+            uint64_t nlo = ~0ull;
+            if (g + 1 < nch) nlo = chunk_lo + kChunk;
+            else if (u + stride < n_units) nlo = (u + stride) * G * kChunk;
+            uint4 nxt = make_uint4(0, 0, 0, 0), nxt_h = make_uint4(0, 0, 0, 0);
+            if (nlo != ~0ull) {
+                nxt = load_vec(nlo + 16ull * lane);
+                if (lane == 0) nxt_h = load_vec(nlo + kChunk);
+            }
+
+            *(uint4 *)(wtext + 16 * lane) = cur;
+            if (lane == 0) *(uint4 *)(wtext + kChunk) = cur_h;
+            bool dirty;
+            unsigned long long next_bnd;
+            chunk_bounds(a, chunk_lo / kChunk, chunk_lo, wbnd, dirty, next_bnd);
+
+            uint32_t w[8];
+            {
+                w[0] = cur.x; w[1] = cur.y; w[2] = cur.z; w[3] = cur.w;
+                const uint4 x = *(const uint4 *)(wtext + 16 * lane + 16);
+                w[4] = x.x; w[5] = x.y; w[6] = x.z; w[7] = x.w;
+            }
+
+            // generic filter state carried across passes
+            const uint32_t b = MODE == 0 ? im.b : 8u;
+            const uint32_t m = (K >= 1 && a.fold) ? im.fold_syms : 0u;
+            const uint32_t L = K >= 1 ? K + m : 1u;
+            const uint32_t full_mask = (b * L >= 32) ? 0xffffffffu : ((1u << (b * L)) - 1u);
+            const uint32_t fmask = (a.fold - 1u) & ((b * m >= 32) ? 0xffffffffu : ((1u << (b * m)) - 1u));
+            uint32_t full = 0, run = 0;
+            if (MODE == 0) {
+                // the first L - 1 symbols of the lane window
+#pragma unroll
+                for (int j = 0; j < 15; j++) {
+                    if ((uint32_t)j + 1 >= L) continue;
+                    const uint32_t byte = wbyte(w, j);
+                    uint32_t s = byte;
+                    bool ok = true;
+                    if (!im.identity) { s = s_sym[byte]; ok = s != 0xffu; }
+                    run = ok ? run + 1 : 0u;
+                    full = ((full << b) | (s & 0xffu)) & full_mask;
+                }
+            }
+
+#pragma unroll
+            for (int pass = 0; pass < 16 / (int)kPPL; pass++) {
+                // ---- stage 1: prefix filter over kPPL start positions per lane
+                uint32_t qn = 0;
+                auto push = [&](bool hit, uint32_t entry) {
+                    const unsigned long long mk = __ballot(hit);
+                    if (hit) wq[qn + mbcnt(mk)] = entry;
+                    qn += (uint32_t)__popcll(mk);
+                };
+#pragma unroll
+                for (int jj = 0; jj < (int)kPPL; jj++) {
+                    const int j = pass * (int)kPPL + jj;
+                    if (MODE == 1 || MODE == 2) {
+                        // code = (B[j] << 8) | B[j+1]; next = B[j+2]
+                        const uint32_t lo = w[j >> 2], hi = w[(j >> 2) + 1];
+                        const uint32_t r = j & 3;
+                        const uint32_t sel = 0x0c0c0000u | (r << 8) | (r + 1);
+                        const uint32_t code = __builtin_amdgcn_perm(hi, lo, sel);
+                        const uint32_t nx = wbyte(w, j + 2);
+                        uint32_t hit;
+                        if (MODE == 1)
+                            hit = (s_ftab[code] >> (nx & 7)) & 1u;
+                        else
+                            hit = (((const uint16_t *)s_ftab)[code] >> (nx & 15)) & 1u;
+                        push(hit != 0, ((16 * lane + j) << 20) | code);
+                    } else {
+                        // the symbol at window byte j + L - 1 completes position j
+                        const uint32_t byte = wtext[16 * lane + j + L - 1];
+                        uint32_t s = byte;
+                        bool ok = true;
+                        if (!im.identity) { s = s_sym[byte]; ok = s != 0xffu; }
+                        run = ok ? run + 1 : 0u;
+                        full = ((full << b) | (s & 0xffu)) & full_mask;
+                        uint32_t hit = 0, code = 0;
+                        if (run >= L) {
+                            if (K == 0) {
+                                hit = (s_root[full >> 5] >> (full & 31)) & 1u;
+                            } else if (a.fold) {
+                                code = full >> (b * m);
+                                const uint32_t bit = full & fmask;
+                                hit = a.fold == 8 ? (s_ftab[code] >> bit) & 1u
+                                                  : (((const uint16_t *)s_ftab)[code] >> bit) & 1u;
+                            } else {
+                                code = full;
+                                hit = (s_bits[code >> 5] >> (code & 31)) & 1u;
+                            }
+                        }
+                        push(hit != 0, ((16 * lane + j) << 20) | code);
+                    }
+                }
+                wave_sync();
+
+                // ---- stage 2: exact next byte, text end, candidates
+                for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
+                    if (cn + 64 > ccap) flush();
+                    const uint32_t e = r0 + lane;
+                    bool pass2 = false;
+                    uint32_t entry = 0, v = 0;
+                    if (e < qn) {
+                        const uint32_t ent = wq[e];
+                        const uint32_t pl = ent >> 20;
+                        const uint64_t p = chunk_lo + pl;
+                        const uint32_t lim = limit_after(wbnd, dirty, chunk_lo, pl, next_bnd);
+                        // the filter read K + 1 bytes: all must be in this text
+                        pass2 = p >= lo_valid && p < hi_valid && lim > K;
+                        if (pass2 && K) {
+                            const uint32_t code = ent & 0xfffffu;
+                            const uint32_t bits = s_bits[code >> 5];
+                            const uint32_t below = bits & ((1u << (code & 31)) - 1u);
+                            const uint32_t rank = s_rank[code >> 5] + (uint32_t)__builtin_popcount(below);
+                            v = im.lvl_start + rank;
+                            if (krec) {
+                                // up to three child labels, or 0xff.. for more
+                                const uint32_t rec = s_krec[rank];
+                                const uint32_t ncc = rec >> 24;
+                                if (ncc <= 3) {
+                                    const uint32_t c = wtext[pl + K];
+                                    const uint32_t x = rec ^ (c * 0x00010101u);
+                                    const uint32_t mm = (x - 0x00010101u) & ~x & 0x00808080u;
+                                    pass2 = mm != 0 && ((uint32_t)__builtin_ctz(mm) >> 3) < ncc;
+                                }
+                            }
+                        }
+                        entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
+                    }
+                    const unsigned long long mk = __ballot(pass2);
+                    if (pass2) wc[cn + mbcnt(mk)] = make_uint2(entry, v);
+                    cn += (uint32_t)__popcll(mk);
+                }
+                wave_sync();
+            }
+            cur = nxt;
+            cur_h = nxt_h;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        flush();
+        wave_sync();
 
-        // ---- 5. stage this chunk's matches in (pos, id) order
-        if (!overflow)
-            emit_chunk(a, c, chunk_lo, wm, mn, (uint2 *)wq);
+        // ---- this unit's matches, in (pos, id) order
+        if (mn <= mcap)
+            emit_unit(a, u, unit_lo, wm, mn, (uint2 *)wq);
         else
-            chunk_from_root(a, T, c);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-        cur = nxt;
-        cur_h = nxt_h;
+            unit_from_root(a, u, unit_lo, nch, wbnd);
+        wave_sync();
     }
 }
 
@@ -424,21 +563,18 @@ void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit) {
     a.off_rank = take(4 * a.im.lvl_words);
     a.root_words = a.im.K == 0 ? std::max(1u, (1u << a.im.b) / 32) : 0u;
     a.off_root = take(4 * a.root_words);
+    a.off_krec = take(4 * a.krec_words);
     a.off_sym = take(a.im.identity ? 0 : 256);
     a.off_wave = off;
-    const uint32_t win = kChunk + a.halo;
-    a.mcap = 128;
-    const uint32_t fixed = ((win + 16 + 15) & ~15u) + ((4 * (win / 32 + 2) + 15) & ~15u) + 8 * a.mcap;
-    // the survivor queue takes what is left, up to one entry per position
-    uint32_t left = lds_limit > off ? (lds_limit - off) / waves : 0;
-    uint32_t q = left > fixed ? (left - fixed) / 4 : 0;
-    q = std::min<uint32_t>(q & ~63u, kChunk);
-    a.qcap = std::max<uint32_t>(q, 2 * a.mcap);
-    a.woff_bnd = (win + 16 + 15) & ~15u;
-    a.woff_queue = a.woff_bnd + ((4 * (win / 32 + 2) + 15) & ~15u);
-    a.woff_match = a.woff_queue + 4 * a.qcap;
+    a.mcap = 64;
+    a.ccap = 128;
+    a.woff_bnd = (kWin + 16 + 15) & ~15u;
+    a.woff_queue = a.woff_bnd + ((4 * (kWin / 32 + 2) + 15) & ~15u);
+    a.woff_cand = a.woff_queue + std::max(4 * kQ1, 8 * a.mcap);
+    a.woff_match = a.woff_cand + 8 * a.ccap;
     a.wave_bytes = a.woff_match + 8 * a.mcap;
     a.lds_total = off + waves * a.wave_bytes;
+    (void)lds_limit;
 }
 
 int wave_mode(const ScanArgs &a) {

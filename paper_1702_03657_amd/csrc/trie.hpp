@@ -78,6 +78,9 @@ struct DeviceImageHost {
     uint32_t fold_syms = 0;            // m
     std::vector<uint8_t> ftab;         // 2^(b K) entries of E bits
     std::vector<uint32_t> root_bits;   // 2^b bits: codes of the root's children
+    // Child labels of every depth-K node in breadth-first order: bytes 0..2
+    // hold up to three labels, byte 3 the count (0xff when there are more).
+    std::vector<uint32_t> krec;
 };
 
 // Derives the device image from the CRS trie for a level index of at most

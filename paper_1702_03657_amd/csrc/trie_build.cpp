@@ -252,6 +252,17 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
         I.lvl[2 * w + 1] = run;
         run += (uint32_t)__builtin_popcount(I.lvl[2 * w]);
     }
+    I.krec.assign(v1 - v0, 0);
+    for (uint32_t v = v0; v < v1; v++) {
+        const uint32_t e0 = T.row_ptr[v], nc = T.row_ptr[v + 1] - e0;
+        uint32_t rec = (nc <= 3 ? nc : 0xffu) << 24;
+        for (uint32_t j = 0; j < 3; j++) {
+            // unused slots repeat the last label; the kernel ignores j >= count
+            const uint32_t lab = nc ? T.labels[e0 + std::min(j, nc - 1)] : 0;
+            rec |= lab << (8 * j);
+        }
+        I.krec[v - v0] = rec;
+    }
 
     // prefix filter over the depth-(K+m) nodes
     if (fold_bits != 8 && fold_bits != 16) return;

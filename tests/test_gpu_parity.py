@@ -36,8 +36,8 @@ def test_c1_full_size_against_brute_force():
 
 TUNINGS = (
     [dict(kernel=0, bytes_per_lane=bpl, index_bits=bits) for bpl in (4, 8, 16) for bits in (8, 12, 16, 18)]
-    + [dict(kernel=1, index_bits=bits, fold_bits=fold, waves_per_wg=w)
-       for bits in (8, 12, 16, 18) for fold in (0, 8, 16) for w in (4, 16)]
+    + [dict(kernel=1, index_bits=bits, fold_bits=fold, waves_per_wg=w, chunks_per_unit=g, child_check=cc)
+       for bits in (8, 12, 16, 18) for fold in (0, 8, 16) for (w, g, cc) in ((4, 1, 0), (16, 16, 1), (12, 64, 1))]
 )
 
 
@@ -63,6 +63,8 @@ DNA_TUNINGS = [
     dict(kernel=1, index_bits=16, fold_bits=8), dict(kernel=1, index_bits=16, fold_bits=16),
     dict(kernel=1, index_bits=12, fold_bits=16, waves_per_wg=8), dict(kernel=1, index_bits=18, fold_bits=0),
     dict(kernel=1, index_bits=14, fold_bits=8, waves_per_wg=4, wg_per_cu=1),
+    dict(kernel=1, index_bits=16, fold_bits=8, chunks_per_unit=1, child_check=0),
+    dict(kernel=1, index_bits=12, fold_bits=8, chunks_per_unit=64, child_check=1),
 ]
 
 
@@ -172,13 +174,19 @@ def _random_batch(rng, n_texts, max_len, alphabet):
     return text, offs
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2])
+BATCH_TUNINGS = [dict(kernel=1), dict(kernel=0, bytes_per_lane=8),
+                 dict(kernel=1, chunks_per_unit=1, child_check=0, waves_per_wg=4),
+                 dict(kernel=1, chunks_per_unit=64, fold_bits=0)]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
 def test_batch_matches_oracle_and_plain(seed):
     rng = np.random.default_rng(seed)
     alphabet = np.frombuffer(b"abcd", dtype=np.uint8)
     text, offs = _random_batch(rng, 3000, 700, alphabet)
     pats = [bytes(rng.choice(alphabet, int(rng.integers(2, 9))).astype(np.uint8)) for _ in range(300)]
     trie = pf.Trie(pats)
+    trie.set_tuning(**BATCH_TUNINGS[seed])
     say(f"batch seed={seed}: {len(offs) - 1} texts, {offs[-1]} bytes")
     want = oracle.brute(text, pats, offsets=offs, threads=8)
     got, n = gpu_scan_batch(trie, text, offs, pad_front=seed * 5)
@@ -187,6 +195,19 @@ def test_batch_matches_oracle_and_plain(seed):
     got_plain, n2 = gpu_scan_batch(trie, text, offs, plain=True)
     assert n2 == want.n
     assert_same(got_plain, want, with_text=True)
+
+
+@pytest.mark.parametrize("tuning", BATCH_TUNINGS, ids=_tid)
+def test_batch_long_patterns_small_texts(tuning):
+    wl = workloads.c4_batched(n_small=3000, n_large=2, large_lo=1 << 15, large_hi=1 << 16,
+                              k=3000, rate=1 / 256)
+    trie = pf.Trie(wl.patterns)
+    trie.set_tuning(**tuning)
+    want = oracle.bucketed(wl.text, wl.patterns, offsets=wl.offsets, threads=8)
+    say(f"batch long {tuning}: {wl.n_texts} texts, {want.n} matches")
+    got, n = gpu_scan_batch(trie, wl.text, wl.offsets, pad_front=3)
+    assert n == want.n
+    assert_same(got, want, with_text=True)
 
 
 def test_batch_graph_replays_are_identical():
