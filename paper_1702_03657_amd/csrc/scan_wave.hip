@@ -35,7 +35,8 @@ namespace pfac {
 constexpr uint32_t kChunk = 1024;   // start positions per chunk (16 per lane)
 constexpr uint32_t kWin = kChunk + 16;  // chunk bytes staged in LDS (+ one vector)
 constexpr uint32_t kPPL = 4;        // start positions per lane per filter pass
-constexpr uint32_t kQ1 = 64 * kPPL; // stage-1 survivors of one pass
+constexpr uint32_t kQ1 = 64 * kPPL; // stage-1 survivors of one pass (32-bit entries)
+constexpr uint32_t kQ16 = 2 * kQ1;  // the same area as 16-bit entries
 
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t &total) {
     const uint32_t incl = wave_incl_scan(x);
@@ -420,94 +421,24 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                 w[4] = x.x; w[5] = x.y; w[6] = x.z; w[7] = x.w;
             }
 
-            // generic filter state carried across passes
-            const uint32_t b = MODE == 0 ? im.b : 8u;
-            const uint32_t m = (K >= 1 && a.fold) ? im.fold_syms : 0u;
-            const uint32_t L = K >= 1 ? K + m : 1u;
-            const uint32_t full_mask = (b * L >= 32) ? 0xffffffffu : ((1u << (b * L)) - 1u);
-            const uint32_t fmask = (a.fold - 1u) & ((b * m >= 32) ? 0xffffffffu : ((1u << (b * m)) - 1u));
-            uint32_t full = 0, run = 0;
-            if (MODE == 0) {
-                // the first L - 1 symbols of the lane window
-#pragma unroll
-                for (int j = 0; j < 15; j++) {
-                    if ((uint32_t)j + 1 >= L) continue;
-                    const uint32_t byte = wbyte(w, j);
-                    uint32_t s = byte;
-                    bool ok = true;
-                    if (!im.identity) { s = s_sym[byte]; ok = s != 0xffu; }
-                    run = ok ? run + 1 : 0u;
-                    full = ((full << b) | (s & 0xffu)) & full_mask;
-                }
-            }
-
-#pragma unroll
-            for (int pass = 0; pass < 16 / (int)kPPL; pass++) {
-                // ---- stage 1: prefix filter over kPPL start positions per lane
-                uint32_t qn = 0;
-                auto push = [&](bool hit, uint32_t entry) {
-                    const unsigned long long mk = __ballot(hit);
-                    if (hit) wq[qn + mbcnt(mk)] = entry;
-                    qn += (uint32_t)__popcll(mk);
-                };
-#pragma unroll
-                for (int jj = 0; jj < (int)kPPL; jj++) {
-                    const int j = pass * (int)kPPL + jj;
-                    if (MODE == 1 || MODE == 2) {
-                        // code = (B[j] << 8) | B[j+1]; next = B[j+2]
-                        const uint32_t lo = w[j >> 2], hi = w[(j >> 2) + 1];
-                        const uint32_t r = j & 3;
-                        const uint32_t sel = 0x0c0c0000u | (r << 8) | (r + 1);
-                        const uint32_t code = __builtin_amdgcn_perm(hi, lo, sel);
-                        const uint32_t nx = wbyte(w, j + 2);
-                        uint32_t hit;
-                        if (MODE == 1)
-                            hit = (s_ftab[code] >> (nx & 7)) & 1u;
-                        else
-                            hit = (((const uint16_t *)s_ftab)[code] >> (nx & 15)) & 1u;
-                        push(hit != 0, ((16 * lane + j) << 20) | code);
-                    } else {
-                        // the symbol at window byte j + L - 1 completes position j
-                        const uint32_t byte = wtext[16 * lane + j + L - 1];
-                        uint32_t s = byte;
-                        bool ok = true;
-                        if (!im.identity) { s = s_sym[byte]; ok = s != 0xffu; }
-                        run = ok ? run + 1 : 0u;
-                        full = ((full << b) | (s & 0xffu)) & full_mask;
-                        uint32_t hit = 0, code = 0;
-                        if (run >= L) {
-                            if (K == 0) {
-                                hit = (s_root[full >> 5] >> (full & 31)) & 1u;
-                            } else if (a.fold) {
-                                code = full >> (b * m);
-                                const uint32_t bit = full & fmask;
-                                hit = a.fold == 8 ? (s_ftab[code] >> bit) & 1u
-                                                  : (((const uint16_t *)s_ftab)[code] >> bit) & 1u;
-                            } else {
-                                code = full;
-                                hit = (s_bits[code >> 5] >> (code & 31)) & 1u;
-                            }
-                        }
-                        push(hit != 0, ((16 * lane + j) << 20) | code);
-                    }
-                }
-                wave_sync();
-
-                // ---- stage 2: exact next byte, text end, candidates
+            // ---- stage 2: the exact byte after the level index, the end of
+            // the text, and the depth-K node; survivors become candidates.
+            // decode(e) gives (window position, K-symbol code) of entry e.
+            auto stage2 = [&](uint32_t qn, auto decode) {
                 for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
                     if (cn + 64 > ccap) flush();
                     const uint32_t e = r0 + lane;
                     bool pass2 = false;
                     uint32_t entry = 0, v = 0;
                     if (e < qn) {
-                        const uint32_t ent = wq[e];
-                        const uint32_t pl = ent >> 20;
+                        const uint2 pc = decode(e);
+                        const uint32_t pl = pc.x;
                         const uint64_t p = chunk_lo + pl;
                         const uint32_t lim = limit_after(wbnd, dirty, chunk_lo, pl, next_bnd);
                         // the filter read K + 1 bytes: all must be in this text
                         pass2 = p >= lo_valid && p < hi_valid && lim > K;
                         if (pass2 && K) {
-                            const uint32_t code = ent & 0xfffffu;
+                            const uint32_t code = pc.y;
                             const uint32_t bits = s_bits[code >> 5];
                             const uint32_t below = bits & ((1u << (code & 31)) - 1u);
                             const uint32_t rank = s_rank[code >> 5] + (uint32_t)__builtin_popcount(below);
@@ -531,6 +462,110 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                     cn += (uint32_t)__popcll(mk);
                 }
                 wave_sync();
+            };
+
+            if (MODE == 1 || MODE == 2) {
+                // ---- stage 1 over the lane's 16 positions into a hit mask:
+                // code = (B[j] << 8) | B[j+1] indexes the table, B[j+2]
+                // picks the folded child bit
+                // the table is the first LDS section (offset 0), so the
+                // code is the address; all sixteen lookups are issued before
+                // any is used
+                const uint8_t *ftab0 = lds;
+                uint32_t ent[16];
+#pragma unroll
+                for (int j = 0; j < 16; j++) {
+                    const uint32_t lo = w[j >> 2], hi = w[(j >> 2) + 1];
+                    const uint32_t r = j & 3;
+                    const uint32_t code = __builtin_amdgcn_perm(hi, lo, 0x0c0c0000u | (r << 8) | (r + 1));
+                    ent[j] = MODE == 1 ? (uint32_t)ftab0[code] : (uint32_t)((const uint16_t *)ftab0)[code];
+                }
+                uint32_t hm = 0;
+#pragma unroll
+                for (int j = 0; j < 16; j++) {
+                    const uint32_t nx = __builtin_amdgcn_ubfe(w[(j + 2) >> 2], 8 * ((j + 2) & 3),
+                                                              MODE == 1 ? 3 : 4);
+                    hm |= __builtin_amdgcn_ubfe(ent[j], nx, 1) << j;
+                }
+                // compact the hits of the wave, at most kQ16 per round
+                uint16_t *wq16 = (uint16_t *)wq;
+                uint32_t tot;
+                const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
+                const int rounds = tot > kQ16 ? 2 : 1;
+                for (int half = 0; half < rounds; half++) {
+                    uint32_t mset = hm, o = off_all, qn = tot, jb = 0;
+                    if (rounds == 2) {
+                        mset = half == 0 ? (hm & 0xffu) : (hm >> 8);
+                        jb = half == 0 ? 0u : 8u;
+                        o = wave_excl_scan((uint32_t)__builtin_popcount(mset), qn);
+                    }
+                    while (mset) {
+                        const uint32_t j = (uint32_t)__builtin_ctz(mset);
+                        wq16[o++] = (uint16_t)(16 * lane + jb + j);
+                        mset &= mset - 1;
+                    }
+                    wave_sync();
+                    stage2(qn, [&](uint32_t e) {
+                        const uint32_t pl = wq16[e];
+                        return make_uint2(pl, ((uint32_t)wtext[pl] << 8) | wtext[pl + 1]);
+                    });
+                }
+            } else {
+                // generic filter: rolling code over L = K + m symbols
+                const uint32_t b = im.b;
+                const uint32_t m = (K >= 1 && a.fold) ? im.fold_syms : 0u;
+                const uint32_t L = K >= 1 ? K + m : 1u;
+                const uint32_t full_mask = (b * L >= 32) ? 0xffffffffu : ((1u << (b * L)) - 1u);
+                const uint32_t fmask = (a.fold - 1u) & ((b * m >= 32) ? 0xffffffffu : ((1u << (b * m)) - 1u));
+                uint32_t full = 0, run = 0;
+                // the first L - 1 symbols of the lane window
+#pragma unroll
+                for (int j = 0; j < 15; j++) {
+                    if ((uint32_t)j + 1 >= L) continue;
+                    const uint32_t byte = wbyte(w, j);
+                    uint32_t s = byte;
+                    bool ok = true;
+                    if (!im.identity) { s = s_sym[byte]; ok = s != 0xffu; }
+                    run = ok ? run + 1 : 0u;
+                    full = ((full << b) | (s & 0xffu)) & full_mask;
+                }
+#pragma unroll
+                for (int pass = 0; pass < 16 / (int)kPPL; pass++) {
+                    uint32_t qn = 0;
+#pragma unroll
+                    for (int jj = 0; jj < (int)kPPL; jj++) {
+                        const int j = pass * (int)kPPL + jj;
+                        // the symbol at window byte j + L - 1 completes position j
+                        const uint32_t byte = wtext[16 * lane + j + L - 1];
+                        uint32_t s = byte;
+                        bool ok = true;
+                        if (!im.identity) { s = s_sym[byte]; ok = s != 0xffu; }
+                        run = ok ? run + 1 : 0u;
+                        full = ((full << b) | (s & 0xffu)) & full_mask;
+                        uint32_t hit = 0, code = 0;
+                        if (run >= L) {
+                            if (K == 0) {
+                                hit = (s_root[full >> 5] >> (full & 31)) & 1u;
+                            } else if (a.fold) {
+                                code = full >> (b * m);
+                                const uint32_t bit = full & fmask;
+                                hit = a.fold == 8 ? (s_ftab[code] >> bit) & 1u
+                                                  : (((const uint16_t *)s_ftab)[code] >> bit) & 1u;
+                            } else {
+                                code = full;
+                                hit = (s_bits[code >> 5] >> (code & 31)) & 1u;
+                            }
+                        }
+                        const unsigned long long mk = __ballot(hit != 0);
+                        if (hit) wq[qn + mbcnt(mk)] = ((16 * lane + j) << 20) | code;
+                        qn += (uint32_t)__popcll(mk);
+                    }
+                    wave_sync();
+                    stage2(qn, [&](uint32_t e) {
+                        const uint32_t ent = wq[e];
+                        return make_uint2(ent >> 20, ent & 0xfffffu);
+                    });
+                }
             }
             cur = nxt;
             cur_h = nxt_h;
