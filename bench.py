@@ -32,7 +32,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
-KERNEL_SRC = os.path.join(ROOT, "paper_1702_03657_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1702_03657_amd", "csrc")
+# sources each scan kernel is compiled from (the traffic counts are tied to them)
+KERNEL_SOURCES = {
+    "scan_waves": ("scan_wave.hip", "kernels.hpp", "device_common.hpp"),
+    "scan_tiles": ("kernels.hip", "kernels.hpp", "device_common.hpp"),
+}
 
 WORKLOADS = {
     "c1": ("c1: 100 patterns len U[4,16] bytes U[0,255]; 1 MiB uniform text, 1000 planted copies",
@@ -44,9 +49,12 @@ WORKLOADS = {
 }
 
 
-def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_hash(kernel: str) -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def log(msg):
@@ -86,9 +94,10 @@ def choose_tuning(pf, trie, ws, text_dev, n, workload, device_name, retune):
     return best, True
 
 
-def traffic_from_profiles(workload, n_launch_bytes):
-    """HBM bytes per scan-kernel launch from committed counter summaries."""
-    path = os.path.join(ROOT, "profiles", f"traffic_scan_tiles_{workload}.json")
+def traffic_from_profiles(kernel, workload, tuning):
+    """HBM bytes per scan-kernel launch from committed counter summaries, when
+    they were taken on the current source of that kernel with the same tuning."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     try:
@@ -96,8 +105,10 @@ def traffic_from_profiles(workload, n_launch_bytes):
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_sha256_16") != kernel_hash():
+    if d.get("kernel_sha256_16") != kernel_hash(kernel):
         return None  # the kernel changed since the counters were taken
+    if d.get("tuning") != {k: int(v) for k, v in tuning.items()}:
+        return None  # taken with another launch configuration
     return d.get("hbm_bytes_per_launch")
 
 
@@ -274,7 +285,8 @@ def main():
     image_bytes = int(st["bytes_device"])
     alg_bytes = n + 16 * n_matches + image_bytes
     achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
-    traffic = traffic_from_profiles(args.workload, alg_bytes)
+    kernel_name = "scan_waves" if st["scan_kernel"] == 1 else "scan_tiles"
+    traffic = traffic_from_profiles(kernel_name, args.workload, tuning)
 
     if args.copy_probe:
         run_copy_probe(torch, n)
@@ -310,7 +322,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "scan_tiles",
+            "kernel": kernel_name,
+            "kernel_source_sha256_16": kernel_hash(kernel_name),
             "kernel_ms": round(kernel_ms, 5),
             "algorithmic_bytes_per_launch": alg_bytes,
         },

@@ -80,6 +80,8 @@ typedef struct {
     uint32_t symbol_bits;      /* bits per symbol in the level index */
     uint32_t index_depth;      /* K: levels resolved by the level index in LDS */
     uint32_t lds_bytes;        /* dynamic LDS per workgroup of the scan kernel */
+    uint32_t scan_kernel;      /* kernel the current tuning launches: 0 = tile, 1 = wave */
+    uint32_t scan_waves;       /* waves per workgroup it launches with (after LDS fitting) */
     double build_seconds;      /* host build time (not part of scan timing) */
     double upload_seconds;     /* host -> device copy time of the image */
 } pfac_stats;

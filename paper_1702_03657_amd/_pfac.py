@@ -46,6 +46,7 @@ class pfac_stats(ctypes.Structure):
         ("bytes_device", ctypes.c_uint64),
         ("alphabet_size", ctypes.c_uint32), ("symbol_bits", ctypes.c_uint32),
         ("index_depth", ctypes.c_uint32), ("lds_bytes", ctypes.c_uint32),
+        ("scan_kernel", ctypes.c_uint32), ("scan_waves", ctypes.c_uint32),
         ("build_seconds", ctypes.c_double), ("upload_seconds", ctypes.c_double),
     ]
 

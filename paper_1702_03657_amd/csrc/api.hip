@@ -274,6 +274,8 @@ static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr) {
     return a;
 }
 
+static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out);
+
 extern "C" int pfac_trie_stats(const pfac_trie *t, pfac_stats *o) {
     if (!t || !o) return PFAC_EINVAL;
     std::memset(o, 0, sizeof(*o));
@@ -294,6 +296,9 @@ extern "C" int pfac_trie_stats(const pfac_trie *t, pfac_stats *o) {
     o->symbol_bits = t->img.b;
     o->index_depth = t->img.K;
     o->lds_bytes = layout_for(t).lds_total;
+    uint32_t waves = t->tuning.waves_per_wg;
+    o->scan_kernel = use_wave_kernel(t, &waves) ? 1u : 0u;
+    o->scan_waves = o->scan_kernel ? waves : kWG / 64;
     o->build_seconds = t->build_s;
     o->upload_seconds = t->upload_s;
     return PFAC_OK;
@@ -426,7 +431,6 @@ static uint64_t tiles_for(uint64_t total, uint64_t shift, uint32_t tile) {
     return total ? (shift + total + tile - 1) / tile : 0;
 }
 
-static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out);
 
 static uint32_t unit_bytes(const pfac_trie *t) {
     return use_wave_kernel(t, nullptr) ? kWaveChunk * t->tuning.chunks_per_unit
