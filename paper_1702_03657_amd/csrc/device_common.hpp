@@ -19,14 +19,33 @@ constexpr uint32_t kCountEscD = (1u << 14) - 1;
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
 
+// x moved by a DPP control: lanes with no source lane, or masked off by
+// row_mask / bank_mask, read 0.
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ uint32_t dpp_or0(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, BANK_MASK, false);
+}
+
+// Inclusive prefix sum over the 64 lanes with DPP moves only (no LDS):
+// shifts by 1, 2, 3 inside each row of 16 lanes, then 4 and 8 over banks of
+// 4 lanes, then the last lane of rows 0 and 2 into rows 1 and 3
+// (row_bcast:15) and lane 31 into rows 2 and 3 (row_bcast:31).  Every lane
+// of the wave must be active.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t y = __shfl_up(x, off, 64);
-        if (lane >= (uint32_t)off) x += y;
-    }
-    return x;
+    uint32_t v = x;
+    v += dpp_or0<0x111, 0xf, 0xf>(x);
+    v += dpp_or0<0x112, 0xf, 0xf>(x);
+    v += dpp_or0<0x113, 0xf, 0xf>(x);
+    v += dpp_or0<0x114, 0xf, 0xe>(v);
+    v += dpp_or0<0x118, 0xf, 0xc>(v);
+    v += dpp_or0<0x142, 0xa, 0xf>(v);
+    v += dpp_or0<0x143, 0xc, 0xf>(v);
+    return v;
+}
+
+// Value of lane 63 in every lane (a scalar read).
+__device__ __forceinline__ uint32_t wave_last(uint32_t x) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)x, 63);
 }
 
 __device__ __forceinline__ unsigned long long wave_reduce_u64(unsigned long long x) {

@@ -302,9 +302,17 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
 
 // ---------------------------------------------------------------- finisher
 
+// One workgroup per 1 << kTpbShift units (one unit per thread): the units'
+// records go to out[] in unit order.  The workgroup's first output slot is
+// the sum of the block sums before it; the records are then copied with one
+// thread per record, each finding its unit by binary search over the
+// workgroup's unit starts.
 __global__ __launch_bounds__(kWG) void finish_tiles(const FinishArgs f) {
+    static_assert((1u << kTpbShift) == kWG, "one unit per thread");
     __shared__ uint32_t s_tmp[kWG / 64];
     __shared__ unsigned long long s_red[2][kWG / 64];
+    __shared__ uint32_t s_start[kWG + 1];
+    __shared__ const pfac_match *s_from[kWG];
     const uint32_t tid = threadIdx.x, b = blockIdx.x;
     unsigned long long pre = 0, all = 0;
     for (uint32_t i = tid; i < f.n_blocks; i += kWG) {
@@ -327,32 +335,34 @@ __global__ __launch_bounds__(kWG) void finish_tiles(const FinishArgs f) {
     }
     if (b == 0 && tid == 0) *f.n_matches = all;
     const uint64_t add = f.base_dev ? *f.base_dev : 0ull;
-    constexpr uint32_t TPB = 1u << kTpbShift, PER = TPB / kWG;
-    const uint64_t t0 = ((uint64_t)b << kTpbShift) + (uint64_t)tid * PER;
-    uint32_t cnt[PER];
-    uint32_t mine = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < PER; i++) {
-        const uint64_t t = t0 + i;
-        cnt[i] = t < f.n_tiles ? f.unit_count[t] : 0u;
-        mine += cnt[i];
+
+    const uint64_t t = ((uint64_t)b << kTpbShift) + tid;
+    const uint32_t cnt = t < f.n_tiles ? f.unit_count[t] : 0u;
+    const pfac_match *from = nullptr;
+    if (cnt) {
+        const uint64_t src = f.unit_off[t];
+        if (src == ~0ull)
+            from = f.inline_stage + t * f.inline_cap;
+        else if (src + cnt <= f.stage_cap)
+            from = f.stage + src;  // else the staging area overflowed: nothing to copy
     }
     uint32_t total;
-    uint64_t off = pre + add + block_excl_scan(mine, s_tmp, total);
-#pragma unroll
-    for (uint32_t i = 0; i < PER; i++) {
-        if (cnt[i]) {
-            const uint64_t src = f.unit_off[t0 + i];
-            const pfac_match *from = nullptr;
-            if (src == ~0ull)
-                from = f.inline_stage + (t0 + i) * f.inline_cap;
-            else if (src + cnt[i] <= f.stage_cap)
-                from = f.stage + src;
-            if (from)
-                for (uint32_t k = 0; k < cnt[i]; k++)
-                    if (off + k < f.capacity) f.out[off + k] = from[k];
-            off += cnt[i];
+    const uint32_t start = block_excl_scan(cnt, s_tmp, total);
+    s_start[tid] = start;
+    s_from[tid] = from;
+    if (tid == 0) s_start[kWG] = total;
+    __syncthreads();
+    const uint64_t base = pre + add;
+    for (uint32_t r = tid; r < total; r += kWG) {
+        // last unit whose start is <= r: s_start[lo] <= r < s_start[hi]
+        uint32_t lo = 0, hi = kWG;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (s_start[mid] <= r) lo = mid; else hi = mid;
         }
+        const pfac_match *src = s_from[lo];
+        const uint64_t dst = base + r;
+        if (src && dst < f.capacity) f.out[dst] = src[r - s_start[lo]];
     }
 }
 

@@ -11,7 +11,7 @@ namespace pfac {
 
 constexpr uint32_t kWG = 256;            // threads per workgroup (4 waves of 64)
 constexpr uint32_t kMatchCap = 256;      // matched positions a tile sorts in LDS
-constexpr uint32_t kTpbShift = 10;       // tiles per block-sum entry = 1024
+constexpr uint32_t kTpbShift = 8;        // units per block-sum entry = 256 = finisher threads
 constexpr uint32_t kHaloCap = 1024;      // most halo bytes staged in LDS
 constexpr uint32_t kInlineCap = 8;       // records a wave unit stages without an atomic
 

@@ -38,9 +38,16 @@ constexpr uint32_t kPPL = 4;        // start positions per lane per filter pass
 constexpr uint32_t kQ1 = 64 * kPPL; // stage-1 survivors of one pass (32-bit entries)
 constexpr uint32_t kQ16 = 2 * kQ1;  // the same area as 16-bit entries
 
+// The prefix-filter table at LDS address 0 (the first section of the dynamic
+// LDS of a kernel without static LDS; checked on the host at launch set-up).
+typedef __attribute__((address_space(3))) const uint8_t lds_u8_t;
+typedef __attribute__((address_space(3))) const uint16_t lds_u16_t;
+__device__ __forceinline__ const lds_u8_t *lds_tab8() { return (const lds_u8_t *)(uintptr_t)0; }
+__device__ __forceinline__ const lds_u16_t *lds_tab16() { return (const lds_u16_t *)(uintptr_t)0; }
+
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t &total) {
     const uint32_t incl = wave_incl_scan(x);
-    total = __shfl(incl, 63, 64);
+    total = wave_last(incl);
     return incl - x;
 }
 
@@ -311,7 +318,9 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     const uint32_t tid = threadIdx.x;
     const uint32_t nthreads = blockDim.x;
     const uint32_t waves = nthreads >> 6;
-    const uint32_t wave = tid >> 6, lane = tid & 63;
+    // the wave index is wave-uniform: keep it (and all unit bookkeeping) scalar
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
+    const uint32_t lane = tid & 63;
 
     uint8_t *s_ftab = lds + a.off_ftab;
     uint32_t *s_bits = (uint32_t *)(lds + a.off_bits);
@@ -467,18 +476,17 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             if (MODE == 1 || MODE == 2) {
                 // ---- stage 1 over the lane's 16 positions into a hit mask:
                 // code = (B[j] << 8) | B[j+1] indexes the table, B[j+2]
-                // picks the folded child bit
-                // the table is the first LDS section (offset 0), so the
-                // code is the address; all sixteen lookups are issued before
-                // any is used
-                const uint8_t *ftab0 = lds;
+                // picks the folded child bit.  The table is the first LDS
+                // section and the kernel has no static LDS, so the code is
+                // the LDS address; all sixteen lookups are issued before any
+                // is used.
                 uint32_t ent[16];
 #pragma unroll
                 for (int j = 0; j < 16; j++) {
                     const uint32_t lo = w[j >> 2], hi = w[(j >> 2) + 1];
                     const uint32_t r = j & 3;
                     const uint32_t code = __builtin_amdgcn_perm(hi, lo, 0x0c0c0000u | (r << 8) | (r + 1));
-                    ent[j] = MODE == 1 ? (uint32_t)ftab0[code] : (uint32_t)((const uint16_t *)ftab0)[code];
+                    ent[j] = MODE == 1 ? (uint32_t)lds_tab8()[code] : (uint32_t)lds_tab16()[code];
                 }
                 uint32_t hm = 0;
 #pragma unroll
@@ -492,6 +500,11 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                 uint32_t tot;
                 const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
                 const int rounds = tot > kQ16 ? 2 : 1;
+                // valid positions and the distance to the next text boundary,
+                // relative to the chunk (wave-uniform)
+                const uint32_t vlo = lo_valid > chunk_lo ? (uint32_t)min(lo_valid - chunk_lo, (uint64_t)kWin) : 0u;
+                const uint32_t vhi = hi_valid > chunk_lo ? (uint32_t)min(hi_valid - chunk_lo, (uint64_t)kWin) : 0u;
+                const uint32_t nb_rel = (uint32_t)min(next_bnd - chunk_lo, (unsigned long long)0x20000);
                 for (int half = 0; half < rounds; half++) {
                     uint32_t mset = hm, o = off_all, qn = tot, jb = 0;
                     if (rounds == 2) {
@@ -505,10 +518,47 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                         mset &= mset - 1;
                     }
                     wave_sync();
-                    stage2(qn, [&](uint32_t e) {
-                        const uint32_t pl = wq16[e];
-                        return make_uint2(pl, ((uint32_t)wtext[pl] << 8) | wtext[pl + 1]);
-                    });
+                    // ---- stage 2 (K = 2): the text's end, the exact third
+                    // byte against the depth-2 node's child labels, the node
+                    for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
+                        if (cn + 64 > ccap) flush();
+                        const uint32_t e = r0 + lane;
+                        bool pass2 = false;
+                        uint32_t entry = 0, v = 0;
+                        if (e < qn) {
+                            const uint32_t pl = wq16[e];
+                            const uint32_t a4 = pl & ~3u;
+                            const uint32_t d0 = *(const uint32_t *)(wtext + a4);
+                            const uint32_t d1 = *(const uint32_t *)(wtext + a4 + 4);
+                            const uint32_t by = __builtin_amdgcn_alignbyte(d1, d0, pl & 3u);  // B[pl..pl+3]
+                            const uint32_t lim = dirty ? limit_after(wbnd, dirty, chunk_lo, pl, next_bnd)
+                                                       : min(nb_rel - pl, 0xffffu);
+                            pass2 = pl >= vlo && pl < vhi && lim > 2u;
+                            if (pass2) {
+                                const uint32_t code = __builtin_amdgcn_perm(0u, by, 0x0c0c0001u);
+                                const uint32_t bits = s_bits[code >> 5];
+                                const uint32_t rank = s_rank[code >> 5] +
+                                    (uint32_t)__builtin_popcount(bits & ((1u << (code & 31)) - 1u));
+                                v = im.lvl_start + rank;
+                                if (krec) {
+                                    // up to three child labels, or a count above 3
+                                    const uint32_t rec = s_krec[rank];
+                                    const uint32_t ncc = rec >> 24;
+                                    if (ncc <= 3) {
+                                        const uint32_t c = (by >> 16) & 0xffu;
+                                        const uint32_t x = rec ^ (c * 0x00010101u);
+                                        const uint32_t mm = (x - 0x00010101u) & ~x & 0x00808080u;
+                                        pass2 = mm != 0 && ((uint32_t)__builtin_ctz(mm) >> 3) < ncc;
+                                    }
+                                }
+                            }
+                            entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
+                        }
+                        const unsigned long long mk = __ballot(pass2);
+                        if (pass2) wc[cn + mbcnt(mk)] = make_uint2(entry, v);
+                        cn += (uint32_t)__popcll(mk);
+                    }
+                    wave_sync();
                 }
             } else {
                 // generic filter: rolling code over L = K + m symbols
@@ -613,6 +663,7 @@ void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit) {
 }
 
 int wave_mode(const ScanArgs &a) {
+    if (a.off_ftab != 0) return 0;  // modes 1 and 2 need the table at LDS address 0
     if (a.im.identity && a.im.K == 2 && a.fold == 8 && a.im.fold_syms == 1) return 1;
     if (a.im.identity && a.im.K == 2 && a.fold == 16 && a.im.fold_syms == 1) return 2;
     return 0;
@@ -632,6 +683,12 @@ static const void *wave_fn_for(int mode) {
 }
 
 hipError_t prepare_wave_kernel(int mode, uint32_t lds_bytes) {
+    // modes 1 and 2 address the filter table at LDS address 0: the kernel
+    // must have no static LDS in front of the dynamic area
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, wave_fn_for(mode));
+    if (e != hipSuccess) return e;
+    if (attr.sharedSizeBytes != 0) return hipErrorInvalidKernelFile;
     return hipFuncSetAttribute(wave_fn_for(mode), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)lds_bytes);
 }
