@@ -109,8 +109,10 @@ static inline uint64_t hmix(uint64_t x) {
     return x;
 }
 
-static const pset *g_sort_P;
-static uint32_t g_sort_m;
+/* qsort has no context argument: the key parameters are per thread, since
+ * the exhaustive check builds indexes on several threads at once */
+static _Thread_local const pset *g_sort_P;
+static _Thread_local uint32_t g_sort_m;
 static int cmp_key_id(const void *a, const void *b) {
     uint32_t ja = *(const uint32_t *)a, jb = *(const uint32_t *)b;
     uint64_t ka = load_key(pbytes(g_sort_P, ja), g_sort_m);
