@@ -72,6 +72,7 @@ struct pfac_trie {
 
 struct pfac_workspace {
     DeviceBuf stage, unit_count, unit_off, blocksum, tile_first, inline_stage, misc;
+    DeviceBuf cand, cand_count;  // split wave kernels: walk candidates per unit
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // optional kernel timing
     // misc: [0] stage cursor, [1] running total, [2] per-launch count
     unsigned long long *cursor() { return (unsigned long long *)misc.p; }
@@ -256,13 +257,13 @@ static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr) {
     a.im.fold_syms = t->img.fold_syms;
     a.halo = t->halo;
     uint32_t waves = t->tuning.waves_per_wg;
-    if (t->tuning.kernel == 1) {
+    if (t->tuning.kernel >= 1) {
         a.fold = t->img.fold_bits;
         a.group = t->tuning.chunks_per_unit;
         for (int with_rec = (t->tuning.child_check && t->img.K) ? 1 : 0; with_rec >= 0; with_rec--) {
             a.krec_words = with_rec ? (uint32_t)t->img.krec.size() : 0u;
             for (waves = t->tuning.waves_per_wg; waves >= 4; waves -= 4) {
-                wave_lds_layout(a, waves, t->lds_limit);
+                wave_lds_layout(a, waves, t->lds_limit, t->tuning.kernel == 2);
                 if (a.lds_total <= t->lds_limit) break;
             }
             if (a.lds_total <= t->lds_limit) break;
@@ -297,7 +298,7 @@ extern "C" int pfac_trie_stats(const pfac_trie *t, pfac_stats *o) {
     o->index_depth = t->img.K;
     o->lds_bytes = layout_for(t).lds_total;
     uint32_t waves = t->tuning.waves_per_wg;
-    o->scan_kernel = use_wave_kernel(t, &waves) ? 1u : 0u;
+    o->scan_kernel = use_wave_kernel(t, &waves) ? t->tuning.kernel : 0u;
     o->scan_waves = o->scan_kernel ? waves : kWG / 64;
     o->build_seconds = t->build_s;
     o->upload_seconds = t->upload_s;
@@ -330,7 +331,7 @@ extern "C" int pfac_trie_get_tuning(const pfac_trie *t, pfac_tuning *out) {
 }
 
 static bool valid_tuning(const pfac_tuning *p) {
-    return p->kernel <= 1 &&
+    return p->kernel <= 2 &&
            (p->bytes_per_lane == 4 || p->bytes_per_lane == 8 || p->bytes_per_lane == 16) &&
            p->index_bits >= 1 && p->index_bits <= 18 &&
            (p->fold_bits == 0 || p->fold_bits == 8 || p->fold_bits == 16) && p->wg_per_cu <= 8 &&
@@ -379,18 +380,28 @@ extern "C" void pfac_workspace_free(pfac_workspace *w) {
     w->blocksum.release();
     w->tile_first.release();
     w->inline_stage.release();
+    w->cand.release();
+    w->cand_count.release();
     w->misc.release();
     delete w;
 }
 
-static int ws_reserve(pfac_workspace *w, uint64_t n_tiles, uint64_t capacity) {
-    uint64_t n_blocks = std::max<uint64_t>(1, (n_tiles + (1u << kTpbShift) - 1) >> kTpbShift);
+// n_tiles: units (or 1 KiB chunks of the wave kernels, at least as many);
+// split: also the candidate lists of the split wave kernels.
+static int ws_reserve(pfac_workspace *w, uint64_t n_tiles, uint64_t capacity, bool split) {
+    uint64_t n_sums = std::max<uint64_t>(1, (n_tiles + (1u << kSumShift) - 1) >> kSumShift);
     HIP_TRY(w->unit_count.reserve(std::max<uint64_t>(n_tiles, 1) * 4));
     HIP_TRY(w->unit_off.reserve(std::max<uint64_t>(n_tiles, 1) * 8));
     HIP_TRY(w->tile_first.reserve(std::max<uint64_t>(n_tiles, 1) * 4));
-    HIP_TRY(w->blocksum.reserve(n_blocks * 8));
+    HIP_TRY(w->blocksum.reserve(n_sums * 8));
     HIP_TRY(w->stage.reserve(std::max<uint64_t>(capacity, 1) * sizeof(pfac_match)));
-    HIP_TRY(w->inline_stage.reserve(std::max<uint64_t>(n_tiles, 1) * kInlineCap * sizeof(pfac_match)));
+    // wave kernels: max(kInlineCap, kInlinePerChunk * G) slots per unit of G
+    // chunks, at most kInlineCap per chunk
+    HIP_TRY(w->inline_stage.reserve((n_tiles + 64) * kInlineCap * sizeof(pfac_match)));
+    if (split) {
+        HIP_TRY(w->cand.reserve((n_tiles + 64) * kCandPerChunk * 16));
+        HIP_TRY(w->cand_count.reserve(std::max<uint64_t>(n_tiles, 1) * 4));
+    }
     return PFAC_OK;
 }
 
@@ -406,7 +417,7 @@ extern "C" int pfac_workspace_reserve(pfac_workspace *w, uint64_t max_bytes, uin
     (void)max_texts;
     if (!w) return PFAC_EINVAL;
     uint64_t n_tiles = (max_bytes + 16 + kWG * 4 - 1) / (kWG * 4);  // smallest tile
-    return ws_reserve(w, n_tiles, max_matches);
+    return ws_reserve(w, n_tiles, max_matches, true);
 }
 
 // ---------------------------------------------------------------------- scan
@@ -440,7 +451,7 @@ static uint32_t unit_bytes(const pfac_trie *t) {
 // Opt a kernel into more than 64 KiB of dynamic LDS (once per size).
 static hipError_t grant_lds(int slot, uint32_t bytes, hipError_t (*fn)(int, uint32_t), int arg) {
     static std::mutex mu;
-    static uint32_t granted[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    static uint32_t granted[16] = {};
     std::lock_guard<std::mutex> lock(mu);
     if (granted[slot] >= bytes) return hipSuccess;
     hipError_t e = fn(arg, bytes);
@@ -453,16 +464,19 @@ static hipError_t prep_wave(int mode, uint32_t bytes) { return prepare_wave_kern
 
 // Wave kernel when asked for and its LDS layout fits; the tile kernel otherwise.
 static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out) {
-    if (t->tuning.kernel != 1) return false;
+    if (t->tuning.kernel != 1 && t->tuning.kernel != 2) return false;
     if (t->crs.max_len > 0xffff) return false;  // walk limits are 16-bit
     const ScanArgs a = layout_for(t, waves_out);
     return a.lds_total <= t->lds_limit;
 }
 
+static bool uses_split(const pfac_trie *t) { return t->tuning.kernel == 2 && use_wave_kernel(t, nullptr); }
+
 static int enqueue_scan(const Launch &L, bool reserve) {
     const pfac_trie *t = L.t;
     uint32_t waves = t->tuning.waves_per_wg;
     const bool wave_kernel = use_wave_kernel(t, &waves);
+    const bool split = wave_kernel && t->tuning.kernel == 2;
     const uint32_t bpl = t->tuning.bytes_per_lane;
     const uint32_t tile = wave_kernel ? kWaveChunk * t->tuning.chunks_per_unit : kWG * bpl;
     const uintptr_t addr = (uintptr_t)L.text;
@@ -473,11 +487,11 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     const uint32_t plan_unit = wave_kernel ? kWaveChunk : tile;
     const uint64_t n_plan = n_tiles ? tiles_for(L.total, shift, plan_unit) : 0;
     if (reserve) {
-        int rc = ws_reserve(L.w, std::max(n_tiles, n_plan), L.capacity);
+        int rc = ws_reserve(L.w, std::max(n_tiles, n_plan), L.capacity, split);
         if (rc != PFAC_OK) return rc;
     }
     pfac_workspace *w = L.w;
-    const uint32_t n_blocks = (uint32_t)std::max<uint64_t>(1, (n_tiles + (1u << kTpbShift) - 1) >> kTpbShift);
+    const uint32_t n_sums = (uint32_t)std::max<uint64_t>(1, (n_tiles + (1u << kSumShift) - 1) >> kSumShift);
 
     ScanArgs a = layout_for(t, &waves);
     a.im = t->view;
@@ -497,10 +511,17 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     a.blocksum = (unsigned long long *)w->blocksum.p;
     a.counts = L.counts;
     a.inline_stage = (pfac_match *)w->inline_stage.p;
-    a.inline_cap = wave_kernel ? kInlineCap : 0;
+    a.inline_cap = wave_kernel ? std::max(kInlineCap, kInlinePerChunk * t->tuning.chunks_per_unit) : 0;
+    if (split) {
+        a.cand = (uint4 *)w->cand.p;
+        a.cand_count = (uint32_t *)w->cand_count.p;
+        a.cand_cap = a.group * kCandPerChunk;
+    }
     if (a.lds_total > t->lds_limit) return PFAC_EINVAL;
 
-    HIP_TRY(launch_reset(a.stage_cursor, a.blocksum, n_blocks, L.s));
+    a.n_sums = n_sums;
+    // the split filter kernel clears the block sums and the cursor itself
+    if (!(split && n_tiles)) HIP_TRY(launch_reset(a.stage_cursor, a.blocksum, n_sums, L.s));
     if (L.counts) HIP_TRY(launch_fill_u32(L.counts, L.total, 0, L.s));
     if (n_tiles) {
         if (L.offsets)
@@ -529,6 +550,7 @@ static int enqueue_scan(const Launch &L, bool reserve) {
         else
             HIP_TRY(launch_scan(a, bpl, grid, L.s));
         if (w->ev_stop) HIP_TRY(hipEventRecord(w->ev_stop, L.s));
+        if (split) HIP_TRY(launch_walk_units(a, L.s));
     }
     FinishArgs f{};
     f.unit_count = a.unit_count;
@@ -537,7 +559,7 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     f.stage = a.stage;
     f.stage_cap = a.stage_cap;
     f.n_tiles = n_tiles;
-    f.n_blocks = n_blocks;
+    f.n_sums = n_sums;
     f.out = L.out;
     f.capacity = L.out ? L.capacity : 0;
     f.n_matches = L.n_matches;
@@ -606,7 +628,7 @@ extern "C" int pfac_scan_batch_plain(const pfac_trie *t, pfac_workspace *w,
         max_tiles = std::max(max_tiles, tiles_for(offsets_host[i + 1] - offsets_host[i], 15,
                                                   std::min(unit_bytes(t), kWaveChunk)));
     }
-    rc = ws_reserve(w, max_tiles, capacity);
+    rc = ws_reserve(w, max_tiles, capacity, uses_split(t));
     if (rc) return rc;
     HIP_TRY(launch_fill_u32((uint32_t *)w->running(), 2, 0, s));
     for (uint32_t i = 0; i < n_texts; i++) {
@@ -634,7 +656,8 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
     int rc = check_scan_args(t, w, texts_dev, total_bytes, out_dev, capacity, n_matches_dev);
     if (rc) return rc;
     if (!offsets_dev) return PFAC_EINVAL;
-    rc = ws_reserve(w, tiles_for(total_bytes, 15, std::min(unit_bytes(t), kWaveChunk)), capacity);
+    rc = ws_reserve(w, tiles_for(total_bytes, 15, std::min(unit_bytes(t), kWaveChunk)), capacity,
+                    uses_split(t));
     if (rc) return rc;
     hipStream_t s = (hipStream_t)stream;
     hipStream_t own = nullptr;
@@ -740,9 +763,11 @@ extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *tex
     std::vector<pfac_tuning> cands;
     for (uint32_t bits : {12u, 16u, 18u}) {
         for (uint32_t fold : {8u, 16u, 0u})
-            for (uint32_t waves : {8u, 16u})
-                for (uint32_t g : {4u, 16u})
-                    for (uint32_t cc : {0u, 1u}) cands.push_back({1, 16, bits, fold, 0, waves, g, cc});
+            for (uint32_t kernel : {1u, 2u})
+                for (uint32_t waves : {8u, 16u})
+                    for (uint32_t g : {4u, 16u, 32u})
+                        for (uint32_t cc : {0u, 1u})
+                            cands.push_back({kernel, 16, bits, fold, 0, waves, g, cc});
         for (uint32_t bpl : {8u, 16u}) cands.push_back({0, bpl, bits, 8, 0, 16, 16, 1});
     }
     float best_ms = 1e30f;

@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
                 const unsigned long long base = atomicAdd(a.stage_cursor, (unsigned long long)total);
                 a.unit_count[t] = total;
                 a.unit_off[t] = base;
-                atomicAdd(&a.blocksum[t >> kTpbShift], (unsigned long long)total);
+                atomicAdd(&a.blocksum[t >> kSumShift], (unsigned long long)total);
                 s_base = base;
             }
             __syncthreads();
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
                 const unsigned long long base = atomicAdd(a.stage_cursor, (unsigned long long)total);
                 a.unit_count[t] = total;
                 a.unit_off[t] = base;
-                atomicAdd(&a.blocksum[t >> kTpbShift], (unsigned long long)total);
+                atomicAdd(&a.blocksum[t >> kSumShift], (unsigned long long)total);
                 s_base = base;
             }
             __syncthreads();
@@ -302,20 +302,20 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
 
 // ---------------------------------------------------------------- finisher
 
-// One workgroup per 1 << kTpbShift units (one unit per thread): the units'
+// One workgroup per block-sum entry (1 << kSumShift units): the units'
 // records go to out[] in unit order.  The workgroup's first output slot is
-// the sum of the block sums before it; the records are then copied with one
-// thread per record, each finding its unit by binary search over the
-// workgroup's unit starts.
+// the sum of the block sums before it; its first wave scans the units'
+// counts, then every thread copies records, each finding its unit by binary
+// search over the unit starts.
 __global__ __launch_bounds__(kWG) void finish_tiles(const FinishArgs f) {
-    static_assert((1u << kTpbShift) == kWG, "one unit per thread");
-    __shared__ uint32_t s_tmp[kWG / 64];
+    constexpr uint32_t kUnits = 1u << kSumShift;
+    static_assert(kUnits <= 64, "one wave scans the units");
     __shared__ unsigned long long s_red[2][kWG / 64];
-    __shared__ uint32_t s_start[kWG + 1];
-    __shared__ const pfac_match *s_from[kWG];
+    __shared__ uint32_t s_start[kUnits + 1];
+    __shared__ const pfac_match *s_from[kUnits];
     const uint32_t tid = threadIdx.x, b = blockIdx.x;
     unsigned long long pre = 0, all = 0;
-    for (uint32_t i = tid; i < f.n_blocks; i += kWG) {
+    for (uint32_t i = tid; i < f.n_sums; i += kWG) {
         const unsigned long long s = f.blocksum[i];
         all += s;
         if (i < b) pre += s;
@@ -326,6 +326,24 @@ __global__ __launch_bounds__(kWG) void finish_tiles(const FinishArgs f) {
         s_red[0][tid >> 6] = pre;
         s_red[1][tid >> 6] = all;
     }
+    if (tid < 64) {
+        const uint64_t t = ((uint64_t)b << kSumShift) + tid;
+        const uint32_t cnt = (tid < kUnits && t < f.n_tiles) ? f.unit_count[t] : 0u;
+        const pfac_match *from = nullptr;
+        if (cnt) {
+            const uint64_t src = f.unit_off[t];
+            if (src == ~0ull)
+                from = f.inline_stage + t * f.inline_cap;
+            else if (src + cnt <= f.stage_cap)
+                from = f.stage + src;  // else the staging area overflowed: nothing to copy
+        }
+        const uint32_t incl = wave_incl_scan(cnt);
+        if (tid < kUnits) {
+            s_start[tid] = incl - cnt;
+            s_from[tid] = from;
+        }
+        if (tid == kUnits - 1) s_start[kUnits] = incl;
+    }
     __syncthreads();
     pre = 0;
     all = 0;
@@ -334,28 +352,11 @@ __global__ __launch_bounds__(kWG) void finish_tiles(const FinishArgs f) {
         all += s_red[1][i];
     }
     if (b == 0 && tid == 0) *f.n_matches = all;
-    const uint64_t add = f.base_dev ? *f.base_dev : 0ull;
-
-    const uint64_t t = ((uint64_t)b << kTpbShift) + tid;
-    const uint32_t cnt = t < f.n_tiles ? f.unit_count[t] : 0u;
-    const pfac_match *from = nullptr;
-    if (cnt) {
-        const uint64_t src = f.unit_off[t];
-        if (src == ~0ull)
-            from = f.inline_stage + t * f.inline_cap;
-        else if (src + cnt <= f.stage_cap)
-            from = f.stage + src;  // else the staging area overflowed: nothing to copy
-    }
-    uint32_t total;
-    const uint32_t start = block_excl_scan(cnt, s_tmp, total);
-    s_start[tid] = start;
-    s_from[tid] = from;
-    if (tid == 0) s_start[kWG] = total;
-    __syncthreads();
-    const uint64_t base = pre + add;
+    const uint64_t base = pre + (f.base_dev ? *f.base_dev : 0ull);
+    const uint32_t total = s_start[kUnits];
     for (uint32_t r = tid; r < total; r += kWG) {
         // last unit whose start is <= r: s_start[lo] <= r < s_start[hi]
-        uint32_t lo = 0, hi = kWG;
+        uint32_t lo = 0, hi = kUnits;
         while (hi - lo > 1) {
             const uint32_t mid = (lo + hi) >> 1;
             if (s_start[mid] <= r) lo = mid; else hi = mid;
@@ -369,9 +370,9 @@ __global__ __launch_bounds__(kWG) void finish_tiles(const FinishArgs f) {
 // ------------------------------------------------------------ small kernels
 
 __global__ void reset_kernel(unsigned long long *cursor, unsigned long long *blocksum,
-                             uint32_t n_blocks) {
+                             uint32_t n_sums) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *cursor = 0;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_blocks;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_sums;
          i += gridDim.x * blockDim.x)
         blocksum[i] = 0;
 }
@@ -476,14 +477,14 @@ int max_wg_per_cu(uint32_t bpl, uint32_t lds_bytes) {
 }
 
 hipError_t launch_finish(const FinishArgs &f, hipStream_t s) {
-    hipLaunchKernelGGL(finish_tiles, dim3(f.n_blocks), dim3(kWG), 0, s, f);
+    hipLaunchKernelGGL(finish_tiles, dim3(f.n_sums), dim3(kWG), 0, s, f);
     return hipGetLastError();
 }
 
 hipError_t launch_reset(unsigned long long *cursor, unsigned long long *blocksum,
-                        uint32_t n_blocks, hipStream_t s) {
-    const uint32_t grid = (n_blocks + 255) / 256 + 1;
-    hipLaunchKernelGGL(reset_kernel, dim3(grid), dim3(256), 0, s, cursor, blocksum, n_blocks);
+                        uint32_t n_sums, hipStream_t s) {
+    const uint32_t grid = (n_sums + 255) / 256 + 1;
+    hipLaunchKernelGGL(reset_kernel, dim3(grid), dim3(256), 0, s, cursor, blocksum, n_sums);
     return hipGetLastError();
 }
 

@@ -11,9 +11,10 @@ namespace pfac {
 
 constexpr uint32_t kWG = 256;            // threads per workgroup (4 waves of 64)
 constexpr uint32_t kMatchCap = 256;      // matched positions a tile sorts in LDS
-constexpr uint32_t kTpbShift = 8;        // units per block-sum entry = 256 = finisher threads
+constexpr uint32_t kSumShift = 5;        // units per block-sum entry and finisher workgroup = 32
 constexpr uint32_t kHaloCap = 1024;      // most halo bytes staged in LDS
-constexpr uint32_t kInlineCap = 8;       // records a wave unit stages without an atomic
+constexpr uint32_t kInlineCap = 8;       // records a wave unit stages without an atomic (at least)
+constexpr uint32_t kInlinePerChunk = 2;  // ... and per 1 KiB chunk of the unit
 
 // Device image as the kernels see it (pointers into one device allocation).
 struct ImageView {
@@ -56,10 +57,17 @@ struct ScanArgs {
     unsigned long long *stage_cursor;
     uint32_t *unit_count;             // per tile
     unsigned long long *unit_off;     // per tile
-    unsigned long long *blocksum;     // per 1 << kTpbShift tiles
+    unsigned long long *blocksum;     // per 1 << kSumShift units
     uint32_t *counts;                 // optional per-position counts
     pfac_match *inline_stage;         // wave kernel: inline_cap records per chunk
     uint64_t inline_cap;
+    // split wave kernels: walk candidates of unit u at cand[u * cand_cap ..)
+    // as {unit position | limit << 16, depth-K node, 8 text bytes after the
+    // index}, their number in cand_count[u] (above cand_cap: overflowed)
+    uint4 *cand;
+    uint32_t *cand_count;
+    uint32_t cand_cap;
+    uint32_t n_sums;                  // split filter kernel: clears blocksum[0 .. n_sums) and the cursor
 };
 
 struct FinishArgs {
@@ -69,7 +77,7 @@ struct FinishArgs {
     const pfac_match *stage;
     uint64_t stage_cap;
     uint64_t n_tiles;
-    uint32_t n_blocks;
+    uint32_t n_sums;                  // block-sum entries = finisher workgroups: 1 << kSumShift units each
     pfac_match *out;
     uint64_t capacity;
     uint64_t *n_matches;              // receives this launch's match count
@@ -82,7 +90,7 @@ struct FinishArgs {
 void lds_layout(ScanArgs &a, uint32_t bpl);
 
 hipError_t launch_reset(unsigned long long *stage_cursor, unsigned long long *blocksum,
-                        uint32_t n_blocks, hipStream_t s);
+                        uint32_t n_sums, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_plan(const uint64_t *offsets, uint32_t n_texts, uint64_t shift,
                        uint64_t n_tiles, uint32_t tile, uint32_t *tile_first_text,
@@ -95,10 +103,13 @@ hipError_t launch_copy_u64(uint64_t *dst, const unsigned long long *src, hipStre
 // Wave kernel: LDS layout for `waves` waves within `lds_limit` bytes, launch,
 // and occupancy.
 constexpr uint32_t kWaveChunk = 1024;
-void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit);
+constexpr uint32_t kCandPerChunk = 32;   // split kernels: candidate slots per 1 KiB chunk
+constexpr uint32_t kWalkWaves = 4;       // waves per workgroup of the walk kernel
+void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit, bool split);
 int wave_mode(const ScanArgs &a);
 hipError_t prepare_wave_kernel(int mode, uint32_t lds_bytes);
 hipError_t launch_scan_waves(const ScanArgs &a, uint32_t waves, uint32_t grid, hipStream_t s);
+hipError_t launch_walk_units(const ScanArgs &a, hipStream_t s);
 int max_wave_wg_per_cu(const ScanArgs &a, uint32_t waves);
 
 // Largest resident workgroups per CU for this layout.

@@ -240,7 +240,7 @@ __device__ __forceinline__ void emit_unit(const ScanArgs &a, uint64_t u, uint64_
         if (lane == 0) {
             a.unit_count[u] = total;
             a.unit_off[u] = ~0ull;
-            atomicAdd(&a.blocksum[u >> kTpbShift], (unsigned long long)total);
+            atomicAdd(&a.blocksum[u >> kSumShift], (unsigned long long)total);
         }
     } else {
         unsigned long long b = 0;
@@ -248,7 +248,7 @@ __device__ __forceinline__ void emit_unit(const ScanArgs &a, uint64_t u, uint64_
             b = atomicAdd(a.stage_cursor, (unsigned long long)total);
             a.unit_count[u] = total;
             a.unit_off[u] = b;
-            atomicAdd(&a.blocksum[u >> kTpbShift], (unsigned long long)total);
+            atomicAdd(&a.blocksum[u >> kSumShift], (unsigned long long)total);
         }
         base = __shfl(b, 0, 64);
         dst = a.stage;
@@ -301,7 +301,7 @@ __device__ __forceinline__ void unit_from_root(const ScanArgs &a, uint64_t u, ui
                 b = atomicAdd(a.stage_cursor, (unsigned long long)total);
                 a.unit_count[u] = total;
                 a.unit_off[u] = b;
-                if (total) atomicAdd(&a.blocksum[u >> kTpbShift], (unsigned long long)total);
+                if (total) atomicAdd(&a.blocksum[u >> kSumShift], (unsigned long long)total);
             }
             base = __shfl(b, 0, 64);
         }
@@ -311,7 +311,10 @@ __device__ __forceinline__ void unit_from_root(const ScanArgs &a, uint64_t u, ui
 // MODE 1: byte symbols, K = 2, 8-bit folded table.  MODE 2: same, 16-bit.
 // MODE 0: any image (symbol table, any K, table or plain level bitmap, or
 // the root bitmap when K = 0).
-template <int MODE>
+// SPLIT: stop after stage 2 and write each unit's walk candidates to global
+// memory for walk_units (the walks then run at the occupancy of a kernel
+// without the LDS tables); otherwise walk and emit here.
+template <int MODE, bool SPLIT>
 __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     const ImageView &im = a.im;
@@ -328,6 +331,14 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     uint32_t *s_root = (uint32_t *)(lds + a.off_root);
     uint32_t *s_krec = (uint32_t *)(lds + a.off_krec);
     uint8_t *s_sym = lds + a.off_sym;
+
+    // the split path needs no reset kernel: the walk kernel, the first to
+    // count into them, starts after this kernel ends
+    if (SPLIT) {
+        const uint32_t gt = blockIdx.x * nthreads + tid;
+        if (gt == 0) *a.stage_cursor = 0;
+        for (uint32_t i = gt; i < a.n_sums; i += gridDim.x * nthreads) a.blocksum[i] = 0;
+    }
 
     // ---- shared tables, once per workgroup
     for (uint32_t i = tid; i < a.ftab_bytes / 16; i += nthreads)
@@ -372,19 +383,68 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     };
 
     uint64_t u = (uint64_t)blockIdx.x * waves + wave;
-    uint4 cur = make_uint4(0, 0, 0, 0), cur_h = make_uint4(0, 0, 0, 0);
-    if (u < n_units) {
-        const uint64_t lo = u * G * kChunk;
-        cur = load_vec(lo + 16ull * lane);
-        if (lane == 0) cur_h = load_vec(lo + kChunk);
-    }
+    // The wave's chunks in order (units u, u + stride, ...; chunks 0..nch-1
+    // of each), loaded two ahead of the one being filtered.  The 16 bytes
+    // after a chunk are the next chunk's first vector (lane 0), except after
+    // the last chunk of a unit, where lane 0 loads them with the chunk.
+    uint64_t pu = u;
+    uint32_t pg = 0;
+    struct Vec2 {
+        uint4 v, h;
+    };
+    uint32_t pn = pu < n_units ? unit_chunks(pu) : 0u;  // chunks of unit pu
+    auto prefetch = [&]() -> Vec2 {
+        Vec2 r;
+        r.v = make_uint4(0, 0, 0, 0);
+        r.h = r.v;
+        if (pu < n_units) {
+            const uint64_t lo = (pu * G + pg) * kChunk;
+            // every 16-byte block of an inner chunk holds text: no lane checks
+            if (lo + 16 > lo_valid && lo + kChunk - 16 < hi_valid)
+                r.v = *(const uint4 *)(a.base + lo + 16 * lane);
+            else
+                r.v = load_vec(lo + 16ull * lane);
+            if (pg + 1 >= pn && lane == 0) r.h = load_vec(lo + kChunk);
+            if (++pg >= pn) {
+                pg = 0;
+                pu += stride;
+                pn = pu < n_units ? unit_chunks(pu) : 0u;
+            }
+        }
+        return r;
+    };
+    Vec2 c0 = prefetch(), c1 = prefetch();
+    uint4 cur = c0.v, cur_h = c0.h, nxt = c1.v, nxt_h = c1.h;
     for (; u < n_units; u += stride) {
         const uint64_t unit_lo = u * G * kChunk;
         const uint32_t nch = unit_chunks(u);
         uint32_t cn = 0, mn = 0;   // candidates, matches (wave-uniform)
+        uint4 *const wcg = SPLIT ? a.cand + u * a.cand_cap : nullptr;
+        // queue a candidate (ballot mask mk over the wave); the split kernels
+        // also pass on the 8 text bytes after the level index, B[pl+K ..
+        // pl+K+8), so that short walks read no text from global memory
+        auto push = [&](bool pass, unsigned long long mk, uint32_t entry, uint32_t v, uint32_t pl) {
+            const uint32_t idx = cn + mbcnt(mk);
+            if (pass) {
+                if (!SPLIT) {
+                    wc[idx] = make_uint2(entry, v);
+                } else if (idx < a.cand_cap) {
+                    // bytes at or past kWin are not text of this window;
+                    // the walk knows how many are valid
+                    const uint32_t q = pl + K, q4 = q & ~3u;
+                    const uint32_t e0 = *(const uint32_t *)(wtext + q4);
+                    const uint32_t e1 = *(const uint32_t *)(wtext + q4 + 4);
+                    const uint32_t e2 = *(const uint32_t *)(wtext + q4 + 8);
+                    wcg[idx] = make_uint4(entry, v, __builtin_amdgcn_alignbyte(e1, e0, q & 3u),
+                                          __builtin_amdgcn_alignbyte(e2, e1, q & 3u));
+                }
+            }
+            cn += (uint32_t)__popcll(mk);
+        };
 
         // walk every queued candidate; matches go to wm
         auto flush = [&]() {
+            if (SPLIT) return;
             for (uint32_t r0 = 0; r0 < cn; r0 += 64) {
                 const uint32_t e = r0 + lane;
                 uint2 h = make_uint2(0, 0);
@@ -407,18 +467,16 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
 
         for (uint32_t g = 0; g < nch; g++) {
             const uint64_t chunk_lo = unit_lo + (uint64_t)g * kChunk;
-            // next chunk's text, in flight while this one is filtered
-            uint64_t nlo = ~0ull;
-            if (g + 1 < nch) nlo = chunk_lo + kChunk;
-            else if (u + stride < n_units) nlo = (u + stride) * G * kChunk;
-            uint4 nxt = make_uint4(0, 0, 0, 0), nxt_h = make_uint4(0, 0, 0, 0);
-            if (nlo != ~0ull) {
-                nxt = load_vec(nlo + 16ull * lane);
-                if (lane == 0) nxt_h = load_vec(nlo + kChunk);
-            }
+            // the chunk after next, in flight while this one is filtered
+            const Vec2 c2 = prefetch();
+            const uint4 nx2 = c2.v, nx2_h = c2.h;
 
             *(uint4 *)(wtext + 16 * lane) = cur;
-            if (lane == 0) *(uint4 *)(wtext + kChunk) = cur_h;
+            if (lane == 0) {
+                const bool more = g + 1 < nch;  // the next chunk follows this one
+                *(uint4 *)(wtext + kChunk) = make_uint4(more ? nxt.x : cur_h.x, more ? nxt.y : cur_h.y,
+                                                        more ? nxt.z : cur_h.z, more ? nxt.w : cur_h.w);
+            }
             bool dirty;
             unsigned long long next_bnd;
             chunk_bounds(a, chunk_lo / kChunk, chunk_lo, wbnd, dirty, next_bnd);
@@ -435,7 +493,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             // decode(e) gives (window position, K-symbol code) of entry e.
             auto stage2 = [&](uint32_t qn, auto decode) {
                 for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
-                    if (cn + 64 > ccap) flush();
+                    if (!SPLIT && cn + 64 > ccap) flush();
                     const uint32_t e = r0 + lane;
                     bool pass2 = false;
                     uint32_t entry = 0, v = 0;
@@ -466,9 +524,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                         }
                         entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
                     }
-                    const unsigned long long mk = __ballot(pass2);
-                    if (pass2) wc[cn + mbcnt(mk)] = make_uint2(entry, v);
-                    cn += (uint32_t)__popcll(mk);
+                    push(pass2, __ballot(pass2), entry, v, entry & (kChunk - 1));
                 }
                 wave_sync();
             };
@@ -521,7 +577,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                     // ---- stage 2 (K = 2): the text's end, the exact third
                     // byte against the depth-2 node's child labels, the node
                     for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
-                        if (cn + 64 > ccap) flush();
+                        if (!SPLIT && cn + 64 > ccap) flush();
                         const uint32_t e = r0 + lane;
                         bool pass2 = false;
                         uint32_t entry = 0, v = 0;
@@ -554,9 +610,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                             }
                             entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
                         }
-                        const unsigned long long mk = __ballot(pass2);
-                        if (pass2) wc[cn + mbcnt(mk)] = make_uint2(entry, v);
-                        cn += (uint32_t)__popcll(mk);
+                        push(pass2, __ballot(pass2), entry, v, entry & (kChunk - 1));
                     }
                     wave_sync();
                 }
@@ -619,6 +673,12 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             }
             cur = nxt;
             cur_h = nxt_h;
+            nxt = nx2;
+            nxt_h = nx2_h;
+        }
+        if (SPLIT) {
+            if (lane == 0) a.cand_count[u] = cn;
+            continue;
         }
         flush();
         wave_sync();
@@ -632,9 +692,138 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     }
 }
 
+// Walks of the split path: one wave per unit walks the unit's candidates
+// (stage-2 survivors, in position order) and stages its matches in (pos, id)
+// order as the fused kernel does.  Lanes walk independently: a lane whose
+// walk ends takes the unit's next candidate, so the wave's time follows the
+// total number of steps rather than the longest walk of each group of 64.
+// One step reads the node record and the text byte together.  A unit whose
+// candidates or matches overflowed is redone from the root.
+constexpr uint32_t kWalkMcap = 128;
+
+__global__ __launch_bounds__(64 * kWalkWaves, 8) void walk_units(const ScanArgs a) {
+    __shared__ __align__(16) uint2 s_match[kWalkWaves][kWalkMcap];
+    __shared__ __align__(16) uint2 s_sorted[kWalkWaves][kWalkMcap];
+    __shared__ uint32_t s_bnd[kWalkWaves][kWin / 32 + 2];
+    const ImageView &im = a.im;
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t u = (uint64_t)blockIdx.x * kWalkWaves + wave;
+    if (u >= a.n_tiles) return;
+    const uint64_t hi_valid = a.shift + a.total;
+    const uint64_t unit_lo = u * a.group * kChunk;
+    const uint64_t left = hi_valid > unit_lo ? hi_valid - unit_lo : 0;
+    const uint32_t nch = (uint32_t)min((uint64_t)a.group, (left + kChunk - 1) / kChunk);
+    uint2 *wm = s_match[wave];
+    const uint32_t cn = a.cand_count[u];
+    if (cn <= a.cand_cap) {
+        const uint4 *cl = a.cand + u * a.cand_cap;
+        const uint32_t K = im.K;
+        uint32_t mn = 0, next = 64;  // matches so far, next candidate to hand out
+        bool live = lane < cn;
+        uint32_t pr = 0, lim = 0, v = 0, d = 0, t0 = 0, t1 = 0, navail = 0;
+        uint2 hit = make_uint2(0, 0);
+        // a candidate: position, text limit, depth-K node, and the text bytes
+        // B[pos+K .. pos+K+navail) that its window held
+        auto take = [&](uint32_t e) {
+            const uint4 c = cl[e];
+            pr = c.x & 0xffffu;
+            lim = c.x >> 16;
+            v = c.y;
+            t0 = c.z;
+            t1 = c.w;
+            d = K;
+            const uint32_t q = (pr & (kChunk - 1)) + K;
+            navail = q < kWin ? min(kWin - q, 8u) : 0u;
+        };
+        if (live) take(lane);
+        while (__ballot(live) != 0) {
+            bool done = false;
+            if (live) {
+                const uint64_t p = unit_lo + pr;
+                const uint4 r = im.node[v];
+                // the text byte at depth d: from the candidate when it holds it
+                const uint32_t i = d - K;
+                uint32_t cb = 0;
+                if (d < lim)
+                    cb = i < navail ? (((i < 4 ? t0 : t1) >> (8 * (i & 3))) & 0xffu) : (uint32_t)a.base[p + d];
+                if (r.z & kTermFlagD) hit = make_uint2(r.w, r.z >> kCountShiftD);
+                const uint32_t nc = r.z & 0xffffu;
+                if (nc == 0 || d >= lim) {
+                    done = true;
+                } else if (r.z & kSkipFlagD) {
+                    // no pattern ends inside a single-child run: it matches
+                    // whole or the walk ends with nothing more to report
+                    const uint32_t len = r.z >> kSkipShiftD;
+                    if (d + len > lim) {
+                        done = true;
+                    } else if (p + d + len + 36 <= hi_valid) {
+                        if (chain_equal_g(a.base, p + d, im.chain, r.x, len)) {
+                            v = r.w;
+                            d += len;
+                        } else {
+                            done = true;
+                        }
+                    } else if (cb == im.label[r.y - 1]) {
+                        v = r.y;
+                        d++;
+                    } else {
+                        done = true;
+                    }
+                } else if (nc <= 4) {
+                    const uint32_t x = r.x ^ (cb * 0x01010101u);
+                    const uint32_t m = (x - 0x01010101u) & ~x & 0x80808080u;  // lowest flag = first zero byte
+                    const uint32_t j = m ? (uint32_t)__builtin_ctz(m) >> 3 : 4u;
+                    if (j < nc) {
+                        v = r.y + j;
+                        d++;
+                    } else {
+                        done = true;
+                    }
+                } else {
+                    const uint8_t *lab = im.label + (r.y - 1);
+                    uint32_t lo = 0, hi = nc;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (lab[mid] < cb) lo = mid + 1; else hi = mid;
+                    }
+                    if (lo < nc && lab[lo] == cb) {
+                        v = r.y + lo;
+                        d++;
+                    } else {
+                        done = true;
+                    }
+                }
+            }
+            // finished walks: keep their matches, take the next candidates
+            const bool got = done && hit.y != 0;
+            const unsigned long long mk = __ballot(got);
+            if (got) {
+                const uint32_t slot = mn + mbcnt(mk);
+                if (slot < kWalkMcap) wm[slot] = make_uint2(pr | (hit.y << 16), hit.x);
+            }
+            mn += (uint32_t)__popcll(mk);
+            const unsigned long long md = __ballot(done);
+            if (done) {
+                const uint32_t e = next + mbcnt(md);
+                live = e < cn;
+                hit = make_uint2(0, 0);
+                if (live) take(e);
+            }
+            next += (uint32_t)__popcll(md);
+        }
+        wave_sync();
+        if (mn <= kWalkMcap) {
+            emit_unit(a, u, unit_lo, wm, mn, s_sorted[wave]);
+            return;
+        }
+    }
+    unit_from_root(a, u, unit_lo, nch, s_bnd[wave]);
+}
+
 // ------------------------------------------------------------------ launchers
 
-void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit) {
+void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit, bool split) {
     uint32_t off = 0;
     auto take = [&](uint32_t bytes) {
         const uint32_t o = off;
@@ -651,8 +840,9 @@ void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit) {
     a.off_krec = take(4 * a.krec_words);
     a.off_sym = take(a.im.identity ? 0 : 256);
     a.off_wave = off;
-    a.mcap = 64;
-    a.ccap = 128;
+    // the split filter kernel keeps no candidate or match lists in LDS
+    a.mcap = split ? 0 : 64;
+    a.ccap = split ? 0 : 128;
     a.woff_bnd = (kWin + 16 + 15) & ~15u;
     a.woff_queue = a.woff_bnd + ((4 * (kWin / 32 + 2) + 15) & ~15u);
     a.woff_cand = a.woff_queue + std::max(4 * kQ1, 8 * a.mcap);
@@ -662,23 +852,27 @@ void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit) {
     (void)lds_limit;
 }
 
+// 0..2: fused kernels; 3..5: the split filter kernels of modes 0..2
 int wave_mode(const ScanArgs &a) {
-    if (a.off_ftab != 0) return 0;  // modes 1 and 2 need the table at LDS address 0
-    if (a.im.identity && a.im.K == 2 && a.fold == 8 && a.im.fold_syms == 1) return 1;
-    if (a.im.identity && a.im.K == 2 && a.fold == 16 && a.im.fold_syms == 1) return 2;
-    return 0;
+    const int split = a.cand != nullptr ? 3 : 0;
+    if (a.off_ftab != 0) return split;  // modes 1 and 2 need the table at LDS address 0
+    if (a.im.identity && a.im.K == 2 && a.fold == 8 && a.im.fold_syms == 1) return 1 + split;
+    if (a.im.identity && a.im.K == 2 && a.fold == 16 && a.im.fold_syms == 1) return 2 + split;
+    return split;
 }
 
 template <int MODE>
-static const void *wave_fn() {
-    return (const void *)scan_waves<MODE>;
+static const void *wave_fn(bool split) {
+    return split ? (const void *)scan_waves<MODE, true> : (const void *)scan_waves<MODE, false>;
 }
 
+// modes 3..5 are the split variants of modes 0..2
 static const void *wave_fn_for(int mode) {
-    switch (mode) {
-        case 1: return wave_fn<1>();
-        case 2: return wave_fn<2>();
-        default: return wave_fn<0>();
+    const bool split = mode >= 3;
+    switch (mode % 3) {
+        case 1: return wave_fn<1>(split);
+        case 2: return wave_fn<2>(split);
+        default: return wave_fn<0>(split);
     }
 }
 
@@ -697,10 +891,21 @@ hipError_t launch_scan_waves(const ScanArgs &a, uint32_t waves, uint32_t grid, h
     const int mode = wave_mode(a);
     const dim3 block(64 * waves);
     switch (mode) {
-        case 1: hipLaunchKernelGGL(scan_waves<1>, dim3(grid), block, a.lds_total, s, a); break;
-        case 2: hipLaunchKernelGGL(scan_waves<2>, dim3(grid), block, a.lds_total, s, a); break;
-        default: hipLaunchKernelGGL(scan_waves<0>, dim3(grid), block, a.lds_total, s, a); break;
+        case 1: hipLaunchKernelGGL((scan_waves<1, false>), dim3(grid), block, a.lds_total, s, a); break;
+        case 2: hipLaunchKernelGGL((scan_waves<2, false>), dim3(grid), block, a.lds_total, s, a); break;
+        case 3: hipLaunchKernelGGL((scan_waves<0, true>), dim3(grid), block, a.lds_total, s, a); break;
+        case 4: hipLaunchKernelGGL((scan_waves<1, true>), dim3(grid), block, a.lds_total, s, a); break;
+        case 5: hipLaunchKernelGGL((scan_waves<2, true>), dim3(grid), block, a.lds_total, s, a); break;
+        default: hipLaunchKernelGGL((scan_waves<0, false>), dim3(grid), block, a.lds_total, s, a); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_units(const ScanArgs &a, hipStream_t s) {
+    if (a.n_tiles == 0) return hipSuccess;
+    const uint64_t grid = (a.n_tiles + kWalkWaves - 1) / kWalkWaves;
+    if (grid > 0x7fffffffull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(walk_units, dim3((uint32_t)grid), dim3(64 * kWalkWaves), 0, s, a);
     return hipGetLastError();
 }
 

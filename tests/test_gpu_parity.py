@@ -38,6 +38,9 @@ TUNINGS = (
     [dict(kernel=0, bytes_per_lane=bpl, index_bits=bits) for bpl in (4, 8, 16) for bits in (8, 12, 16, 18)]
     + [dict(kernel=1, index_bits=bits, fold_bits=fold, waves_per_wg=w, chunks_per_unit=g, child_check=cc)
        for bits in (8, 12, 16, 18) for fold in (0, 8, 16) for (w, g, cc) in ((4, 1, 0), (16, 16, 1), (12, 64, 1))]
+    # split filter + walk kernels
+    + [dict(kernel=2, index_bits=bits, fold_bits=fold, waves_per_wg=w, chunks_per_unit=g, child_check=cc)
+       for bits in (8, 12, 16, 18) for fold in (0, 8, 16) for (w, g, cc) in ((4, 1, 0), (16, 32, 1))]
 )
 
 
@@ -65,6 +68,8 @@ DNA_TUNINGS = [
     dict(kernel=1, index_bits=14, fold_bits=8, waves_per_wg=4, wg_per_cu=1),
     dict(kernel=1, index_bits=16, fold_bits=8, chunks_per_unit=1, child_check=0),
     dict(kernel=1, index_bits=12, fold_bits=8, chunks_per_unit=64, child_check=1),
+    dict(kernel=2, index_bits=16, fold_bits=8), dict(kernel=2, index_bits=18, fold_bits=0),
+    dict(kernel=2, index_bits=12, fold_bits=16, waves_per_wg=8, chunks_per_unit=2),
 ]
 
 
@@ -82,10 +87,12 @@ def test_dna_tuning_points(tuning):
     assert np.array_equal(counts, oracle.counts(wl.text.size, want))
 
 
-def test_c2_scaled_full_pattern_set():
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_c2_scaled_full_pattern_set(kernel):
     wl = workloads.c2_signature_set(n_text=16 << 20, k=10_000)
-    say(f"c2 scaled: {wl.text.size} bytes")
+    say(f"c2 scaled: {wl.text.size} bytes, kernel {kernel}")
     trie = pf.Trie(wl.patterns)
+    trie.set_tuning(kernel=kernel, chunks_per_unit=32)
     got, counts = gpu_scan(trie, wl.text)
     want = oracle.bucketed(wl.text, wl.patterns, threads=8)
     assert_same(got, want)
@@ -102,11 +109,12 @@ def test_misaligned_text_addresses(pad):
     assert np.array_equal(counts, oracle.counts(wl.text.size, want))
 
 
+@pytest.mark.parametrize("kernel", [0, 1, 2])
 @pytest.mark.parametrize("case", [
     "empty_text", "short_text", "no_patterns", "length_one", "duplicates", "nested_runs",
-    "all_windows", "sigma1_long", "long_patterns", "match_at_end",
+    "all_windows", "sigma1_long", "long_patterns", "match_at_end", "dense_candidates",
 ])
-def test_edge_cases(case):
+def test_edge_cases(case, kernel):
     rng = np.random.default_rng(hash(case) & 0xffff)
     if case == "empty_text":
         pats, text = [b"abc", b"x"], b""
@@ -135,12 +143,17 @@ def test_edge_cases(case):
         base = bytes(rng.integers(0, 4, 5000).astype(np.uint8))
         pats = [base[:3000], base[:2000] + b"\xff", base[1000:4500], base[4000:4003]]
         text = (base * 7)[: 30_000]
+    elif case == "dense_candidates":
+        # every position passes both filter stages: candidate lists overflow
+        pats = [b"aaaab", b"aaab", b"aabx"]
+        text = (b"a" * 3000 + b"b") * 12
     else:  # match_at_end
         pats = [b"tail!", b"l!"]
         text = bytes(rng.integers(0, 200, 8191).astype(np.uint8)) + b"tail!"
     text = np.frombuffer(text, dtype=np.uint8).copy()
     trie = pf.Trie(pats)
-    say(f"edge {case}: n={text.size} k={len(pats)} K={trie.stats()['index_depth']}")
+    trie.set_tuning(kernel=kernel)
+    say(f"edge {case} kernel {kernel}: n={text.size} k={len(pats)} K={trie.stats()['index_depth']}")
     got, counts = gpu_scan(trie, text)
     want = oracle.brute(text, pats, threads=8)
     assert_same(got, want)
@@ -148,9 +161,11 @@ def test_edge_cases(case):
         assert np.array_equal(counts, oracle.counts(text.size, want))
 
 
-def test_capacity_overflow_reports_exact_count():
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_capacity_overflow_reports_exact_count(kernel):
     wl = workloads.c1_plain_small(n_text=200_000, k=100, n_plants=2000)
     trie = pf.Trie(wl.patterns)
+    trie.set_tuning(kernel=kernel)
     want = oracle.brute(wl.text, wl.patterns, threads=8)
     ws = pf.Workspace()
     import torch
@@ -176,10 +191,11 @@ def _random_batch(rng, n_texts, max_len, alphabet):
 
 BATCH_TUNINGS = [dict(kernel=1), dict(kernel=0, bytes_per_lane=8),
                  dict(kernel=1, chunks_per_unit=1, child_check=0, waves_per_wg=4),
-                 dict(kernel=1, chunks_per_unit=64, fold_bits=0)]
+                 dict(kernel=1, chunks_per_unit=64, fold_bits=0),
+                 dict(kernel=2), dict(kernel=2, chunks_per_unit=1, child_check=0, waves_per_wg=4)]
 
 
-@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+@pytest.mark.parametrize("seed", range(len(BATCH_TUNINGS)))
 def test_batch_matches_oracle_and_plain(seed):
     rng = np.random.default_rng(seed)
     alphabet = np.frombuffer(b"abcd", dtype=np.uint8)
@@ -210,11 +226,13 @@ def test_batch_long_patterns_small_texts(tuning):
     assert_same(got, want, with_text=True)
 
 
-def test_batch_graph_replays_are_identical():
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_batch_graph_replays_are_identical(kernel):
     rng = np.random.default_rng(9)
     wl = workloads.c4_batched(n_small=2000, n_large=3, large_lo=1 << 16, large_hi=1 << 18,
                               k=2000, rate=1 / 512)
     trie = pf.Trie(wl.patterns)
+    trie.set_tuning(kernel=kernel)
     want = oracle.bucketed(wl.text, wl.patterns, offsets=wl.offsets, threads=8)
     say(f"graph: {wl.n_texts} texts {wl.text.size} bytes, {want.n} matches")
     results, n = gpu_scan_batch(trie, wl.text, wl.offsets, graph_replays=4)
@@ -238,9 +256,10 @@ def test_exhaustive_binary_alphabet_batched():
     assert len(sets) == 679
     ws = pf.Workspace()
     say(f"exhaustive: {len(sets)} pattern sets x {len(texts)} texts")
-    for s in sets:
+    for i_set, s in enumerate(sets):
         pats = [strs[i] for i in s]
         trie = pf.Trie(pats)
+        trie.set_tuning(kernel=1 + i_set % 2)  # fused and split wave kernels alternate
         got, n = gpu_scan_batch(trie, text, offs, ws=ws, capacity=4096)
         want = oracle.brute(text, pats, offsets=offs)
         assert n == want.n, pats
