@@ -186,6 +186,111 @@ def extras_batched(pf, torch, steps):
     return res
 
 
+def _percentiles(lat_s):
+    import numpy as np
+    a = np.asarray(lat_s) * 1e3
+    return round(float(np.percentile(a, 50)), 3), round(float(np.percentile(a, 99)), 3)
+
+
+def extras_serving(pf, torch, n_requests, rate_per_s, budget_bytes):
+    """C5: Poisson arrivals at a fixed offered rate into the continuous-batching
+    server, against one request at a time (copy in, scan, copy out, next)."""
+    import threading
+
+    import numpy as np
+    from synth import workloads
+    t0 = time.time()
+    wl = workloads.c5_requests(n_requests)
+    log(f"c5 generated in {time.time() - t0:.1f}s: {n_requests} requests, {wl.text.size} bytes")
+    offs = wl.offsets.astype(np.int64)
+    sizes = np.diff(offs)
+    total = int(offs[-1])
+    host = torch.from_numpy(wl.text).pin_memory()  # request bodies in pinned host memory
+    base_ptr = host.data_ptr()
+    arrivals = workloads.poisson_arrivals(n_requests, rate_per_s)
+    trie = pf.Trie(wl.patterns)
+    max_n = int(sizes.max())
+    res = {"workload": f"c5: {n_requests} requests, sizes log-uniform [1 KiB, 64 MiB] "
+                       f"(mean {sizes.mean() / 2**20:.2f} MiB), 50,000 patterns len U[8,64], "
+                       f"copies 1 per 2 KiB; Poisson arrivals",
+           "offered_req_s": rate_per_s,
+           "offered_gbit_s": round(sizes.mean() * 8 * rate_per_s / 1e9, 2),
+           "hbm_budget_bytes": budget_bytes}
+
+    # ---- one request at a time
+    stream = torch.cuda.Stream()
+    ws = pf.Workspace()
+    dev = torch.empty(max_n + 16, dtype=torch.uint8, device="cuda")
+    cap = 1 << 22
+    out = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out_host = torch.empty(cap * 16, dtype=torch.uint8).pin_memory()
+    ws.reserve(max_n, 1, cap)
+
+    def serve_one(i):
+        a, b = int(offs[i]), int(offs[i + 1])
+        with torch.cuda.stream(stream):
+            dev[:b - a].copy_(host[a:b], non_blocking=True)
+            pf.pfac_scan(trie, ws, dev, b - a, out, cap, cnt, None, stream)
+            n = int(cnt.item())  # synchronizes the stream
+            if n:
+                out_host[:16 * min(n, cap)].copy_(out[:16 * min(n, cap)])
+        return n
+
+    serve_one(0)  # warm-up
+    lat_base, n_base = [], 0
+    start = time.perf_counter()
+    for i in range(n_requests):
+        due = start + arrivals[i]
+        while time.perf_counter() < due:
+            pass
+        n_base += serve_one(i)
+        lat_base.append(time.perf_counter() - due)
+    end_base = time.perf_counter() - start
+    p50b, p99b = _percentiles(lat_base)
+    res["one_at_a_time"] = {"p50_ms": p50b, "p99_ms": p99b, "matches": n_base,
+                            "served_gbit_s": round(total * 8 / end_base / 1e9, 2)}
+
+    # ---- the server
+    arena = torch.empty(budget_bytes + (256 << 20), dtype=torch.uint8, device="cuda")
+    cs, xs = torch.cuda.Stream(), torch.cuda.Stream()
+    srv = pf.Server(trie, arena, budget_bytes, 64, cs, xs)
+    # warm-up request
+    rid = srv.submit_ptr(base_ptr, int(sizes[0]))
+    srv.wait(rid, capacity=cap)
+    ids = [None] * n_requests
+    lat_srv = [0.0] * n_requests
+    n_srv = [0]
+    ready = threading.Semaphore(0)
+
+    def waiter():
+        for i in range(n_requests):
+            ready.acquire()
+            m, lat = srv.wait(ids[i], capacity=cap)
+            lat_srv[i] = lat
+            n_srv[0] += m.size
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    start = time.perf_counter()
+    for i in range(n_requests):
+        due = start + arrivals[i]
+        while time.perf_counter() < due:
+            pass
+        ids[i] = srv.submit_ptr(base_ptr + int(offs[i]), int(sizes[i]))
+        ready.release()
+    th.join()
+    end_srv = time.perf_counter() - start
+    st = srv.stats()
+    srv.close()
+    p50s, p99s = _percentiles(lat_srv)
+    res["server"] = {"p50_ms": p50s, "p99_ms": p99s, "matches": n_srv[0],
+                     "served_gbit_s": round(total * 8 / end_srv / 1e9, 2),
+                     "batches": st["batches"] - 1, "max_batch": 64}
+    res["same_matches"] = n_srv[0] == n_base
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -198,6 +303,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--extras", action="store_true", help="add batched-vs-plain (c4)")
+    ap.add_argument("--serving", action="store_true",
+                    help="add the serving loop (c5) against one request at a time")
+    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-rate", type=float, default=1000.0, help="offered requests per second")
+    ap.add_argument("--serving-budget", type=int, default=1 << 30, help="HBM bytes for request texts")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of the text size (counter calibration)")
     args = ap.parse_args()
@@ -349,6 +459,9 @@ def main():
         line["parity_with_oracle"] = bool(same)
     if args.extras:
         line["batched_vs_plain"] = extras_batched(pf, torch, max(3, args.steps // 5))
+    if args.serving:
+        line["serving"] = extras_serving(pf, torch, args.serving_requests, args.serving_rate,
+                                         args.serving_budget)
 
     print(json.dumps(line), flush=True)
 

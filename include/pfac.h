@@ -80,7 +80,8 @@ typedef struct {
     uint32_t symbol_bits;      /* bits per symbol in the level index */
     uint32_t index_depth;      /* K: levels resolved by the level index in LDS */
     uint32_t lds_bytes;        /* dynamic LDS per workgroup of the scan kernel */
-    uint32_t scan_kernel;      /* kernel the current tuning launches: 0 = tile, 1 = wave */
+    uint32_t scan_kernel;      /* kernels the current tuning launches: 0 = tile, 1 = fused
+                                  wave kernel, 2 = split filter + walk kernels */
     uint32_t scan_waves;       /* waves per workgroup it launches with (after LDS fitting) */
     double build_seconds;      /* host build time (not part of scan timing) */
     double upload_seconds;     /* host -> device copy time of the image */
@@ -88,7 +89,10 @@ typedef struct {
 
 /* Launch parameters chosen by hand or by pfac_autotune. */
 typedef struct {
-    uint32_t kernel;           /* 0 = tile kernel (workgroup tiles), 1 = wave kernel */
+    uint32_t kernel;           /* 0 = tile kernel (workgroup tiles), 1 = fused wave kernel
+                                  (filter, walks and emission in one kernel), 2 = split wave
+                                  kernels (filter kernel writes walk candidates, a walk kernel
+                                  runs them; the default for byte alphabets) */
     uint32_t bytes_per_lane;   /* tile kernel: start positions per lane per tile: 4, 8 or 16 */
     uint32_t index_bits;       /* level-index width in bits (1..18); depth K = bits / symbol_bits */
     uint32_t fold_bits;        /* wave kernel prefix filter: 0 (level bitmap), 8 or 16 bits per node */
@@ -166,9 +170,10 @@ int pfac_workspace_reserve(pfac_workspace *w, uint64_t max_bytes, uint32_t max_t
 /*
  * Instrumentation: when both events are set (hipEvent_t, NULL to clear),
  * every later scan on this workspace records `start_event` on its stream
- * right before the main scan kernel and `stop_event` right after it, so the
- * caller can time that kernel alone.  The events are only recorded, never
- * created or destroyed, by the library.
+ * right before the main scan kernel (the tile kernel, the fused wave kernel,
+ * or the filter kernel of the split pair) and `stop_event` right after it,
+ * so the caller can time that kernel alone.  The events are only recorded,
+ * never created or destroyed, by the library.
  */
 int pfac_workspace_set_timing(pfac_workspace *w, void *start_event, void *stop_event);
 

@@ -230,10 +230,15 @@ class Trie:
         check("pfac_trie_get_tuning", load().pfac_trie_get_tuning(self.handle, ctypes.byref(t)))
         return {n: getattr(t, n) for n, _ in t._fields_}
 
-    def set_tuning(self, kernel=1, bytes_per_lane=16, index_bits=16, fold_bits=8, wg_per_cu=0,
-                   waves_per_wg=16, chunks_per_unit=16, child_check=1):
-        t = pfac_tuning(kernel, bytes_per_lane, index_bits, fold_bits, wg_per_cu, waves_per_wg,
-                        chunks_per_unit, child_check)
+    def set_tuning(self, **fields):
+        """Change the named fields of the launch tuning (pfac_tuning); the
+        others keep their current values."""
+        cur = self.tuning()
+        unknown = set(fields) - set(cur)
+        if unknown:
+            raise TypeError(f"unknown tuning fields {sorted(unknown)}")
+        cur.update(fields)
+        t = pfac_tuning(*(int(cur[name]) for name, _ in pfac_tuning._fields_))
         check("pfac_trie_set_tuning", load().pfac_trie_set_tuning(self.handle, ctypes.byref(t)))
 
 

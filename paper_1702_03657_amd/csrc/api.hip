@@ -191,6 +191,10 @@ static int build_common(const uint8_t *data, const uint64_t *offsets, uint32_t k
         delete t;
         return PFAC_ENOMEM;
     }
+    // default launch: the split filter + walk kernels where the byte-symbol
+    // two-level filter applies (few walk candidates); the fused wave kernel
+    // otherwise (small alphabets and short patterns leave many candidates)
+    if (t->img.identity && t->img.K == 2) t->tuning.kernel = 2;
     t->build_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     set_halo(t);
     t->host_only = (flags & PFAC_BUILD_HOST_ONLY) != 0;

@@ -1,0 +1,111 @@
+"""GPU tests of the serving loop (pfac_server_*): every request's result is
+the same as the oracle's for that text alone and as a scan of it alone on the
+GPU, whatever the mix it was batched with, the ring wrap-around, the budget
+and the overflow fallback."""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1702_03657_amd as pf
+from synth import workloads
+from tests.gpu_util import assert_same, gpu_scan, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    # torch takes the device first, then the library
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    torch.cuda.set_device(0)
+    pf.load()
+
+
+def _requests(seed, n, lo, hi, pats, rate=1 / 1024):
+    """Seeded request texts of log-uniform sizes with planted pattern copies."""
+    rng = np.random.default_rng(seed)
+    sizes = np.floor(np.exp(rng.uniform(math.log(lo), math.log(hi), n))).astype(np.int64)
+    texts = []
+    for s in sizes:
+        t = rng.integers(0, 256, int(s), dtype=np.uint8)
+        for _ in range(rng.poisson(s * rate)):
+            p = pats[int(rng.integers(0, len(pats)))]
+            if len(p) <= s:
+                at = int(rng.integers(0, s - len(p) + 1))
+                t[at:at + len(p)] = np.frombuffer(p, dtype=np.uint8)
+        texts.append(t)
+    return texts
+
+
+def _server(trie, budget, arena, max_batch):
+    import torch
+    buf = torch.empty(arena, dtype=torch.uint8, device="cuda")
+    cs, xs = torch.cuda.Stream(), torch.cuda.Stream()
+    return pf.Server(trie, buf, budget, max_batch, cs, xs), buf
+
+
+@pytest.mark.parametrize("kernel", [1, 2])
+def test_mix_equals_alone(kernel):
+    pats = workloads.make_patterns(np.random.default_rng(5), 2000, 8, 64, "uniform")
+    texts = _requests(11, 48, 1024, 512 * 1024, pats)
+    trie = pf.Trie(pats)
+    trie.set_tuning(kernel=kernel)
+    budget = 2 << 20  # smaller than the sum: several batches and ring wrap-around
+    srv, _buf = _server(trie, budget, budget + (16 << 20), 16)
+    say(f"server kernel {kernel}: {len(texts)} requests, {sum(t.size for t in texts)} bytes")
+    ids = [srv.submit(t) for t in texts]
+    lat = []
+    for t, rid in zip(texts, ids):
+        got, l = srv.wait(rid, capacity=1 << 16)
+        lat.append(l)
+        want = oracle.bucketed(t, pats, threads=8)
+        assert_same(got, want)
+        alone, _ = gpu_scan(trie, t, counts=False)
+        assert np.array_equal(got, alone)
+    st = srv.stats()
+    say(f"stats {st}, latency max {max(lat):.4f}s")
+    assert st["requests"] == len(texts)
+    assert st["batches"] > 1 and st["batches"] < len(texts)  # batched, more than once
+    srv.close()
+
+
+def test_overflow_falls_back_to_single_scans():
+    # dense matches overflow the small per-batch output: each request is then
+    # scanned alone with an exact-size buffer
+    pats = [b"aa", b"aaa", b"ab"]
+    rng = np.random.default_rng(3)
+    texts = [np.frombuffer((b"a" * int(n)) + b"b", dtype=np.uint8).copy()
+             for n in rng.integers(2000, 9000, 6)]
+    trie = pf.Trie(pats)
+    budget = 1 << 20
+    srv, _buf = _server(trie, budget, budget + (256 << 10), 8)
+    ids = [srv.submit(t) for t in texts]
+    for t, rid in zip(texts, ids):
+        got, _ = srv.wait(rid, capacity=1 << 16)
+        assert_same(got, oracle.brute(t, pats))
+    srv.close()
+
+
+def test_empty_request_and_limits():
+    pats = [b"abc", b"bcd"]
+    trie = pf.Trie(pats)
+    budget = 1 << 16
+    srv, _buf = _server(trie, budget, budget + (1 << 20), 4)
+    rid = srv.submit(np.zeros(0, dtype=np.uint8))
+    got, _ = srv.wait(rid)
+    assert got.size == 0
+    with pytest.raises(pf.PfacError):
+        srv.submit(np.zeros(budget + 1, dtype=np.uint8))  # larger than the ring
+    t = np.frombuffer(b"xxabcdxx" * 100, dtype=np.uint8).copy()
+    rid = srv.submit(t)
+    with pytest.raises(pf.PfacError):
+        srv.wait(rid, capacity=4)  # more matches than the caller's buffer
+    rid = srv.submit(t)
+    got, _ = srv.wait(rid, capacity=1024)
+    assert_same(got, oracle.brute(t, pats))
+    srv.close()
