@@ -14,8 +14,10 @@ text and the trie already resident in HBM.  Prints one JSON line:
 
 Workloads (seeded synthetic data, see synth/workloads.py): ``c2`` (default,
 10,000 patterns of 8-64 bytes, 70% printable bytes, 256 MiB text), ``c1``,
-``c3`` (1 GiB DNA text, 100,000 patterns).  ``--extras`` adds the batched vs
-plain per-text comparison (65,600 texts) and the serving loop latencies.
+``c3`` (1 GiB DNA text, 100,000 patterns).  The line also carries the batched
+vs plain per-text comparison (c4: 65,600 texts in one graph-captured launch
+against one launch per text) and the serving loop's p50/p99 latency against
+one request at a time (c5); ``--no-extras`` / ``--no-serving`` leave them out.
 """
 
 from __future__ import annotations
@@ -133,7 +135,7 @@ def run_copy_probe(torch, nbytes):
     log(f"copy probe: 3 copies of {nbytes} bytes")
 
 
-def extras_batched(pf, torch, steps):
+def extras_batched(pf, torch, steps, oracle_threads=0):
     """C4: one graph-captured persistent launch vs one launch per text."""
     import numpy as np
     from synth import workloads
@@ -158,6 +160,7 @@ def extras_batched(pf, torch, steps):
         g.launch(stream)
         stream.synchronize()
         n_batched = int(cnt.item())
+        batched_list = pf.matches_to_numpy(out, min(n_batched, cap))
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         for _ in range(steps):
@@ -175,6 +178,13 @@ def extras_batched(pf, torch, steps):
         e1.record(stream)
         stream.synchronize()
         ms_p = e0.elapsed_time(e1) / plain_steps
+    if oracle_threads:
+        import oracle
+        want = oracle.bucketed(wl.text, wl.patterns, offsets=wl.offsets, threads=oracle_threads)
+        res["parity_with_oracle"] = bool(
+            n_batched == want.n and np.array_equal(batched_list["pos"], want["pos"])
+            and np.array_equal(batched_list["pattern_id"], want["id"])
+            and np.array_equal(batched_list["text_id"], want["text"]))
     res.update({
         "matches": n_batched, "plain_matches_equal": n_plain == n_batched,
         "batched_ms": round(ms_b, 4), "plain_ms": round(ms_p, 4),
@@ -302,9 +312,10 @@ def main():
                     help="kernel,bytes_per_lane,index_bits,fold_bits,wg_per_cu,waves_per_wg,chunks_per_unit,child_check")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
-    ap.add_argument("--extras", action="store_true", help="add batched-vs-plain (c4)")
-    ap.add_argument("--serving", action="store_true",
-                    help="add the serving loop (c5) against one request at a time")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-vs-plain comparison (c4)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving loop (c5) against one request at a time")
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-rate", type=float, default=1000.0, help="offered requests per second")
     ap.add_argument("--serving-budget", type=int, default=1 << 30, help="HBM bytes for request texts")
@@ -457,9 +468,11 @@ def main():
         same = (got_m.size == want.n and np.array_equal(got_m["pos"], want["pos"])
                 and np.array_equal(got_m["pattern_id"], want["id"]))
         line["parity_with_oracle"] = bool(same)
-    if args.extras:
-        line["batched_vs_plain"] = extras_batched(pf, torch, max(3, args.steps // 5))
-    if args.serving:
+    if not args.no_extras:
+        line["batched_vs_plain"] = extras_batched(
+            pf, torch, max(3, args.steps // 5),
+            0 if args.no_cpu_baseline else (args.cpu_threads or min(16, os.cpu_count() or 1)))
+    if not args.no_serving:
         line["serving"] = extras_serving(pf, torch, args.serving_requests, args.serving_rate,
                                          args.serving_budget)
 

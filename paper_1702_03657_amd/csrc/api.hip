@@ -506,6 +506,8 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     a.n_texts = L.n_texts;
     a.text_id0 = L.text_id0;
     a.tile_first_text = L.offsets ? (const uint32_t *)w->tile_first.p : nullptr;
+    a.n_plan = n_plan;
+    a.plan_shift = (uint32_t)__builtin_ctz(plan_unit);
     a.n_tiles = n_tiles;
     a.stage = (pfac_match *)w->stage.p;
     a.stage_cap = std::min<uint64_t>(L.capacity, w->stage.bytes / sizeof(pfac_match));

@@ -185,10 +185,11 @@ __device__ __forceinline__ uint2 walk(const ImageView &im, const uint8_t *gbase,
     return hit;
 }
 
-// Text holding frame position g (batch), by binary search over the starts.
-__device__ __forceinline__ uint32_t text_of(const uint64_t *offsets, uint32_t n_texts,
+// Text holding frame position g (batch): the last text starting at or before
+// g, by binary search over the starts with the answer known to be in
+// [lo, hi).
+__device__ __forceinline__ uint32_t text_of(const uint64_t *offsets, uint32_t lo, uint32_t hi,
                                             uint64_t shift, uint64_t g) {
-    uint32_t lo = 0, hi = n_texts;  // answer in [0, n_texts)
     while (hi - lo > 1) {
         uint32_t mid = (lo + hi) >> 1;
         if (offsets[mid] + shift <= g) lo = mid; else hi = mid;
@@ -211,7 +212,12 @@ __device__ __forceinline__ void emit(const ScanArgs &a, uint64_t frame_pos, uint
     uint32_t tid = 0;
     uint64_t start = a.shift;
     if (a.offsets) {
-        tid = text_of(a.offsets, a.n_texts, a.shift, frame_pos);
+        // the batch plan bounds the search: the texts holding the first
+        // bytes of this plan unit and of the next one
+        const uint64_t c = frame_pos >> a.plan_shift;
+        const uint32_t lo = a.tile_first_text[c];
+        const uint32_t hi = (c + 1 < a.n_plan ? a.tile_first_text[c + 1] : a.n_texts - 1) + 1;
+        tid = text_of(a.offsets, lo, hi, a.shift, frame_pos);
         start = a.offsets[tid] + a.shift;
     }
     tid += a.text_id0;

@@ -38,7 +38,9 @@ struct ScanArgs {
     uint64_t shift;                   // frame position of the first text byte (0..15)
     uint64_t total;                   // bytes of all texts
     const uint64_t *offsets;          // n_texts + 1 text starts, or NULL for one text
-    const uint32_t *tile_first_text;  // per tile: text holding its first byte (batch only)
+    const uint32_t *tile_first_text;  // per plan unit: text holding its first byte (batch only)
+    uint64_t n_plan;                  // plan units of 1 << plan_shift bytes
+    uint32_t plan_shift, pad3;
     uint64_t n_tiles;
     uint32_t n_texts;
     uint32_t text_id0;                // added to every reported text id
