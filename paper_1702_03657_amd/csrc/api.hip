@@ -117,7 +117,8 @@ static int upload_image(pfac_trie *t) {
     size_t o_root = align256(o_ftab + std::max<size_t>(I.ftab.size(), 16));
     size_t o_chain = align256(o_root + std::max<size_t>(I.root_bits.size(), 1) * 4);
     size_t o_krec = align256(o_chain + std::max<size_t>(I.chain.size(), 64));
-    size_t total = align256(o_krec + std::max<size_t>(I.krec.size(), 1) * 4);
+    size_t o_pfx4 = align256(o_krec + std::max<size_t>(I.krec.size(), 1) * 4);
+    size_t total = align256(o_pfx4 + std::max<size_t>(I.pfx4.size(), 1) * 4);
     auto t0 = std::chrono::steady_clock::now();
     t->dev.release();
     HIP_TRY(t->dev.reserve(total));
@@ -135,6 +136,8 @@ static int upload_image(pfac_trie *t) {
         HIP_TRY(hipMemcpy(b + o_krec, I.krec.data(), I.krec.size() * 4, hipMemcpyHostToDevice));
     if (!I.chain.empty())
         HIP_TRY(hipMemcpy(b + o_chain, I.chain.data(), I.chain.size(), hipMemcpyHostToDevice));
+    if (!I.pfx4.empty())
+        HIP_TRY(hipMemcpy(b + o_pfx4, I.pfx4.data(), I.pfx4.size() * 4, hipMemcpyHostToDevice));
     if (!I.root_bits.empty())
         HIP_TRY(hipMemcpy(b + o_root, I.root_bits.data(), I.root_bits.size() * 4, hipMemcpyHostToDevice));
     ImageView &v = t->view;
@@ -148,6 +151,9 @@ static int upload_image(pfac_trie *t) {
     v.root_bits = (const uint32_t *)(b + o_root);
     v.chain = b + o_chain;
     v.krec = (const uint32_t *)(b + o_krec);
+    v.pfx4 = (const uint32_t *)(b + o_pfx4);
+    v.pfx4_log2 = I.pfx4_log2;
+    v.pfx4_mul = kPfx4Mul;
     v.fold_syms = I.fold_syms;
     v.K = I.K;
     v.b = I.b;
@@ -195,6 +201,7 @@ static int build_common(const uint8_t *data, const uint64_t *offsets, uint32_t k
     // two-level filter applies (few walk candidates); the fused wave kernel
     // otherwise (small alphabets and short patterns leave many candidates)
     if (t->img.identity && t->img.K == 2) t->tuning.kernel = 2;
+    if (t->img.pfx4_log2) t->tuning.child_check = 2;
     t->build_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     set_halo(t);
     t->host_only = (flags & PFAC_BUILD_HOST_ONLY) != 0;
@@ -264,8 +271,12 @@ static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr) {
     if (t->tuning.kernel >= 1) {
         a.fold = t->img.fold_bits;
         a.group = t->tuning.chunks_per_unit;
+        // child_check 2: the prefix-4 filter where the image has one, else
+        // the child records; dropped last when the layout does not fit
+        const bool pfx4 = t->tuning.child_check == 2 && t->img.pfx4_log2 != 0;
         for (int with_rec = (t->tuning.child_check && t->img.K) ? 1 : 0; with_rec >= 0; with_rec--) {
-            a.krec_words = with_rec ? (uint32_t)t->img.krec.size() : 0u;
+            a.krec_words = with_rec && !pfx4 ? (uint32_t)t->img.krec.size() : 0u;
+            a.pfx4_words = with_rec && pfx4 ? (uint32_t)t->img.pfx4.size() : 0u;
             for (waves = t->tuning.waves_per_wg; waves >= 4; waves -= 4) {
                 wave_lds_layout(a, waves, t->lds_limit, t->tuning.kernel == 2);
                 if (a.lds_total <= t->lds_limit) break;
@@ -341,7 +352,7 @@ static bool valid_tuning(const pfac_tuning *p) {
            (p->fold_bits == 0 || p->fold_bits == 8 || p->fold_bits == 16) && p->wg_per_cu <= 8 &&
            (p->waves_per_wg == 4 || p->waves_per_wg == 8 || p->waves_per_wg == 12 ||
             p->waves_per_wg == 16) &&
-           p->chunks_per_unit >= 1 && p->chunks_per_unit <= 64 && p->child_check <= 1;
+           p->chunks_per_unit >= 1 && p->chunks_per_unit <= 64 && p->child_check <= 2;
 }
 
 extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {

@@ -28,8 +28,10 @@ struct ImageView {
     const uint32_t *root_bits;  // codes of the root's children
     const uint8_t *chain;     // labels of compressed single-child runs
     const uint32_t *krec;     // per depth-K node: up to three child labels, count in the top byte
+    const uint32_t *pfx4;     // prefix-4 filter bitmap (2^pfx4_log2 bits)
     uint32_t K, b, identity, lvl_words;
     uint32_t lvl_start, max_len, n_nodes, fold_syms;
+    uint32_t pfx4_log2, pfx4_mul;     // prefix-4 filter: 2^pfx4_log2 bits, hash multiplier
 };
 
 struct ScanArgs {
@@ -53,6 +55,7 @@ struct ScanArgs {
     uint32_t ftab_bytes, off_ftab, root_words, off_root;
     uint32_t off_wave, wave_bytes, woff_bnd, woff_queue, woff_cand, woff_match, ccap, mcap;
     uint32_t krec_words, off_krec, group, pad1;   // LDS child records, chunks per unit
+    uint32_t pfx4_words, off_pfx4;    // LDS prefix-4 filter (instead of the child records)
     // outputs
     pfac_match *stage;
     uint64_t stage_cap;

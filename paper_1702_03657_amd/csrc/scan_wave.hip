@@ -330,6 +330,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     uint32_t *s_rank = (uint32_t *)(lds + a.off_rank);
     uint32_t *s_root = (uint32_t *)(lds + a.off_root);
     uint32_t *s_krec = (uint32_t *)(lds + a.off_krec);
+    uint32_t *s_pfx4 = (uint32_t *)(lds + a.off_pfx4);
     uint8_t *s_sym = lds + a.off_sym;
 
     // the split path needs no reset kernel: the walk kernel, the first to
@@ -350,6 +351,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     }
     for (uint32_t i = tid; i < a.root_words; i += nthreads) s_root[i] = im.root_bits[i];
     for (uint32_t i = tid; i < a.krec_words; i += nthreads) s_krec[i] = im.krec[i];
+    for (uint32_t i = tid; i < a.pfx4_words; i += nthreads) s_pfx4[i] = im.pfx4[i];
     if (MODE == 0 && !im.identity)
         for (uint32_t i = tid; i < 256; i += nthreads) s_sym[i] = im.sym[i];
     __syncthreads();
@@ -368,6 +370,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     const uint32_t K = im.K;
     const uint32_t ccap = a.ccap, mcap = a.mcap;
     const bool krec = a.krec_words != 0;
+    const bool pfx4 = a.pfx4_words != 0;
 
     auto load_vec = [&](uint64_t g) -> uint4 {
         uint4 v = make_uint4(0, 0, 0, 0);
@@ -589,7 +592,15 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                             const uint32_t by = __builtin_amdgcn_alignbyte(d1, d0, pl & 3u);  // B[pl..pl+3]
                             const uint32_t lim = dirty ? limit_after(wbnd, dirty, chunk_lo, pl, next_bnd)
                                                        : min(nb_rel - pl, 0xffffu);
-                            pass2 = pl >= vlo && pl < vhi && lim > 2u;
+                            // with the prefix-4 filter every pattern is 4 bytes or longer
+                            pass2 = pl >= vlo && pl < vhi && lim > (pfx4 ? 3u : 2u);
+                            if (pass2 && pfx4) {
+                                // both bits of the first four bytes' hash must be set
+                                const uint64_t m = (uint64_t)by * im.pfx4_mul;
+                                const uint32_t sh = 32u - im.pfx4_log2;
+                                const uint32_t h1 = (uint32_t)m >> sh, h2 = (uint32_t)(m >> 32) >> sh;
+                                pass2 = ((s_pfx4[h1 >> 5] >> (h1 & 31)) & (s_pfx4[h2 >> 5] >> (h2 & 31)) & 1u) != 0;
+                            }
                             if (pass2) {
                                 const uint32_t code = __builtin_amdgcn_perm(0u, by, 0x0c0c0001u);
                                 const uint32_t bits = s_bits[code >> 5];
@@ -838,6 +849,7 @@ void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit, bool split
     a.root_words = a.im.K == 0 ? std::max(1u, (1u << a.im.b) / 32) : 0u;
     a.off_root = take(4 * a.root_words);
     a.off_krec = take(4 * a.krec_words);
+    a.off_pfx4 = take(4 * a.pfx4_words);
     a.off_sym = take(a.im.identity ? 0 : 256);
     a.off_wave = off;
     // the split filter kernel keeps no candidate or match lists in LDS

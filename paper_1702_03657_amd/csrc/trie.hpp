@@ -81,7 +81,16 @@ struct DeviceImageHost {
     // Child labels of every depth-K node in breadth-first order: bytes 0..2
     // hold up to three labels, byte 3 the count (0xff when there are more).
     std::vector<uint32_t> krec;
+    // Prefix-4 filter (byte alphabets, every pattern of 4 bytes or more): a
+    // bitmap of 2^pfx4_log2 bits in which each pattern's first four bytes
+    // x = B0 | B1 << 8 | B2 << 16 | B3 << 24 set the two bits named by the
+    // top pfx4_log2 bits of the low and of the high word of x * kPfx4Mul.  A
+    // start position with either bit clear matches no pattern.
+    uint32_t pfx4_log2 = 0;            // 0 = no filter
+    std::vector<uint32_t> pfx4;
 };
+
+constexpr uint32_t kPfx4Mul = 0x9E3779B1u;
 
 // Derives the device image from the CRS trie for a level index of at most
 // `index_bits` bits and a prefix filter of `fold_bits` (0, 8 or 16) bits per

@@ -264,6 +264,26 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
         I.krec[v - v0] = rec;
     }
 
+    // prefix-4 filter: about 16 bits per distinct 4-byte prefix, 2^10..2^18
+    I.pfx4_log2 = 0;
+    I.pfx4.clear();
+    if (I.identity && T.k && T.min_len >= 4 && T.level_start.size() > 5) {
+        const uint32_t n4 = T.level_start[5] - T.level_start[4];  // depth-4 nodes
+        uint32_t lg = 10;
+        while (lg < 18 && (1ull << lg) < 16ull * n4) lg++;
+        I.pfx4_log2 = lg;
+        I.pfx4.assign((1u << lg) / 32, 0);
+        for (uint32_t v = T.level_start[4]; v < T.level_start[5]; v++) {
+            const uint8_t *p = T.pat_data.data() + T.pat_off[T.rep[v]];
+            const uint32_t x = (uint32_t)p[0] | (uint32_t)p[1] << 8 | (uint32_t)p[2] << 16 |
+                               (uint32_t)p[3] << 24;
+            const uint64_t m = (uint64_t)x * kPfx4Mul;
+            const uint32_t h1 = (uint32_t)m >> (32 - lg), h2 = (uint32_t)(m >> 32) >> (32 - lg);
+            I.pfx4[h1 >> 5] |= 1u << (h1 & 31);
+            I.pfx4[h2 >> 5] |= 1u << (h2 & 31);
+        }
+    }
+
     // prefix filter over the depth-(K+m) nodes
     if (fold_bits != 8 && fold_bits != 16) return;
     const uint32_t log2e = fold_bits == 8 ? 3 : 4;

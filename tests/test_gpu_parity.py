@@ -37,10 +37,10 @@ def test_c1_full_size_against_brute_force():
 TUNINGS = (
     [dict(kernel=0, bytes_per_lane=bpl, index_bits=bits) for bpl in (4, 8, 16) for bits in (8, 12, 16, 18)]
     + [dict(kernel=1, index_bits=bits, fold_bits=fold, waves_per_wg=w, chunks_per_unit=g, child_check=cc)
-       for bits in (8, 12, 16, 18) for fold in (0, 8, 16) for (w, g, cc) in ((4, 1, 0), (16, 16, 1), (12, 64, 1))]
+       for bits in (8, 12, 16, 18) for fold in (0, 8, 16) for (w, g, cc) in ((4, 1, 0), (16, 16, 1), (12, 64, 1), (12, 16, 2))]
     # split filter + walk kernels
     + [dict(kernel=2, index_bits=bits, fold_bits=fold, waves_per_wg=w, chunks_per_unit=g, child_check=cc)
-       for bits in (8, 12, 16, 18) for fold in (0, 8, 16) for (w, g, cc) in ((4, 1, 0), (16, 32, 1))]
+       for bits in (8, 12, 16, 18) for fold in (0, 8, 16) for (w, g, cc) in ((4, 1, 0), (16, 32, 1), (16, 16, 2), (8, 4, 2))]
 )
 
 
