@@ -404,9 +404,13 @@ def main():
 
     gbit_s = n * 8 / (ms_per_step / 1e3) / 1e9
     image_bytes = int(st["bytes_device"])
-    alg_bytes = n + 16 * n_matches + image_bytes
+    split = int(st["scan_kernel"]) == 2
+    # the timed kernel reads the text and the image once; the tile and fused
+    # wave kernels also write the 16-byte match records (the walk kernel
+    # writes them on the split path)
+    alg_bytes = n + image_bytes + (0 if split else 16 * n_matches)
     achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
-    kernel_name = "scan_waves" if st["scan_kernel"] == 1 else "scan_tiles"
+    kernel_name = "scan_waves" if int(st["scan_kernel"]) in (1, 2) else "scan_tiles"
     traffic = traffic_from_profiles(kernel_name, args.workload, tuning)
 
     if args.copy_probe:
