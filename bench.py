@@ -135,28 +135,19 @@ def run_copy_probe(torch, nbytes):
     log(f"copy probe: 3 copies of {nbytes} bytes")
 
 
-def extras_batched(pf, torch, steps, oracle_threads=0):
-    """C4: one graph-captured persistent launch vs one launch per text."""
+def _graph_vs_plain(pf, torch, trie, ws, text_host, offs_host, steps, cap):
+    """One graph-captured batched launch vs one plain launch per text, on the
+    same device copy of a batch: (batched ms, plain ms, batched list, counts)."""
     import numpy as np
-    from synth import workloads
-    t0 = time.time()
-    wl = workloads.c4_batched()
-    log(f"c4 generated in {time.time() - t0:.1f}s: {wl.n_texts} texts, {wl.text.size} bytes")
-    trie = pf.Trie(wl.patterns)
-    ws = pf.Workspace()
-    text = torch.from_numpy(wl.text).cuda()
-    offs_host = wl.offsets.astype(np.uint64)
+    text = torch.from_numpy(text_host).cuda()
     offs = torch.from_numpy(offs_host.view(np.int64)).cuda()
+    n_texts = len(offs_host) - 1
     total = int(offs_host[-1])
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
-    cap = 4 << 20
     out = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.Stream()
-    res = {"workload": "c4: 65,536 texts lognormal(512, 0.75) clipped [64,1500] B + 64 texts "
-                       "U[1,64] MiB; 20,000 patterns len U[8,64]; copies 1 per 2 KiB",
-           "texts": wl.n_texts, "text_bytes": total}
     with torch.cuda.stream(stream):
-        g = pf.Graph(trie, ws, text, offs, wl.n_texts, total, out, cap, cnt, stream)
+        g = pf.Graph(trie, ws, text, offs, n_texts, total, out, cap, cnt, stream)
         g.launch(stream)
         stream.synchronize()
         n_batched = int(cnt.item())
@@ -168,16 +159,38 @@ def extras_batched(pf, torch, steps, oracle_threads=0):
         e1.record(stream)
         stream.synchronize()
         ms_b = e0.elapsed_time(e1) / steps
-        pf.pfac_scan_batch_plain(trie, ws, text, offs_host, wl.n_texts, out, cap, cnt, stream)
+        pf.pfac_scan_batch_plain(trie, ws, text, offs_host, n_texts, out, cap, cnt, stream)
         stream.synchronize()
         n_plain = int(cnt.item())
         plain_steps = max(1, min(steps, 3))
         e0.record(stream)
         for _ in range(plain_steps):
-            pf.pfac_scan_batch_plain(trie, ws, text, offs_host, wl.n_texts, out, cap, cnt, stream)
+            pf.pfac_scan_batch_plain(trie, ws, text, offs_host, n_texts, out, cap, cnt, stream)
         e1.record(stream)
         stream.synchronize()
         ms_p = e0.elapsed_time(e1) / plain_steps
+    g.close()
+    return ms_b, ms_p, batched_list, n_batched, n_plain
+
+
+def extras_batched(pf, torch, steps, oracle_threads=0):
+    """C4: one graph-captured persistent launch vs one launch per text, for
+    all texts, the small texts only and the large texts only."""
+    import numpy as np
+    from synth import workloads
+    t0 = time.time()
+    wl = workloads.c4_batched()
+    log(f"c4 generated in {time.time() - t0:.1f}s: {wl.n_texts} texts, {wl.text.size} bytes")
+    trie = pf.Trie(wl.patterns)
+    ws = pf.Workspace()
+    offs_host = wl.offsets.astype(np.uint64)
+    total = int(offs_host[-1])
+    cap = 4 << 20
+    res = {"workload": "c4: 65,536 texts lognormal(512, 0.75) clipped [64,1500] B + 64 texts "
+                       "U[1,64] MiB; 20,000 patterns len U[8,64]; copies 1 per 2 KiB",
+           "texts": wl.n_texts, "text_bytes": total}
+    ms_b, ms_p, batched_list, n_batched, n_plain = _graph_vs_plain(
+        pf, torch, trie, ws, wl.text, offs_host, steps, cap)
     if oracle_threads:
         import oracle
         want = oracle.bucketed(wl.text, wl.patterns, offsets=wl.offsets, threads=oracle_threads)
@@ -192,7 +205,20 @@ def extras_batched(pf, torch, steps, oracle_threads=0):
         "plain_gbit_s": round(total * 8 / ms_p / 1e6, 2),
         "speedup": round(ms_p / ms_b, 2),
     })
-    g.close()
+    # the same comparison on each kind of text alone
+    lens = np.diff(offs_host.astype(np.int64))
+    for name, sel in (("small_texts", lens <= 1500), ("large_texts", lens > 1500)):
+        idx = np.nonzero(sel)[0]
+        parts = [wl.text[int(offs_host[i]):int(offs_host[i + 1])] for i in idx]
+        sub = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+        so = np.zeros(len(idx) + 1, dtype=np.uint64)
+        so[1:] = np.cumsum(lens[idx])
+        b, p, _, nb, npl = _graph_vs_plain(pf, torch, trie, ws, sub, so, steps, cap)
+        res[name] = {"texts": int(len(idx)), "text_bytes": int(so[-1]), "matches": nb,
+                     "plain_matches_equal": nb == npl,
+                     "batched_gbit_s": round(int(so[-1]) * 8 / b / 1e6, 2),
+                     "plain_gbit_s": round(int(so[-1]) * 8 / p / 1e6, 2),
+                     "speedup": round(p / b, 2)}
     return res
 
 
@@ -202,9 +228,10 @@ def _percentiles(lat_s):
     return round(float(np.percentile(a, 50)), 3), round(float(np.percentile(a, 99)), 3)
 
 
-def extras_serving(pf, torch, n_requests, rate_per_s, budget_bytes):
-    """C5: Poisson arrivals at a fixed offered rate into the continuous-batching
-    server, against one request at a time (copy in, scan, copy out, next)."""
+def extras_serving(pf, torch, n_requests, rates, budget_bytes):
+    """C5: Poisson arrivals at fixed offered rates into the continuous-batching
+    server, against one request at a time (copy in, scan, copy out, next) on
+    the same arrival trace."""
     import threading
 
     import numpy as np
@@ -217,17 +244,15 @@ def extras_serving(pf, torch, n_requests, rate_per_s, budget_bytes):
     total = int(offs[-1])
     host = torch.from_numpy(wl.text).pin_memory()  # request bodies in pinned host memory
     base_ptr = host.data_ptr()
-    arrivals = workloads.poisson_arrivals(n_requests, rate_per_s)
     trie = pf.Trie(wl.patterns)
     max_n = int(sizes.max())
     res = {"workload": f"c5: {n_requests} requests, sizes log-uniform [1 KiB, 64 MiB] "
                        f"(mean {sizes.mean() / 2**20:.2f} MiB), 50,000 patterns len U[8,64], "
-                       f"copies 1 per 2 KiB; Poisson arrivals",
-           "offered_req_s": rate_per_s,
-           "offered_gbit_s": round(sizes.mean() * 8 * rate_per_s / 1e9, 2),
-           "hbm_budget_bytes": budget_bytes}
+                       f"copies 1 per 2 KiB; Poisson arrivals; latency = arrival to results "
+                       f"in host memory",
+           "hbm_budget_bytes": budget_bytes, "max_batch": 64, "points": []}
 
-    # ---- one request at a time
+    # one request at a time
     stream = torch.cuda.Stream()
     ws = pf.Workspace()
     dev = torch.empty(max_n + 16, dtype=torch.uint8, device="cuda")
@@ -247,57 +272,62 @@ def extras_serving(pf, torch, n_requests, rate_per_s, budget_bytes):
                 out_host[:16 * min(n, cap)].copy_(out[:16 * min(n, cap)])
         return n
 
-    serve_one(0)  # warm-up
-    lat_base, n_base = [], 0
-    start = time.perf_counter()
-    for i in range(n_requests):
-        due = start + arrivals[i]
-        while time.perf_counter() < due:
-            pass
-        n_base += serve_one(i)
-        lat_base.append(time.perf_counter() - due)
-    end_base = time.perf_counter() - start
-    p50b, p99b = _percentiles(lat_base)
-    res["one_at_a_time"] = {"p50_ms": p50b, "p99_ms": p99b, "matches": n_base,
-                            "served_gbit_s": round(total * 8 / end_base / 1e9, 2)}
-
-    # ---- the server
+    # the server
     arena = torch.empty(budget_bytes + (256 << 20), dtype=torch.uint8, device="cuda")
     cs, xs = torch.cuda.Stream(), torch.cuda.Stream()
     srv = pf.Server(trie, arena, budget_bytes, 64, cs, xs)
-    # warm-up request
-    rid = srv.submit_ptr(base_ptr, int(sizes[0]))
-    srv.wait(rid, capacity=cap)
-    ids = [None] * n_requests
-    lat_srv = [0.0] * n_requests
-    n_srv = [0]
-    ready = threading.Semaphore(0)
+    serve_one(0)  # warm-ups
+    srv.wait(srv.submit_ptr(base_ptr, int(sizes[0])), capacity=cap)
 
-    def waiter():
+    for rate in rates:
+        arrivals = workloads.poisson_arrivals(n_requests, rate)
+        lat_base, n_base = [], 0
+        start = time.perf_counter()
         for i in range(n_requests):
-            ready.acquire()
-            m, lat = srv.wait(ids[i], capacity=cap)
-            lat_srv[i] = lat
-            n_srv[0] += m.size
+            due = start + arrivals[i]
+            while time.perf_counter() < due:
+                pass
+            n_base += serve_one(i)
+            lat_base.append(time.perf_counter() - due)
+        end_base = time.perf_counter() - start
 
-    th = threading.Thread(target=waiter)
-    th.start()
-    start = time.perf_counter()
-    for i in range(n_requests):
-        due = start + arrivals[i]
-        while time.perf_counter() < due:
-            pass
-        ids[i] = srv.submit_ptr(base_ptr + int(offs[i]), int(sizes[i]))
-        ready.release()
-    th.join()
-    end_srv = time.perf_counter() - start
-    st = srv.stats()
+        b0 = srv.stats()["batches"]
+        ids = [None] * n_requests
+        lat_srv = [0.0] * n_requests
+        n_srv = [0]
+        ready = threading.Semaphore(0)
+
+        def waiter():
+            for i in range(n_requests):
+                ready.acquire()
+                m, lat = srv.wait(ids[i], capacity=cap)
+                lat_srv[i] = lat
+                n_srv[0] += m.size
+
+        th = threading.Thread(target=waiter)
+        th.start()
+        start = time.perf_counter()
+        for i in range(n_requests):
+            due = start + arrivals[i]
+            while time.perf_counter() < due:
+                pass
+            ids[i] = srv.submit_ptr(base_ptr + int(offs[i]), int(sizes[i]))
+            ready.release()
+        th.join()
+        end_srv = time.perf_counter() - start
+        p50b, p99b = _percentiles(lat_base)
+        p50s, p99s = _percentiles(lat_srv)
+        res["points"].append({
+            "offered_req_s": rate,
+            "offered_gbit_s": round(sizes.mean() * 8 * rate / 1e9, 2),
+            "one_at_a_time": {"p50_ms": p50b, "p99_ms": p99b,
+                              "served_gbit_s": round(total * 8 / end_base / 1e9, 2)},
+            "server": {"p50_ms": p50s, "p99_ms": p99s,
+                       "served_gbit_s": round(total * 8 / end_srv / 1e9, 2),
+                       "batches": srv.stats()["batches"] - b0},
+            "same_matches": n_srv[0] == n_base,
+        })
     srv.close()
-    p50s, p99s = _percentiles(lat_srv)
-    res["server"] = {"p50_ms": p50s, "p99_ms": p99s, "matches": n_srv[0],
-                     "served_gbit_s": round(total * 8 / end_srv / 1e9, 2),
-                     "batches": st["batches"] - 1, "max_batch": 64}
-    res["same_matches"] = n_srv[0] == n_base
     return res
 
 
@@ -317,7 +347,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving loop (c5) against one request at a time")
     ap.add_argument("--serving-requests", type=int, default=200)
-    ap.add_argument("--serving-rate", type=float, default=1000.0, help="offered requests per second")
+    ap.add_argument("--serving-rates", default="1000,4000,8000",
+                    help="offered requests per second, one measurement per rate")
     ap.add_argument("--serving-budget", type=int, default=1 << 30, help="HBM bytes for request texts")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of the text size (counter calibration)")
@@ -477,7 +508,8 @@ def main():
             pf, torch, max(3, args.steps // 5),
             0 if args.no_cpu_baseline else (args.cpu_threads or min(16, os.cpu_count() or 1)))
     if not args.no_serving:
-        line["serving"] = extras_serving(pf, torch, args.serving_requests, args.serving_rate,
+        line["serving"] = extras_serving(pf, torch, args.serving_requests,
+                                         [float(x) for x in args.serving_rates.split(",")],
                                          args.serving_budget)
 
     print(json.dumps(line), flush=True)

@@ -68,6 +68,7 @@ struct pfac_server {
     uint64_t budget = 0;
     uint32_t max_batch = 1;
     hipStream_t cs = nullptr, xs = nullptr;
+    hipStream_t ds = nullptr;  // own stream for result copies (device to host)
     int device = 0;
     Slot slot[2];
 
@@ -141,16 +142,17 @@ struct pfac_server {
         }
     }
 
-    // Ready requests contiguous in the ring, in ring order, up to max_batch.
+    // Admitted requests not yet scanned, contiguous in the ring, in ring
+    // order, up to max_batch.  Their copies may still be in flight: the scan
+    // waits for them on the device.
     void form_batch_locked(std::vector<Req *> &b) {
         b.clear();
         for (Req *r : in_ring) {
-            if (r->st == St::Copying && hipEventQuery(r->copied) == hipSuccess) r->st = St::Ready;
             if (r->st == St::Scanning || r->st == St::Done) {
                 if (b.empty()) continue;
                 break;
             }
-            if (r->st != St::Ready) break;
+            if (r->st != St::Ready && r->st != St::Copying) break;
             if (!b.empty()) {
                 const Req *p = b.back();
                 if (p->ring_off + p->n != r->ring_off) break;  // ring wrapped
@@ -169,6 +171,10 @@ struct pfac_server {
         hipError_t e = hipMemcpyAsync(S.offsets_dev, S.offsets_host, 8 * (b.size() + 1),
                                       hipMemcpyHostToDevice, cs);
         if (e != hipSuccess) return PFAC_EDEVICE;
+        // the scan starts once every text of the batch has landed
+        for (Req *r : b)
+            if (r->st == St::Copying && hipStreamWaitEvent(cs, r->copied, 0) != hipSuccess)
+                return PFAC_EDEVICE;
         int rc = pfac_scan_batch(t, S.ws, ring + base, S.offsets_dev, (uint32_t)b.size(), total,
                                  S.out_dev, S.out_cap, S.count_dev, cs);
         if (rc != PFAC_OK) return rc;
@@ -209,9 +215,13 @@ struct pfac_server {
         const uint64_t cnt = *S.count_host;
         std::vector<uint64_t> start(S.reqs.size() + 1, 0);
         if (cnt <= S.out_cap) {
-            if (cnt)
-                (void)hipMemcpy(S.out_host, S.out_dev, cnt * sizeof(pfac_match),
-                                hipMemcpyDeviceToHost);
+            if (cnt) {
+                // the batch has ended (its event was seen): copy on our own stream,
+                // behind nothing queued on the compute or copy streams
+                (void)hipMemcpyAsync(S.out_host, S.out_dev, cnt * sizeof(pfac_match),
+                                     hipMemcpyDeviceToHost, ds);
+                (void)hipStreamSynchronize(ds);
+            }
             // records are sorted by text id: split by a linear sweep
             uint64_t k = 0;
             for (size_t i = 0; i < S.reqs.size(); i++) {
@@ -276,7 +286,14 @@ struct pfac_server {
                 }
                 if (stop && queue.empty() && in_ring.empty() && !slot[0].busy && !slot[1].busy)
                     break;
-                if (!did) cv_work.wait_for(lock, std::chrono::microseconds(50));
+                // poll briefly while work is on the device, sleep when idle
+                const bool busy = slot[0].busy || slot[1].busy || !in_ring.empty();
+                if (!did) {
+                    if (busy)
+                        cv_work.wait_for(lock, std::chrono::microseconds(5));
+                    else
+                        cv_work.wait_for(lock, std::chrono::milliseconds(2));
+                }
             }
         }
     }
@@ -298,6 +315,10 @@ extern "C" int pfac_server_create(const pfac_trie *t, void *arena_dev, uint64_t 
     s->cs = (hipStream_t)compute_stream;
     s->xs = (hipStream_t)copy_stream;
     (void)hipGetDevice(&s->device);
+    if (hipStreamCreateWithFlags(&s->ds, hipStreamNonBlocking) != hipSuccess) {
+        delete s;
+        return PFAC_EDEVICE;
+    }
     // arena: [ text ring (budget) | slot 0 | slot 1 ]
     uint8_t *a = (uint8_t *)arena_dev;
     const uint64_t rest = arena_bytes - budget_bytes;
@@ -335,6 +356,7 @@ extern "C" int pfac_server_create(const pfac_trie *t, void *arena_dev, uint64_t 
             if (S.done) (void)hipEventDestroy(S.done);
             pfac_workspace_free(S.ws);
         }
+        (void)hipStreamDestroy(s->ds);
         delete s;
         return rc;
     }
@@ -433,5 +455,6 @@ extern "C" void pfac_server_free(pfac_server *s) {
         if (kv.second->copied) (void)hipEventDestroy(kv.second->copied);
         delete kv.second;
     }
+    if (s->ds) (void)hipStreamDestroy(s->ds);
     delete s;
 }
