@@ -118,7 +118,9 @@ static int upload_image(pfac_trie *t) {
     size_t o_chain = align256(o_root + std::max<size_t>(I.root_bits.size(), 1) * 4);
     size_t o_krec = align256(o_chain + std::max<size_t>(I.chain.size(), 64));
     size_t o_pfx4 = align256(o_krec + std::max<size_t>(I.krec.size(), 1) * 4);
-    size_t total = align256(o_pfx4 + std::max<size_t>(I.pfx4.size(), 1) * 4);
+    size_t o_q16 = align256(o_pfx4 + std::max<size_t>(I.pfx4.size(), 1) * 4);
+    size_t o_qfp = align256(o_q16 + std::max<size_t>(I.q16.size(), 1) * 4);
+    size_t total = align256(o_qfp + std::max<size_t>(I.qfp.size(), 16) * 2);
     auto t0 = std::chrono::steady_clock::now();
     t->dev.release();
     HIP_TRY(t->dev.reserve(total));
@@ -138,6 +140,10 @@ static int upload_image(pfac_trie *t) {
         HIP_TRY(hipMemcpy(b + o_chain, I.chain.data(), I.chain.size(), hipMemcpyHostToDevice));
     if (!I.pfx4.empty())
         HIP_TRY(hipMemcpy(b + o_pfx4, I.pfx4.data(), I.pfx4.size() * 4, hipMemcpyHostToDevice));
+    if (!I.q16.empty())
+        HIP_TRY(hipMemcpy(b + o_q16, I.q16.data(), I.q16.size() * 4, hipMemcpyHostToDevice));
+    if (!I.qfp.empty())
+        HIP_TRY(hipMemcpy(b + o_qfp, I.qfp.data(), I.qfp.size() * 2, hipMemcpyHostToDevice));
     if (!I.root_bits.empty())
         HIP_TRY(hipMemcpy(b + o_root, I.root_bits.data(), I.root_bits.size() * 4, hipMemcpyHostToDevice));
     ImageView &v = t->view;
@@ -154,6 +160,14 @@ static int upload_image(pfac_trie *t) {
     v.pfx4 = (const uint32_t *)(b + o_pfx4);
     v.pfx4_log2 = I.pfx4_log2;
     v.pfx4_mul = kPfx4Mul;
+    v.q16 = (const uint32_t *)(b + o_q16);
+    v.qfp = (const uint4 *)(b + o_qfp);
+    v.q16_lw = I.q16_lw;
+    v.qfp_lb = I.qfp_lb;
+    v.qa = I.qa;
+    v.qb = I.qb;
+    v.qalph = I.qalph;
+    v.q16_mul = kQ16Mul;
     v.fold_syms = I.fold_syms;
     v.K = I.K;
     v.b = I.b;
@@ -202,6 +216,7 @@ static int build_common(const uint8_t *data, const uint64_t *offsets, uint32_t k
     // otherwise (small alphabets and short patterns leave many candidates)
     if (t->img.identity && t->img.K == 2) t->tuning.kernel = 2;
     if (t->img.pfx4_log2) t->tuning.child_check = 2;
+    if (t->img.q16_lw) t->tuning.kernel = 2;  // four-symbol alphabets: the 16-symbol filter
     t->build_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     set_halo(t);
     t->host_only = (flags & PFAC_BUILD_HOST_ONLY) != 0;
@@ -274,6 +289,9 @@ static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr) {
         // child_check 2: the prefix-4 filter where the image has one, else
         // the child records; dropped last when the layout does not fit
         const bool pfx4 = t->tuning.child_check == 2 && t->img.pfx4_log2 != 0;
+        // the split kernel filters four-symbol alphabets with the 16-symbol
+        // filter when the image has one
+        a.q16_words = (t->tuning.kernel == 2 && t->img.q16_lw) ? (1u << t->img.q16_lw) : 0u;
         for (int with_rec = (t->tuning.child_check && t->img.K) ? 1 : 0; with_rec >= 0; with_rec--) {
             a.krec_words = with_rec && !pfx4 ? (uint32_t)t->img.krec.size() : 0u;
             a.pfx4_words = with_rec && pfx4 ? (uint32_t)t->img.pfx4.size() : 0u;

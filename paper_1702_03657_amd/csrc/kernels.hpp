@@ -29,9 +29,13 @@ struct ImageView {
     const uint8_t *chain;     // labels of compressed single-child runs
     const uint32_t *krec;     // per depth-K node: up to three child labels, count in the top byte
     const uint32_t *pfx4;     // prefix-4 filter bitmap (2^pfx4_log2 bits)
+    const uint32_t *q16;      // four-symbol filter: bitmap words (2^q16_lw)
+    const uint4 *qfp;         // four-symbol filter: buckets of 16 x 16-bit fingerprints (2 x uint4)
     uint32_t K, b, identity, lvl_words;
     uint32_t lvl_start, max_len, n_nodes, fold_syms;
     uint32_t pfx4_log2, pfx4_mul;     // prefix-4 filter: 2^pfx4_log2 bits, hash multiplier
+    uint32_t q16_lw, qfp_lb;          // four-symbol filter sizes (0 = none)
+    uint32_t qa, qb, qalph, q16_mul;  // its symbol map, alphabet bytes and hash multiplier
 };
 
 struct ScanArgs {
@@ -56,6 +60,8 @@ struct ScanArgs {
     uint32_t off_wave, wave_bytes, woff_bnd, woff_queue, woff_cand, woff_match, ccap, mcap;
     uint32_t krec_words, off_krec, group, pad1;   // LDS child records, chunks per unit
     uint32_t pfx4_words, off_pfx4;    // LDS prefix-4 filter (instead of the child records)
+    uint32_t q16_words;               // four-symbol filter words in LDS (mode 3; 0 = other modes)
+    uint32_t lvl_lds;                 // level-index words kept in LDS (0 in mode 3)
     // outputs
     pfac_match *stage;
     uint64_t stage_cap;

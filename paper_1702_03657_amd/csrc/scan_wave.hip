@@ -44,6 +44,8 @@ typedef __attribute__((address_space(3))) const uint8_t lds_u8_t;
 typedef __attribute__((address_space(3))) const uint16_t lds_u16_t;
 __device__ __forceinline__ const lds_u8_t *lds_tab8() { return (const lds_u8_t *)(uintptr_t)0; }
 __device__ __forceinline__ const lds_u16_t *lds_tab16() { return (const lds_u16_t *)(uintptr_t)0; }
+typedef __attribute__((address_space(3))) const uint32_t lds_u32_t;
+__device__ __forceinline__ const lds_u32_t *lds_tab32() { return (const lds_u32_t *)(uintptr_t)0; }
 
 __device__ __forceinline__ uint32_t wave_excl_scan(uint32_t x, uint32_t &total) {
     const uint32_t incl = wave_incl_scan(x);
@@ -342,9 +344,11 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     }
 
     // ---- shared tables, once per workgroup
-    for (uint32_t i = tid; i < a.ftab_bytes / 16; i += nthreads)
-        ((uint4 *)s_ftab)[i] = ((const uint4 *)im.ftab)[i];
-    for (uint32_t i = tid; i < im.lvl_words; i += nthreads) {
+    {
+        const uint4 *tab = (const uint4 *)(a.q16_words ? (const void *)im.q16 : (const void *)im.ftab);
+        for (uint32_t i = tid; i < a.ftab_bytes / 16; i += nthreads) ((uint4 *)s_ftab)[i] = tab[i];
+    }
+    for (uint32_t i = tid; i < a.lvl_lds; i += nthreads) {
         const uint2 e = ((const uint2 *)im.lvl)[i];
         s_bits[i] = e.x;
         s_rank[i] = e.y;
@@ -625,6 +629,117 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                     }
                     wave_sync();
                 }
+            } else if (MODE == 3) {
+                // ---- four-symbol alphabets.  Stage 1: the lane's 32 bytes
+                // as 2-bit symbols (symbol j at bits 2j of P), the 16-symbol
+                // key of position j = bits [2j, 2j + 32), one LDS word of the
+                // filter per position, two bits of it tested.
+                const uint32_t qa = im.qa, qb = im.qb;
+                auto pack4 = [&](uint32_t x) -> uint32_t {
+                    const uint32_t t = ((x >> qa) ^ (x >> qb)) & 0x03030303u;
+                    const uint32_t u = t | (t >> 6);
+                    return (u | (u >> 12)) & 0xffu;
+                };
+                const uint32_t P0 = pack4(w[0]) | pack4(w[1]) << 8 | pack4(w[2]) << 16 | pack4(w[3]) << 24;
+                const uint32_t P1 = pack4(w[4]) | pack4(w[5]) << 8 | pack4(w[6]) << 16 | pack4(w[7]) << 24;
+                const uint32_t qsh = 32u - im.q16_lw;
+                uint32_t hh[16], ent[16];
+#pragma unroll
+                for (int j = 0; j < 16; j++) {
+                    const uint32_t key = j == 0 ? P0 : __builtin_amdgcn_alignbit(P1, P0, 2 * j);
+                    hh[j] = (key & 0xffffffu) * im.q16_mul + (key >> 8);
+                    ent[j] = lds_tab32()[hh[j] >> qsh];
+                }
+                uint32_t hm = 0;
+#pragma unroll
+                for (int j = 0; j < 16; j++)
+                    hm |= ((ent[j] >> hh[j]) & (ent[j] >> (hh[j] >> 5)) & 1u) << j;
+                uint16_t *wq16 = (uint16_t *)wq;
+                uint32_t tot;
+                const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
+                const int rounds = tot > kQ16 ? 2 : 1;
+                const uint32_t vlo = lo_valid > chunk_lo ? (uint32_t)min(lo_valid - chunk_lo, (uint64_t)kWin) : 0u;
+                const uint32_t vhi = hi_valid > chunk_lo ? (uint32_t)min(hi_valid - chunk_lo, (uint64_t)kWin) : 0u;
+                const uint32_t nb_rel = (uint32_t)min(next_bnd - chunk_lo, (unsigned long long)0x20000);
+                for (int half = 0; half < rounds; half++) {
+                    uint32_t mset = hm, o = off_all, qn = tot, jb = 0;
+                    if (rounds == 2) {
+                        mset = half == 0 ? (hm & 0xffu) : (hm >> 8);
+                        jb = half == 0 ? 0u : 8u;
+                        o = wave_excl_scan((uint32_t)__builtin_popcount(mset), qn);
+                    }
+                    while (mset) {
+                        const uint32_t j = (uint32_t)__builtin_ctz(mset);
+                        wq16[o++] = (uint16_t)(16 * lane + jb + j);
+                        mset &= mset - 1;
+                    }
+                    wave_sync();
+                    // ---- stage 2: the 16 bytes all in this text and all of
+                    // the alphabet, the key's fingerprint in its buckets,
+                    // then the depth-K node from the level index
+                    for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
+                        const uint32_t e = r0 + lane;
+                        bool pass2 = false;
+                        uint32_t entry = 0, v = 0, pl = 0;
+                        if (e < qn) {
+                            pl = wq16[e];
+                            const uint32_t lim = dirty ? limit_after(wbnd, dirty, chunk_lo, pl, next_bnd)
+                                                       : min(nb_rel - pl, 0xffffu);
+                            pass2 = pl >= vlo && pl < vhi && lim >= 16u;
+                            entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
+                            uint32_t key = 0;
+                            if (pass2) {
+                                const uint32_t *t32 = (const uint32_t *)(wtext + (pl & ~3u));
+                                uint32_t d[5];
+#pragma unroll
+                                for (int k = 0; k < 5; k++) d[k] = t32[k];
+                                bool valid = true;
+#pragma unroll
+                                for (int k = 0; k < 4; k++) {
+                                    const uint32_t x = __builtin_amdgcn_alignbyte(d[k + 1], d[k], pl & 3u);
+                                    const uint32_t t = ((x >> qa) ^ (x >> qb)) & 0x03030303u;
+                                    valid = valid && __builtin_amdgcn_perm(0u, im.qalph, t) == x;
+                                    const uint32_t u = t | (t >> 6);
+                                    key |= ((u | (u >> 12)) & 0xffu) << (8 * k);
+                                }
+                                pass2 = valid;
+                            }
+                            if (pass2 && im.qfp_lb) {
+                                const uint32_t h2 = key * a.im.pfx4_mul;
+                                const uint32_t fp = (h2 & 0xffffu) | 1u;
+                                const uint32_t nb = 1u << im.qfp_lb;
+                                const uint32_t bk = h2 >> (32u - im.qfp_lb);
+                                const uint4 *b0 = im.qfp + 2 * bk, *b1 = im.qfp + 2 * ((bk + 1) & (nb - 1));
+                                const uint4 f[4] = {b0[0], b0[1], b1[0], b1[1]};
+                                const uint32_t fp2 = fp * 0x00010001u;
+                                uint32_t hit = 0;
+#pragma unroll
+                                for (int k = 0; k < 4; k++) {
+                                    const uint32_t wv[4] = {f[k].x, f[k].y, f[k].z, f[k].w};
+#pragma unroll
+                                    for (int q = 0; q < 4; q++) {
+                                        const uint32_t x = wv[q] ^ fp2;  // a zero half = equal fingerprint
+                                        hit |= (x - 0x00010001u) & ~x & 0x80008000u;
+                                    }
+                                }
+                                pass2 = hit != 0;
+                            }
+                            if (pass2) {
+                                // depth-K code, first symbol highest: the low
+                                // 2K bits of the key with the symbol order reversed
+                                const uint32_t r = __builtin_bitreverse32(key);
+                                uint32_t code = ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
+                                code >>= 32u - 2u * K;
+                                const uint2 lv = ((const uint2 *)im.lvl)[code >> 5];
+                                v = im.lvl_start + lv.y +
+                                    (uint32_t)__builtin_popcount(lv.x & ((1u << (code & 31)) - 1u));
+                                pass2 = (lv.x >> (code & 31)) & 1u;
+                            }
+                        }
+                        push(pass2, __ballot(pass2), entry, v, pl);
+                    }
+                    wave_sync();
+                }
             } else {
                 // generic filter: rolling code over L = K + m symbols
                 const uint32_t b = im.b;
@@ -842,10 +957,14 @@ void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit, bool split
         return o;
     };
     a.ftab_bytes = (uint32_t)((a.fold && a.im.K) ? ((1ull << (a.im.b * a.im.K)) * (a.fold / 8)) : 0);
+    // mode 3: the four-symbol filter takes the table's place; the level
+    // index stays in global memory (only survivors of both filters read it)
+    if (a.q16_words) a.ftab_bytes = 4 * a.q16_words;
     a.ftab_bytes = (a.ftab_bytes + 15u) & ~15u;
     a.off_ftab = take(a.ftab_bytes);
-    a.off_bits = take(4 * a.im.lvl_words);
-    a.off_rank = take(4 * a.im.lvl_words);
+    a.lvl_lds = a.q16_words ? 0u : a.im.lvl_words;
+    a.off_bits = take(4 * a.lvl_lds);
+    a.off_rank = take(4 * a.lvl_lds);
     a.root_words = a.im.K == 0 ? std::max(1u, (1u << a.im.b) / 32) : 0u;
     a.off_root = take(4 * a.root_words);
     a.off_krec = take(4 * a.krec_words);
@@ -864,10 +983,12 @@ void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit, bool split
     (void)lds_limit;
 }
 
-// 0..2: fused kernels; 3..5: the split filter kernels of modes 0..2
+// 0..2: fused kernels; 3..5: the split filter kernels of modes 0..2; 6: the
+// split filter kernel of mode 3 (four-symbol alphabets)
 int wave_mode(const ScanArgs &a) {
     const int split = a.cand != nullptr ? 3 : 0;
-    if (a.off_ftab != 0) return split;  // modes 1 and 2 need the table at LDS address 0
+    if (a.off_ftab != 0) return split;  // modes 1..3 need the table at LDS address 0
+    if (split && a.q16_words) return 6;
     if (a.im.identity && a.im.K == 2 && a.fold == 8 && a.im.fold_syms == 1) return 1 + split;
     if (a.im.identity && a.im.K == 2 && a.fold == 16 && a.im.fold_syms == 1) return 2 + split;
     return split;
@@ -878,8 +999,9 @@ static const void *wave_fn(bool split) {
     return split ? (const void *)scan_waves<MODE, true> : (const void *)scan_waves<MODE, false>;
 }
 
-// modes 3..5 are the split variants of modes 0..2
+// modes 3..5 are the split variants of modes 0..2, 6 of mode 3
 static const void *wave_fn_for(int mode) {
+    if (mode == 6) return (const void *)scan_waves<3, true>;
     const bool split = mode >= 3;
     switch (mode % 3) {
         case 1: return wave_fn<1>(split);
@@ -908,6 +1030,7 @@ hipError_t launch_scan_waves(const ScanArgs &a, uint32_t waves, uint32_t grid, h
         case 3: hipLaunchKernelGGL((scan_waves<0, true>), dim3(grid), block, a.lds_total, s, a); break;
         case 4: hipLaunchKernelGGL((scan_waves<1, true>), dim3(grid), block, a.lds_total, s, a); break;
         case 5: hipLaunchKernelGGL((scan_waves<2, true>), dim3(grid), block, a.lds_total, s, a); break;
+        case 6: hipLaunchKernelGGL((scan_waves<3, true>), dim3(grid), block, a.lds_total, s, a); break;
         default: hipLaunchKernelGGL((scan_waves<0, false>), dim3(grid), block, a.lds_total, s, a); break;
     }
     return hipGetLastError();

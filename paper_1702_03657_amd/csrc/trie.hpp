@@ -88,7 +88,24 @@ struct DeviceImageHost {
     // start position with either bit clear matches no pattern.
     uint32_t pfx4_log2 = 0;            // 0 = no filter
     std::vector<uint32_t> pfx4;
+    // Four-symbol filter (alphabets of at most four bytes whose sorted bytes
+    // c_i satisfy ((c_i >> qa) ^ (c_i >> qb)) & 3 == i, every pattern of 16
+    // bytes or more).  key = the first 16 symbols, 2 bits each, symbol 0
+    // lowest; h = (key mod 2^24) * kQ16Mul + (key >> 8) mod 2^32.
+    //  - q16: 2^q16_lw words; word h >> (32 - q16_lw) has bits h & 31 and
+    //    (h >> 5) & 31 set for every distinct 16-symbol prefix;
+    //  - qfp: 2^qfp_lb buckets of 16 nonzero 16-bit fingerprints
+    //    (key * kPfx4Mul) & 0xffff | 1 in bucket (key * kPfx4Mul) >> (32 -
+    //    qfp_lb) or the next one (qfp_lb = 0: no fingerprints);
+    //  - qalph: byte i = c_i (an unused symbol holds a byte of another one).
+    uint32_t q16_lw = 0;               // 0 = no four-symbol filter
+    uint32_t qfp_lb = 0;
+    uint32_t qa = 0, qb = 0, qalph = 0;
+    std::vector<uint32_t> q16;
+    std::vector<uint16_t> qfp;
 };
+
+constexpr uint32_t kQ16Mul = 0x9E3779u;     // 24-bit odd multiplier
 
 constexpr uint32_t kPfx4Mul = 0x9E3779B1u;
 

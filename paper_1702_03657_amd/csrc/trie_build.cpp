@@ -284,6 +284,73 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
         }
     }
 
+    // four-symbol filter over the 16-symbol prefixes
+    I.q16_lw = I.qfp_lb = 0;
+    I.q16.clear();
+    I.qfp.clear();
+    if (!I.identity && I.b == 2 && T.k && T.min_len >= 16 && T.level_start.size() > 17) {
+        std::vector<uint8_t> alph;
+        for (int c = 0; c < 256; c++)
+            if (used[c]) alph.push_back((uint8_t)c);
+        bool found = false;
+        for (uint32_t qa = 0; qa <= 6 && !found; qa++)
+            for (uint32_t qb = qa + 1; qb <= 6 && !found; qb++) {
+                bool ok = true;
+                for (size_t i = 0; i < alph.size() && ok; i++)
+                    ok = (((alph[i] >> qa) ^ (alph[i] >> qb)) & 3u) == i;
+                if (ok) {
+                    found = true;
+                    I.qa = qa;
+                    I.qb = qb;
+                }
+            }
+        if (found) {
+            // unused symbols get a byte that maps to another symbol
+            I.qalph = 0;
+            for (uint32_t i = 0; i < 4; i++) {
+                const uint32_t c = i < alph.size() ? alph[i] : alph[0];
+                I.qalph |= c << (8 * i);
+            }
+            const uint32_t v0 = T.level_start[16], v1 = T.level_start[17];
+            const uint64_t n16 = v1 - v0;
+            uint32_t lg = 10;  // bits of the bitmap: about 10.5 per key, at most 2^20
+            while (lg < 20 && (1ull << lg) < 10ull * n16 + n16 / 2) lg++;
+            I.q16_lw = lg - 5;
+            I.q16.assign(1u << I.q16_lw, 0);
+            uint32_t lb = 0;  // buckets: about four keys each
+            while ((1ull << lb) * 4 < n16) lb++;
+            I.qfp_lb = std::max(lb, 1u);
+            const uint32_t nb = 1u << I.qfp_lb;
+            I.qfp.assign((size_t)nb * 16, 0);
+            bool fp_ok = true;
+            for (uint32_t v = v0; v < v1; v++) {
+                const uint8_t *p = T.pat_data.data() + T.pat_off[T.rep[v]];
+                uint32_t key = 0;
+                for (uint32_t i = 0; i < 16; i++) key |= (uint32_t)I.sym[p[i]] << (2 * i);
+                const uint32_t h = (uint32_t)((uint64_t)(key & 0xffffffu) * kQ16Mul + (key >> 8));
+                const uint32_t wd = h >> (32 - I.q16_lw);
+                I.q16[wd] |= (1u << (h & 31)) | (1u << ((h >> 5) & 31));
+                const uint32_t h2 = key * kPfx4Mul;
+                const uint32_t b = h2 >> (32 - I.qfp_lb);
+                const uint16_t fp = (uint16_t)((h2 & 0xffffu) | 1u);
+                bool put = false;
+                for (uint32_t q = 0; q < 2 && !put; q++) {
+                    uint16_t *bk = I.qfp.data() + (size_t)((b + q) & (nb - 1)) * 16;
+                    for (uint32_t s = 0; s < 16 && !put; s++)
+                        if (bk[s] == 0 || bk[s] == fp) {
+                            bk[s] = fp;
+                            put = true;
+                        }
+                }
+                fp_ok = fp_ok && put;
+            }
+            if (!fp_ok) {  // two full buckets: no fingerprint stage
+                I.qfp_lb = 0;
+                I.qfp.clear();
+            }
+        }
+    }
+
     // prefix filter over the depth-(K+m) nodes
     if (fold_bits != 8 && fold_bits != 16) return;
     const uint32_t log2e = fold_bits == 8 ? 3 : 4;

@@ -87,6 +87,48 @@ def test_dna_tuning_points(tuning):
     assert np.array_equal(counts, oracle.counts(wl.text.size, want))
 
 
+@pytest.mark.parametrize("case", ["dirty_text", "three_letters", "batch", "short_units"])
+def test_four_symbol_filter(case):
+    """The split kernel's 16-symbol filter: texts with bytes outside the
+    alphabet (which the symbol arithmetic aliases), a smaller alphabet,
+    batches of uneven texts and one-chunk units."""
+    rng = np.random.default_rng(17)
+    if case == "three_letters":
+        pats = [bytes(rng.choice(list(b"ACG"), int(n)).astype(np.uint8)) for n in rng.integers(16, 40, 3000)]
+        text = rng.choice(list(b"ACGT"), 300_000, p=[0.33, 0.33, 0.33, 0.01]).astype(np.uint8)
+    else:
+        wl = workloads.c3_dna(n_text=(1 << 19) + 3, k=5000, n_plants=800)
+        pats, text = wl.patterns.as_list(), wl.text.copy()
+    if case == "dirty_text":
+        # 'N', lower case and other bytes, some inside planted copies
+        bad = rng.integers(0, text.size, 4000)
+        text[bad] = rng.choice(list(b"Nacgt\x00\xff@"), bad.size).astype(np.uint8)
+    # every 16-symbol prefix of some pattern appears too (filter hits that
+    # fail later), and exact copies
+    for _ in range(300):
+        p = pats[int(rng.integers(0, len(pats)))]
+        at = int(rng.integers(0, text.size - len(p)))
+        cut = int(rng.integers(16, len(p) + 1))
+        text[at:at + cut] = np.frombuffer(p[:cut], dtype=np.uint8)
+    trie = pf.Trie(pats)
+    trie.set_tuning(kernel=2, chunks_per_unit=1 if case == "short_units" else 16)
+    say(f"four-symbol {case}: n={text.size} k={len(pats)} K={trie.stats()['index_depth']}")
+    if case == "batch":
+        lens = rng.integers(0, 5000, 200)
+        offs = np.zeros(lens.size + 1, dtype=np.uint64)
+        offs[1:] = np.cumsum(lens)
+        t = text[: int(offs[-1])]
+        want = oracle.bucketed(t, pats, offsets=offs, threads=8)
+        got, n = gpu_scan_batch(trie, t, offs, pad_front=5)
+        assert n == want.n
+        assert_same(got, want, with_text=True)
+        return
+    got, counts = gpu_scan(trie, text)
+    want = oracle.bucketed(text, pats, threads=8)
+    assert_same(got, want)
+    assert np.array_equal(counts, oracle.counts(text.size, want))
+
+
 @pytest.mark.parametrize("kernel", [1, 2])
 def test_c2_scaled_full_pattern_set(kernel):
     wl = workloads.c2_signature_set(n_text=16 << 20, k=10_000)
