@@ -30,7 +30,7 @@ struct ImageView {
     const uint32_t *krec;     // per depth-K node: up to three child labels, count in the top byte
     const uint32_t *pfx4;     // prefix-4 filter bitmap (2^pfx4_log2 bits)
     const uint32_t *q16;      // four-symbol filter: bitmap words (2^q16_lw)
-    const uint4 *qfp;         // four-symbol filter: buckets of 16 x 16-bit fingerprints (2 x uint4)
+    const uint4 *qfp;         // four-symbol filter: buckets of 8 x 16-bit fingerprints
     uint32_t K, b, identity, lvl_words;
     uint32_t lvl_start, max_len, n_nodes, fold_syms;
     uint32_t pfx4_log2, pfx4_mul;     // prefix-4 filter: 2^pfx4_log2 bits, hash multiplier

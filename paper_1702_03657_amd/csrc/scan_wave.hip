@@ -647,7 +647,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
 #pragma unroll
                 for (int j = 0; j < 16; j++) {
                     const uint32_t key = j == 0 ? P0 : __builtin_amdgcn_alignbit(P1, P0, 2 * j);
-                    hh[j] = (key & 0xffffffu) * im.q16_mul + (key >> 8);
+                    hh[j] = __umul24(key, im.q16_mul) + (key >> 8);  // 24 x 24-bit multiply
                     ent[j] = lds_tab32()[hh[j] >> qsh];
                 }
                 uint32_t hm = 0;
@@ -709,12 +709,11 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                                 const uint32_t fp = (h2 & 0xffffu) | 1u;
                                 const uint32_t nb = 1u << im.qfp_lb;
                                 const uint32_t bk = h2 >> (32u - im.qfp_lb);
-                                const uint4 *b0 = im.qfp + 2 * bk, *b1 = im.qfp + 2 * ((bk + 1) & (nb - 1));
-                                const uint4 f[4] = {b0[0], b0[1], b1[0], b1[1]};
+                                const uint4 f[2] = {im.qfp[bk], im.qfp[(bk + 1) & (nb - 1)]};
                                 const uint32_t fp2 = fp * 0x00010001u;
                                 uint32_t hit = 0;
 #pragma unroll
-                                for (int k = 0; k < 4; k++) {
+                                for (int k = 0; k < 2; k++) {
                                     const uint32_t wv[4] = {f[k].x, f[k].y, f[k].z, f[k].w};
 #pragma unroll
                                     for (int q = 0; q < 4; q++) {

@@ -94,7 +94,7 @@ struct DeviceImageHost {
     // lowest; h = (key mod 2^24) * kQ16Mul + (key >> 8) mod 2^32.
     //  - q16: 2^q16_lw words; word h >> (32 - q16_lw) has bits h & 31 and
     //    (h >> 5) & 31 set for every distinct 16-symbol prefix;
-    //  - qfp: 2^qfp_lb buckets of 16 nonzero 16-bit fingerprints
+    //  - qfp: 2^qfp_lb buckets of 8 nonzero 16-bit fingerprints
     //    (key * kPfx4Mul) & 0xffff | 1 in bucket (key * kPfx4Mul) >> (32 -
     //    qfp_lb) or the next one (qfp_lb = 0: no fingerprints);
     //  - qalph: byte i = c_i (an unused symbol holds a byte of another one).

@@ -317,11 +317,11 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
             while (lg < 20 && (1ull << lg) < 10ull * n16 + n16 / 2) lg++;
             I.q16_lw = lg - 5;
             I.q16.assign(1u << I.q16_lw, 0);
-            uint32_t lb = 0;  // buckets: about four keys each
-            while ((1ull << lb) * 4 < n16) lb++;
+            uint32_t lb = 0;  // buckets of 8: about two keys each
+            while ((1ull << lb) * 2 < n16) lb++;
             I.qfp_lb = std::max(lb, 1u);
             const uint32_t nb = 1u << I.qfp_lb;
-            I.qfp.assign((size_t)nb * 16, 0);
+            I.qfp.assign((size_t)nb * 8, 0);
             bool fp_ok = true;
             for (uint32_t v = v0; v < v1; v++) {
                 const uint8_t *p = T.pat_data.data() + T.pat_off[T.rep[v]];
@@ -335,8 +335,8 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
                 const uint16_t fp = (uint16_t)((h2 & 0xffffu) | 1u);
                 bool put = false;
                 for (uint32_t q = 0; q < 2 && !put; q++) {
-                    uint16_t *bk = I.qfp.data() + (size_t)((b + q) & (nb - 1)) * 16;
-                    for (uint32_t s = 0; s < 16 && !put; s++)
+                    uint16_t *bk = I.qfp.data() + (size_t)((b + q) & (nb - 1)) * 8;
+                    for (uint32_t s = 0; s < 8 && !put; s++)
                         if (bk[s] == 0 || bk[s] == fp) {
                             bk[s] = fp;
                             put = true;
