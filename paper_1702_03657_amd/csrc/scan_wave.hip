@@ -1,31 +1,35 @@
-// Wave-independent scan kernel for gfx950.
+// Wave-independent scan kernels for gfx950.
 //
 // The failure-less walk of the paper (one start position per lane slot, walk
 // the trie from the root until the first byte without an edge, report every
 // pattern that ends on the way), organised so that no step waits for the
-// whole workgroup and so that the memory latency of walks is paid once per
-// unit of several KiB rather than once per position:
+// whole workgroup, so that positions no pattern can start at cost one LDS
+// lookup, and so that walks do not hold up the filtering:
 //
-//   * a workgroup only cooperates to load the shared tables into LDS once;
-//   * each wave owns units of G consecutive 1 KiB chunks (round robin over the
-//     grid) and loads the next chunk's 16-byte vectors while it filters the
-//     current one;
-//   * stage 1 rejects most start positions with one LDS lookup: the table is
-//     indexed by the first K symbols (the code of a depth-K trie node) and
+//   * a workgroup cooperates only to load the shared tables into LDS;
+//   * each wave owns units of G consecutive 1 KiB chunks (round robin over
+//     the grid) and loads chunks two ahead of the one it filters;
+//   * stage 1 tests all 16 start positions of a lane against a table at LDS
+//     address 0 and builds a hit mask: for byte alphabets the table is
+//     indexed by the first two bytes (the code of a depth-2 trie node) and
 //     holds that node's child bitmap folded to 8 or 16 bits, tested with the
-//     next symbol (the bitmapped node of Design and Implementation, with the
-//     bitmap narrowed as that section allows);
-//   * stage 2 (optional) checks the next byte exactly against the child
-//     labels of the depth-K node, kept in LDS when they fit;
+//     third byte (the bitmapped node of Design and Implementation, narrowed
+//     as that section allows); for alphabets of at most four bytes (mode 3)
+//     it is a hashed bitmap over 16-symbol prefixes; other images use a
+//     rolling code over K symbols (mode 0);
+//   * stage 2 takes the compacted hits: the text end, the prefix-4 filter or
+//     the depth-K node's child labels (byte alphabets), the alphabet bytes
+//     and a fingerprint (mode 3), and the depth-K node from the level index;
 //   * survivors become walk candidates (start, depth-K node, distance to the
-//     end of their text); a unit's candidates are walked together, reading
-//     the text and the CRS records from global memory (L2 resident), with
-//     single-child runs compared in bulk;
-//   * matches of a unit are sorted by position in the wave's LDS area and
-//     staged in the unit's inline slots (or with one atomic when there are
-//     more); the shared finisher orders units.
-// A unit whose matches overflow the per-wave list is redone from the root,
-// 64 positions at a time, in position order.
+//     end of their text).  The split kernel writes them, with the 8 text
+//     bytes after the index, for walk_units; the fused kernel walks a unit's
+//     candidates itself, reading the text and the CRS records from global
+//     memory, with single-child runs compared in bulk;
+//   * matches of a unit are sorted by position in LDS and staged in the
+//     unit's inline slots (or with one atomic when there are more); the
+//     shared finisher orders units.
+// A unit whose candidates or matches overflow their lists is redone from the
+// root, 64 positions at a time, in position order.
 #include <hip/hip_runtime.h>
 
 #include "device_common.hpp"

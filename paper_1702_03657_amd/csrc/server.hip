@@ -2,13 +2,14 @@
 //
 // Requests are admitted in arrival order into a byte ring in caller-provided
 // device memory while the budget (text bytes in flight) allows.  Their
-// host-to-device copies run on a copy stream; every request whose copy has
-// landed and that is contiguous in the ring joins the next batched scan on
-// the compute stream.  Two batch slots alternate, so a batch is launched
-// while the previous one still runs and new requests keep arriving and
-// copying in the meantime.  When a batch completes its matches are copied
-// back, split per request by text id, and the ring space and budget of its
-// requests are released.
+// host-to-device copies run on a copy stream; the admitted requests that are
+// contiguous in the ring and not yet scanned form the next batched scan on
+// the compute stream, which waits on the device for their copies.  Two batch
+// slots alternate, so a batch is launched while the previous one still runs
+// and new requests keep arriving and copying in the meantime.  When a batch
+// completes its matches are copied back on the server's own stream, split
+// per request by text id, and the ring space and budget of its requests are
+// released.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -28,7 +29,7 @@ namespace {
 
 using clk = std::chrono::steady_clock;
 
-enum class St { Queued, Copying, Ready, Scanning, Done };
+enum class St { Queued, Copying, Scanning, Done };
 
 struct Req {
     uint64_t id = 0;
@@ -152,7 +153,7 @@ struct pfac_server {
                 if (b.empty()) continue;
                 break;
             }
-            if (r->st != St::Ready && r->st != St::Copying) break;
+            if (r->st != St::Copying) break;
             if (!b.empty()) {
                 const Req *p = b.back();
                 if (p->ring_off + p->n != r->ring_off) break;  // ring wrapped
