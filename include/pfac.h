@@ -92,7 +92,9 @@ typedef struct {
     uint32_t kernel;           /* 0 = tile kernel (workgroup tiles), 1 = fused wave kernel
                                   (filter, walks and emission in one kernel), 2 = split wave
                                   kernels (filter kernel writes walk candidates, a walk kernel
-                                  runs them; the default for byte alphabets) */
+                                  runs them; the default for byte alphabets with K = 2 and for
+                                  alphabets of at most four bytes, where it uses the 16-symbol
+                                  filter when every pattern has 16 bytes or more) */
     uint32_t bytes_per_lane;   /* tile kernel: start positions per lane per tile: 4, 8 or 16 */
     uint32_t index_bits;       /* level-index width in bits (1..18); depth K = bits / symbol_bits */
     uint32_t fold_bits;        /* wave kernel prefix filter: 0 (level bitmap), 8 or 16 bits per node */
@@ -100,8 +102,11 @@ typedef struct {
     uint32_t waves_per_wg;     /* wave kernel: 4, 8, 12 or 16 waves per workgroup (fewer when
                                   the LDS tables leave no room) */
     uint32_t chunks_per_unit;  /* wave kernel: 1 KiB chunks per output unit, 1..64 */
-    uint32_t child_check;      /* wave kernel: 1 = check the byte after the level index against
-                                  the depth-K node's child labels in LDS when they fit */
+    uint32_t child_check;      /* wave kernel second stage: 0 = none, 1 = check the byte after
+                                  the level index against the depth-K node's child labels in
+                                  LDS when they fit, 2 = the prefix-4 filter (two hashed bits
+                                  per distinct 4-byte pattern prefix; byte alphabets with every
+                                  pattern of 4 bytes or more, the default there), else as 1 */
 } pfac_tuning;
 
 /* ----------------------------------------------------------------- errors */
