@@ -83,6 +83,11 @@ typedef struct {
     uint32_t scan_kernel;      /* kernels the current tuning launches: 0 = tile, 1 = fused
                                   wave kernel, 2 = split filter + walk kernels */
     uint32_t scan_waves;       /* waves per workgroup it launches with (after LDS fitting) */
+    uint32_t stage1;           /* wave kernels' first filter: 0 = rolling code over K symbols (or
+                                  the tile kernel), 1 / 2 = two-byte table with the third byte
+                                  folded to 8 / 16 bits, 3 = 16-symbol filter */
+    uint32_t stage2;           /* second filter: 0 = none, 1 = child labels of depth-K nodes,
+                                  2 = prefix-4 filter, 3 = alphabet bytes + 16-bit fingerprint */
     double build_seconds;      /* host build time (not part of scan timing) */
     double upload_seconds;     /* host -> device copy time of the image */
 } pfac_stats;

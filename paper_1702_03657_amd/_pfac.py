@@ -47,6 +47,7 @@ class pfac_stats(ctypes.Structure):
         ("alphabet_size", ctypes.c_uint32), ("symbol_bits", ctypes.c_uint32),
         ("index_depth", ctypes.c_uint32), ("lds_bytes", ctypes.c_uint32),
         ("scan_kernel", ctypes.c_uint32), ("scan_waves", ctypes.c_uint32),
+        ("stage1", ctypes.c_uint32), ("stage2", ctypes.c_uint32),
         ("build_seconds", ctypes.c_double), ("upload_seconds", ctypes.c_double),
     ]
 

@@ -58,7 +58,7 @@ struct pfac_trie {
     CrsTrie crs;
     DeviceImageHost img;
     pfac_tuning tuning{1, 16, 16, 8, 0, 16, 16, 1};
-    uint32_t lds_limit = 64 * 1024;  // dynamic LDS a workgroup may use
+    uint32_t lds_limit = 160 * 1024;  // dynamic LDS a workgroup may use (gfx950; queried on the device)
     bool host_only = false;
     int device = -1;
     int n_cu = 0;
@@ -333,6 +333,20 @@ extern "C" int pfac_trie_stats(const pfac_trie *t, pfac_stats *o) {
     uint32_t waves = t->tuning.waves_per_wg;
     o->scan_kernel = use_wave_kernel(t, &waves) ? t->tuning.kernel : 0u;
     o->scan_waves = o->scan_kernel ? waves : kWG / 64;
+    // the wave kernels' filter stages for this tuning
+    o->stage1 = 0;
+    o->stage2 = 0;
+    if (o->scan_kernel) {
+        const ScanArgs a = layout_for(t);
+        if (a.q16_words) {
+            o->stage1 = 3;
+            o->stage2 = 3;
+        } else {
+            if (t->img.identity && t->img.K == 2 && t->img.fold_syms == 1)
+                o->stage1 = a.fold == 8 ? 1u : a.fold == 16 ? 2u : 0u;
+            o->stage2 = a.pfx4_words ? 2u : a.krec_words ? 1u : 0u;
+        }
+    }
     o->build_seconds = t->build_s;
     o->upload_seconds = t->upload_s;
     return PFAC_OK;

@@ -125,3 +125,30 @@ def test_pattern_pointer_build(lib):
     assert lib.pfac_trie_stats(h, ctypes.byref(st)) == 0
     assert st.nodes == len(oracle.canonical_trie(pats)["row_ptr"]) - 1
     lib.pfac_trie_free(h)
+
+
+def test_default_launch_and_filters(lib):
+    """The build picks the split kernels and the matching filter stages; the
+    tuning can switch them."""
+    t = pf.Trie(workloads.c2_signature_set(n_text=64, k=2000).patterns, host_only=True)
+    s = t.stats()
+    assert (s["scan_kernel"], s["stage1"], s["stage2"]) == (2, 1, 2)  # two-byte table, prefix-4
+    t.set_tuning(child_check=1)
+    assert t.stats()["stage2"] == 1                                 # child labels
+    t.set_tuning(fold_bits=0, child_check=0)
+    assert (t.stats()["stage1"], t.stats()["stage2"]) == (0, 0)
+    t.set_tuning(kernel=0)
+    assert t.stats()["scan_kernel"] == 0
+    # DNA: 16-symbol filter with its second stage
+    t = pf.Trie(workloads.c3_dna(n_text=64, k=3000, n_plants=0).patterns, host_only=True)
+    s = t.stats()
+    assert (s["scan_kernel"], s["stage1"], s["stage2"]) == (2, 3, 3)
+    t.set_tuning(kernel=1)
+    assert (t.stats()["scan_kernel"], t.stats()["stage1"]) == (1, 0)  # fused: rolling code
+    # patterns shorter than 16 symbols: no 16-symbol filter
+    short = [bytes(p) for p in np.random.default_rng(1).choice(list(b"ACGT"), (500, 12)).astype(np.uint8)]
+    s = pf.Trie(short, host_only=True).stats()
+    assert s["stage1"] != 3
+    # patterns shorter than 4 bytes: no prefix-4 filter
+    s = pf.Trie([b"abc", b"abcdef", b"xyz"], host_only=True).stats()
+    assert s["stage2"] != 2

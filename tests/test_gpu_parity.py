@@ -129,6 +129,23 @@ def test_four_symbol_filter(case):
     assert np.array_equal(counts, oracle.counts(text.size, want))
 
 
+def test_four_symbol_filter_graph_replays():
+    rng = np.random.default_rng(23)
+    wl = workloads.c3_dna(n_text=(1 << 20), k=8000, n_plants=1500)
+    lens = rng.integers(0, 40_000, 60)
+    offs = np.zeros(lens.size + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum(lens)
+    text = wl.text[: int(offs[-1])]
+    trie = pf.Trie(wl.patterns)
+    assert trie.stats()["stage1"] == 3
+    want = oracle.bucketed(text, wl.patterns, offsets=offs, threads=8)
+    say(f"four-symbol graph: {lens.size} texts, {want.n} matches")
+    results, n = gpu_scan_batch(trie, text, offs, graph_replays=3)
+    assert n == want.n
+    for r in results:
+        assert_same(r, want, with_text=True)
+
+
 @pytest.mark.parametrize("kernel", [1, 2])
 def test_c2_scaled_full_pattern_set(kernel):
     wl = workloads.c2_signature_set(n_text=16 << 20, k=10_000)
