@@ -814,7 +814,7 @@ extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *tex
         for (uint32_t fold : {8u, 16u, 0u})
             for (uint32_t kernel : {1u, 2u})
                 for (uint32_t waves : {8u, 16u})
-                    for (uint32_t g : {4u, 16u, 64u})
+                    for (uint32_t g : {4u, 16u, 32u, 64u})
                         for (uint32_t cc : {0u, 1u, 2u})
                             cands.push_back({kernel, 16, bits, fold, 0, waves, g, cc});
         for (uint32_t bpl : {8u, 16u}) cands.push_back({0, bpl, bits, 8, 0, 16, 16, 1});

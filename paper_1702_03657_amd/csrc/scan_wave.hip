@@ -403,7 +403,15 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     struct Vec2 {
         uint4 v, h;
     };
+    // A unit of a single text that starts inside it and ends at least
+    // 0x20000 bytes before its end: no chunk of it needs a boundary test and
+    // every limit is the 16-bit maximum.
+    auto interior = [&](uint64_t uu) -> bool {
+        const uint64_t lo = uu * G * kChunk;
+        return a.offsets == nullptr && lo >= lo_valid && lo + (uint64_t)G * kChunk + 0x20000 <= hi_valid;
+    };
     uint32_t pn = pu < n_units ? unit_chunks(pu) : 0u;  // chunks of unit pu
+    bool p_in = pu < n_units && interior(pu);
     auto prefetch = [&]() -> Vec2 {
         Vec2 r;
         r.v = make_uint4(0, 0, 0, 0);
@@ -411,7 +419,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         if (pu < n_units) {
             const uint64_t lo = (pu * G + pg) * kChunk;
             // every 16-byte block of an inner chunk holds text: no lane checks
-            if (lo + 16 > lo_valid && lo + kChunk - 16 < hi_valid)
+            if (p_in || (lo + 16 > lo_valid && lo + kChunk - 16 < hi_valid))
                 r.v = *(const uint4 *)(a.base + lo + 16 * lane);
             else
                 r.v = load_vec(lo + 16ull * lane);
@@ -420,6 +428,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                 pg = 0;
                 pu += stride;
                 pn = pu < n_units ? unit_chunks(pu) : 0u;
+                p_in = pu < n_units && interior(pu);
             }
         }
         return r;
@@ -429,6 +438,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     for (; u < n_units; u += stride) {
         const uint64_t unit_lo = u * G * kChunk;
         const uint32_t nch = unit_chunks(u);
+        const bool u_in = interior(u);
         uint32_t cn = 0, mn = 0;   // candidates, matches (wave-uniform)
         uint4 *const wcg = SPLIT ? a.cand + u * a.cand_cap : nullptr;
         // queue a candidate (ballot mask mk over the wave); the split kernels
@@ -488,9 +498,9 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                 *(uint4 *)(wtext + kChunk) = make_uint4(more ? nxt.x : cur_h.x, more ? nxt.y : cur_h.y,
                                                         more ? nxt.z : cur_h.z, more ? nxt.w : cur_h.w);
             }
-            bool dirty;
-            unsigned long long next_bnd;
-            chunk_bounds(a, chunk_lo / kChunk, chunk_lo, wbnd, dirty, next_bnd);
+            bool dirty = false;
+            unsigned long long next_bnd = hi_valid;
+            if (!u_in) chunk_bounds(a, chunk_lo / kChunk, chunk_lo, wbnd, dirty, next_bnd);
 
             uint32_t w[8];
             {
@@ -569,9 +579,12 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                 const int rounds = tot > kQ16 ? 2 : 1;
                 // valid positions and the distance to the next text boundary,
                 // relative to the chunk (wave-uniform)
-                const uint32_t vlo = lo_valid > chunk_lo ? (uint32_t)min(lo_valid - chunk_lo, (uint64_t)kWin) : 0u;
-                const uint32_t vhi = hi_valid > chunk_lo ? (uint32_t)min(hi_valid - chunk_lo, (uint64_t)kWin) : 0u;
-                const uint32_t nb_rel = (uint32_t)min(next_bnd - chunk_lo, (unsigned long long)0x20000);
+                uint32_t vlo = 0, vhi = kWin, nb_rel = 0x20000;
+                if (!u_in) {
+                    vlo = lo_valid > chunk_lo ? (uint32_t)min(lo_valid - chunk_lo, (uint64_t)kWin) : 0u;
+                    vhi = hi_valid > chunk_lo ? (uint32_t)min(hi_valid - chunk_lo, (uint64_t)kWin) : 0u;
+                    nb_rel = (uint32_t)min(next_bnd - chunk_lo, (unsigned long long)0x20000);
+                }
                 for (int half = 0; half < rounds; half++) {
                     uint32_t mset = hm, o = off_all, qn = tot, jb = 0;
                     if (rounds == 2) {
@@ -662,9 +675,12 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                 uint32_t tot;
                 const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
                 const int rounds = tot > kQ16 ? 2 : 1;
-                const uint32_t vlo = lo_valid > chunk_lo ? (uint32_t)min(lo_valid - chunk_lo, (uint64_t)kWin) : 0u;
-                const uint32_t vhi = hi_valid > chunk_lo ? (uint32_t)min(hi_valid - chunk_lo, (uint64_t)kWin) : 0u;
-                const uint32_t nb_rel = (uint32_t)min(next_bnd - chunk_lo, (unsigned long long)0x20000);
+                uint32_t vlo = 0, vhi = kWin, nb_rel = 0x20000;
+                if (!u_in) {
+                    vlo = lo_valid > chunk_lo ? (uint32_t)min(lo_valid - chunk_lo, (uint64_t)kWin) : 0u;
+                    vhi = hi_valid > chunk_lo ? (uint32_t)min(hi_valid - chunk_lo, (uint64_t)kWin) : 0u;
+                    nb_rel = (uint32_t)min(next_bnd - chunk_lo, (unsigned long long)0x20000);
+                }
                 for (int half = 0; half < rounds; half++) {
                     uint32_t mset = hm, o = off_all, qn = tot, jb = 0;
                     if (rounds == 2) {
