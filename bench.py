@@ -18,6 +18,12 @@ Workloads (seeded synthetic data, see synth/workloads.py): ``c2`` (default,
 vs plain per-text comparison (c4: 65,600 texts in one graph-captured launch
 against one launch per text) and the serving loop's p50/p99 latency against
 one request at a time (c5); ``--no-extras`` / ``--no-serving`` leave them out.
+
+``--placement c1,c2,...`` prints instead one line with the trie-placement
+ablation: the tile kernel with 0, 1, 2, ... trie levels resolved in LDS (the
+rest walked through the node records in global memory), the default launch
+and the autotuned one, on each workload, every point checked against the
+oracle.
 """
 
 from __future__ import annotations
@@ -331,6 +337,124 @@ def extras_serving(pf, torch, n_requests, rates, budget_bytes):
     return res
 
 
+def lds_depth_tuning(stats, depth):
+    """Tile-kernel tuning whose level index resolves `depth` trie levels in
+    LDS (0: nothing of the trie in LDS, every start position walks from the
+    root through the node records in global memory), or None if the pattern
+    set does not allow that depth."""
+    alpha = max(1, int(stats["alphabet_size"]))
+    b = max(1, (alpha - 1).bit_length())
+    b = 8 if b >= 8 else b
+    if depth == 0:
+        if b < 2:
+            return None  # one bit already resolves a level of a binary alphabet
+        bits = 1
+    else:
+        bits = depth * b
+    if bits > 18 or depth > int(stats["min_len"]) - 1:
+        return None
+    return dict(kernel=0, bytes_per_lane=16, index_bits=bits, fold_bits=0, wg_per_cu=0,
+                child_check=0)
+
+
+PLACEMENT_WORKLOADS = {
+    "c1": lambda w: w.c1_plain_small(),
+    "c2": lambda w: w.c2_signature_set(),
+    "c3": lambda w: w.c3_dna(),
+    "c4": lambda w: w.c4_batched(),
+    # the serving pattern set over its first 64 requests, as one batch
+    "c5": lambda w: w.c5_requests(64),
+}
+
+
+def placement_ablation(pf, torch, names, steps, warmup, threads):
+    """Trie placement: the tile kernel with 0, 1, 2, ... trie levels resolved
+    from the level index in LDS (the rest walked through the node records in
+    global memory), the library's default launch and the autotuned one, on
+    each workload; every point's match list is checked against the oracle."""
+    import numpy as np
+
+    import oracle
+    from synth import workloads
+    rows = []
+    for name in names:
+        t0 = time.time()
+        wl = PLACEMENT_WORKLOADS[name](workloads)
+        offs_host = wl.offsets.astype(np.uint64)
+        n_texts = len(offs_host) - 1
+        n = int(offs_host[-1])
+        log(f"placement {name}: generated in {time.time() - t0:.1f}s, {n_texts} texts, {n} bytes")
+        want = oracle.bucketed(wl.text, wl.patterns, offsets=wl.offsets if n_texts > 1 else None,
+                               threads=threads)
+        trie = pf.Trie(wl.patterns)
+        st = trie.stats()
+        default = trie.tuning()
+        ws = pf.Workspace()
+        text = torch.from_numpy(wl.text).cuda()
+        offs = torch.from_numpy(offs_host.view(np.int64)).cuda()
+        cap = max(1024, want.n)
+        out = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+        cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+        ws.reserve(n, n_texts, cap)
+        stream = torch.cuda.current_stream()
+
+        def scan():
+            if n_texts > 1:
+                pf.pfac_scan_batch(trie, ws, text, offs, n_texts, n, out, cap, cnt, stream)
+            else:
+                pf.pfac_scan(trie, ws, text, n, out, cap, cnt, None, stream)
+
+        points = [(f"tile kernel, LDS depth {d}", lds_depth_tuning(st, d)) for d in range(0, 10)]
+        points = [(lab, t) for lab, t in points if t is not None]
+        points.append(("library default", default))
+        trie.set_tuning(**default)
+        points.append(("autotuned", pf.pfac_autotune(trie, ws, text, n)))
+        res = {"workload": name, "texts": n_texts, "text_bytes": n, "patterns": len(wl.patterns),
+               "alphabet": int(st["alphabet_size"]), "matches": int(want.n), "points": []}
+        for label, tn in points:
+            trie.set_tuning(**tn)
+            s2 = trie.stats()
+            for _ in range(warmup):
+                scan()
+            kev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(steps)]
+            for a, b in kev:
+                a.record(stream)
+                b.record(stream)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record(stream)
+            for i in range(steps):
+                ws.set_timing(kev[i][0], kev[i][1])
+                scan()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ws.set_timing(None, None)
+            ms = e0.elapsed_time(e1) / steps
+            kms = statistics.mean(a.elapsed_time(b) for a, b in kev)
+            got_n = int(cnt.item())
+            got = pf.matches_to_numpy(out, min(got_n, cap))
+            same = bool(got_n == want.n and np.array_equal(got["pos"], want["pos"])
+                        and np.array_equal(got["pattern_id"], want["id"])
+                        and (n_texts == 1 or np.array_equal(got["text_id"], want["text"])))
+            gbit = n * 8 / ms / 1e6
+            res["points"].append({
+                "placement": label, "index_depth": int(s2["index_depth"]),
+                "lds_bytes": int(s2["lds_bytes"]), "scan_kernel": int(s2["scan_kernel"]),
+                "tuning": {k: int(v) for k, v in tn.items()},
+                "ms_per_scan": round(ms, 5), "gbit_s": round(gbit, 2),
+                "hbm_frac": round(n / ms / 1e6 / HBM_PEAK_GBS, 4),
+                "main_kernel_ms": round(kms, 5), "parity_with_oracle": same})
+            log(f"  {label:28s} K={int(s2['index_depth'])} {gbit:10.2f} Gbit/s "
+                f"({ms:.4f} ms/scan, kernel {kms:.4f} ms) parity={same}")
+        rows.append(res)
+        del text, offs, out
+        trie.close()
+        ws.close()
+        torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,6 +476,10 @@ def main():
     ap.add_argument("--serving-budget", type=int, default=1 << 30, help="HBM bytes for request texts")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of the text size (counter calibration)")
+    ap.add_argument("--placement", default=None, metavar="c1,c2,...",
+                    help="instead of the headline line: the trie-placement ablation (LDS depth "
+                         "0, 1, 2, ... of the tile kernel, default and autotuned launches) on "
+                         "these workloads, one JSON line")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -369,6 +497,16 @@ def main():
 
     torch.cuda.set_device(0)
     dev_name = torch.cuda.get_device_name(0)
+    if args.placement:
+        names = args.placement.split(",")
+        bad = [x for x in names if x not in PLACEMENT_WORKLOADS]
+        if bad:
+            raise SystemExit(f"unknown workloads {bad}; choose from {sorted(PLACEMENT_WORKLOADS)}")
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        rows = placement_ablation(pf, torch, names, args.steps, args.warmup, threads)
+        print(json.dumps({"placement_ablation": rows, "device": dev_name, "steps": args.steps,
+                          "warmup": args.warmup, "hbm_peak_gb_s": HBM_PEAK_GBS}), flush=True)
+        return
     desc, make = WORKLOADS[args.workload]
     t0 = time.time()
     wl = make(workloads)

@@ -152,3 +152,24 @@ def test_default_launch_and_filters(lib):
     # patterns shorter than 4 bytes: no prefix-4 filter
     s = pf.Trie([b"abc", b"abcdef", b"xyz"], host_only=True).stats()
     assert s["stage2"] != 2
+
+
+def test_placement_depths_reach_the_requested_level_index():
+    """The placement ablation's tunings resolve exactly the requested number
+    of trie levels in LDS (0: none), for a byte alphabet and for DNA."""
+    from bench import lds_depth_tuning
+    from synth import workloads
+    for wl, depths in ((workloads.c1_plain_small(n_text=1024), [0, 1, 2]),
+                       (workloads.c3_dna(n_text=4096, k=3000, n_plants=10), list(range(10)))):
+        t = pf.Trie(wl.patterns, host_only=True)
+        st = t.stats()
+        got = []
+        for d in range(12):
+            tn = lds_depth_tuning(st, d)
+            if tn is None:
+                continue
+            t.set_tuning(**tn)
+            assert t.stats()["index_depth"] == d
+            got.append(d)
+        assert got == depths
+        t.close()
