@@ -20,10 +20,11 @@ against one launch per text) and the serving loop's p50/p99 latency against
 one request at a time (c5); ``--no-extras`` / ``--no-serving`` leave them out.
 
 ``--placement c1,c2,...`` prints instead one line with the trie-placement
-ablation: the tile kernel with 0, 1, 2, ... trie levels resolved in LDS (the
-rest walked through the node records in global memory), the default launch
-and the autotuned one, on each workload, every point checked against the
-oracle.
+ablation: the tile kernel with 0, 1, 2, ... trie levels resolved in LDS by
+the level index or by bitmapped nodes (the rest walked through the node
+records in global memory), the default launch and the autotuned one, on each
+workload, every point checked against the oracle, with the trie's footprint
+in each encoding.
 """
 
 from __future__ import annotations
@@ -354,7 +355,7 @@ def lds_depth_tuning(stats, depth):
     if bits > 18 or depth > int(stats["min_len"]) - 1:
         return None
     return dict(kernel=0, bytes_per_lane=16, index_bits=bits, fold_bits=0, wg_per_cu=0,
-                child_check=0)
+                child_check=0, top_nodes=0)
 
 
 PLACEMENT_WORKLOADS = {
@@ -405,14 +406,26 @@ def placement_ablation(pf, torch, names, steps, warmup, threads):
                 pf.pfac_scan(trie, ws, text, n, out, cap, cnt, None, stream)
 
         points = [(f"tile kernel, LDS depth {d}", lds_depth_tuning(st, d)) for d in range(0, 10)]
+        # the same depths through the bitmapped nodes (where they fit in LDS)
+        points += [(f"tile kernel, bitmapped nodes depth {d}", t and dict(t, top_nodes=1))
+                   for d, t in ((d, lds_depth_tuning(st, d)) for d in range(1, 10))]
         points = [(lab, t) for lab, t in points if t is not None]
         points.append(("library default", default))
         trie.set_tuning(**default)
         points.append(("autotuned", pf.pfac_autotune(trie, ws, text, n)))
         res = {"workload": name, "texts": n_texts, "text_bytes": n, "patterns": len(wl.patterns),
-               "alphabet": int(st["alphabet_size"]), "matches": int(want.n), "points": []}
+               "alphabet": int(st["alphabet_size"]), "matches": int(want.n),
+               "footprint_bytes": {"crs": int(st["bytes_crs"]), "dense256": int(st["bytes_dense256"]),
+                                   "bitmap36": int(st["bytes_bitmap36"]),
+                                   "bitmap_narrow": int(st["bytes_bitmap_narrow"]),
+                                   "device_image": int(st["bytes_device"])},
+               "points": []}
         for label, tn in points:
-            trie.set_tuning(**tn)
+            try:
+                trie.set_tuning(**tn)
+            except pf.PfacError:
+                log(f"  {label:28s} does not fit in LDS")
+                continue
             s2 = trie.stats()
             for _ in range(warmup):
                 scan()
@@ -441,6 +454,8 @@ def placement_ablation(pf, torch, names, steps, warmup, threads):
             res["points"].append({
                 "placement": label, "index_depth": int(s2["index_depth"]),
                 "lds_bytes": int(s2["lds_bytes"]), "scan_kernel": int(s2["scan_kernel"]),
+                "top_lds_bytes": int(s2["bytes_top_nodes"] if tn.get("top_nodes")
+                                     else s2["bytes_level_index"]),
                 "tuning": {k: int(v) for k, v in tn.items()},
                 "ms_per_scan": round(ms, 5), "gbit_s": round(gbit, 2),
                 "hbm_frac": round(n / ms / 1e6 / HBM_PEAK_GBS, 4),
@@ -463,7 +478,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--retune", action="store_true", help="ignore the cached autotune choice")
     ap.add_argument("--tuning", default=None,
-                    help="kernel,bytes_per_lane,index_bits,fold_bits,wg_per_cu,waves_per_wg,chunks_per_unit,child_check")
+                    help="kernel,bytes_per_lane,index_bits,fold_bits,wg_per_cu,waves_per_wg,"
+                         "chunks_per_unit,child_check[,top_nodes]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true",
@@ -530,7 +546,7 @@ def main():
 
     if args.tuning:
         names = ["kernel", "bytes_per_lane", "index_bits", "fold_bits", "wg_per_cu", "waves_per_wg",
-                 "chunks_per_unit", "child_check"]
+                 "chunks_per_unit", "child_check", "top_nodes"]
         trie.set_tuning(**dict(zip(names, (int(x) for x in args.tuning.split(",")))))
         tuning, tuned_now = trie.tuning(), False
     else:

@@ -90,6 +90,14 @@ typedef struct {
                                   2 = prefix-4 filter, 3 = alphabet bytes + 16-bit fingerprint */
     double build_seconds;      /* host build time (not part of scan timing) */
     double upload_seconds;     /* host -> device copy time of the image */
+    uint64_t bytes_bitmap_narrow; /* every node as a bitmapped node (Design and Implementation,
+                                     bitmapped-node figure) with the bitmap narrowed to the
+                                     2^b symbols used, b = ceil(log2 alphabet), in whole bytes,
+                                     + a 4-byte first-child offset (= bytes_bitmap36 for b = 8) */
+    uint64_t bytes_level_index;   /* LDS bytes of the level index at depth K (bitmap + ranks) */
+    uint64_t bytes_top_nodes;     /* LDS bytes of the same K levels as bitmapped nodes (nodes of
+                                     depths 0 .. K-1, bitmap over the index's 2^symbol_bits
+                                     symbols padded to 32-bit words, + first child) */
 } pfac_stats;
 
 /* Launch parameters chosen by hand or by pfac_autotune. */
@@ -112,6 +120,12 @@ typedef struct {
                                   LDS when they fit, 2 = the prefix-4 filter (two hashed bits
                                   per distinct 4-byte pattern prefix; byte alphabets with every
                                   pattern of 4 bytes or more, the default there), else as 1 */
+    uint32_t top_nodes;        /* tile kernel: how the first K levels are resolved in LDS:
+                                  0 = the level index (one lookup of the K-symbol code),
+                                  1 = bitmapped nodes of depths 0 .. K-1 (Design and
+                                  Implementation, bitmapped-node figure: K dependent lookups,
+                                  child = first child + set bits below the symbol).  Setting 1
+                                  fails with PFAC_EINVAL when those nodes do not fit in LDS */
 } pfac_tuning;
 
 /* ----------------------------------------------------------------- errors */

@@ -49,6 +49,8 @@ class pfac_stats(ctypes.Structure):
         ("scan_kernel", ctypes.c_uint32), ("scan_waves", ctypes.c_uint32),
         ("stage1", ctypes.c_uint32), ("stage2", ctypes.c_uint32),
         ("build_seconds", ctypes.c_double), ("upload_seconds", ctypes.c_double),
+        ("bytes_bitmap_narrow", ctypes.c_uint64), ("bytes_level_index", ctypes.c_uint64),
+        ("bytes_top_nodes", ctypes.c_uint64),
     ]
 
     def as_dict(self):
@@ -59,7 +61,8 @@ class pfac_tuning(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_uint32), ("bytes_per_lane", ctypes.c_uint32),
                 ("index_bits", ctypes.c_uint32), ("fold_bits", ctypes.c_uint32),
                 ("wg_per_cu", ctypes.c_uint32), ("waves_per_wg", ctypes.c_uint32),
-                ("chunks_per_unit", ctypes.c_uint32), ("child_check", ctypes.c_uint32)]
+                ("chunks_per_unit", ctypes.c_uint32), ("child_check", ctypes.c_uint32),
+                ("top_nodes", ctypes.c_uint32)]
 
 
 class PfacError(RuntimeError):

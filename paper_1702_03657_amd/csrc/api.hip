@@ -120,7 +120,8 @@ static int upload_image(pfac_trie *t) {
     size_t o_pfx4 = align256(o_krec + std::max<size_t>(I.krec.size(), 1) * 4);
     size_t o_q16 = align256(o_pfx4 + std::max<size_t>(I.pfx4.size(), 1) * 4);
     size_t o_qfp = align256(o_q16 + std::max<size_t>(I.q16.size(), 1) * 4);
-    size_t total = align256(o_qfp + std::max<size_t>(I.qfp.size(), 16) * 2);
+    size_t o_top = align256(o_qfp + std::max<size_t>(I.qfp.size(), 16) * 2);
+    size_t total = align256(o_top + std::max<size_t>(I.top.size(), 1) * 4);
     auto t0 = std::chrono::steady_clock::now();
     t->dev.release();
     HIP_TRY(t->dev.reserve(total));
@@ -146,6 +147,8 @@ static int upload_image(pfac_trie *t) {
         HIP_TRY(hipMemcpy(b + o_qfp, I.qfp.data(), I.qfp.size() * 2, hipMemcpyHostToDevice));
     if (!I.root_bits.empty())
         HIP_TRY(hipMemcpy(b + o_root, I.root_bits.data(), I.root_bits.size() * 4, hipMemcpyHostToDevice));
+    if (!I.top.empty())
+        HIP_TRY(hipMemcpy(b + o_top, I.top.data(), I.top.size() * 4, hipMemcpyHostToDevice));
     ImageView &v = t->view;
     v.node = (const uint4 *)(b + o_node);
     v.label = b + o_label;
@@ -168,6 +171,9 @@ static int upload_image(pfac_trie *t) {
     v.qb = I.qb;
     v.qalph = I.qalph;
     v.q16_mul = kQ16Mul;
+    v.top = (const uint32_t *)(b + o_top);
+    v.top_nodes = I.top_nodes;
+    v.top_rw = I.top_rw;
     v.fold_syms = I.fold_syms;
     v.K = I.K;
     v.b = I.b;
@@ -302,6 +308,7 @@ static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr) {
             if (a.lds_total <= t->lds_limit) break;
         }
     } else {
+        a.top_words = t->tuning.top_nodes && t->img.K ? (uint32_t)t->img.top.size() : 0u;
         lds_layout(a, t->tuning.bytes_per_lane);
     }
     if (waves_out) *waves_out = std::max(4u, waves);
@@ -349,6 +356,11 @@ extern "C" int pfac_trie_stats(const pfac_trie *t, pfac_stats *o) {
     }
     o->build_seconds = t->build_s;
     o->upload_seconds = t->upload_s;
+    uint32_t bc = 0;
+    while ((1u << bc) < std::max(t->img.alphabet, 2u)) bc++;
+    o->bytes_bitmap_narrow = N * ((((uint64_t)1 << bc) + 7) / 8 + 4);
+    o->bytes_level_index = 8ull * t->img.lvl_words;
+    o->bytes_top_nodes = 4ull * t->img.top.size();
     return PFAC_OK;
 }
 
@@ -384,21 +396,30 @@ static bool valid_tuning(const pfac_tuning *p) {
            (p->fold_bits == 0 || p->fold_bits == 8 || p->fold_bits == 16) && p->wg_per_cu <= 8 &&
            (p->waves_per_wg == 4 || p->waves_per_wg == 8 || p->waves_per_wg == 12 ||
             p->waves_per_wg == 16) &&
-           p->chunks_per_unit >= 1 && p->chunks_per_unit <= 64 && p->child_check <= 2;
+           p->chunks_per_unit >= 1 && p->chunks_per_unit <= 64 && p->child_check <= 2 &&
+           p->top_nodes <= 1;
 }
 
 extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
     if (!t || !tn || !valid_tuning(tn)) return PFAC_EINVAL;
     const bool repack = tn->index_bits != t->tuning.index_bits || tn->fold_bits != t->tuning.fold_bits;
+    const pfac_tuning old = t->tuning;
     t->tuning = *tn;
     if (repack) {
         try {
             pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->img);
         } catch (const std::bad_alloc &) {
+            t->tuning = old;
             return PFAC_ENOMEM;
         }
-        if (!t->host_only) return upload_image(t);
     }
+    if (tn->kernel == 0 && tn->top_nodes && layout_for(t).lds_total > t->lds_limit) {
+        // the bitmapped top nodes do not fit: keep the previous tuning
+        t->tuning = old;
+        if (repack) pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->img);
+        return PFAC_EINVAL;
+    }
+    if (repack && !t->host_only) return upload_image(t);
     return PFAC_OK;
 }
 
@@ -587,7 +608,7 @@ static int enqueue_scan(const Launch &L, bool reserve) {
         } else {
             const int slot = bpl == 4 ? 0 : bpl == 8 ? 1 : 2;
             if (a.lds_total > 64 * 1024) HIP_TRY(grant_lds(slot, a.lds_total, prep_tile, (int)bpl));
-            occ = max_wg_per_cu(bpl, a.lds_total);
+            occ = max_wg_per_cu(bpl, a.lds_total, a.top_words != 0);
             want = n_tiles;
         }
         if (per_cu == 0 || per_cu > occ) per_cu = occ;

@@ -30,7 +30,7 @@ namespace pfac {
 
 // ------------------------------------------------------------------- scan
 
-template <int BPL, bool IDENT>
+template <int BPL, bool IDENT, bool TOP>
 __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
     constexpr uint32_t TILE = kWG * BPL;
     extern __shared__ __align__(16) uint8_t lds[];
@@ -49,11 +49,15 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
     const uint32_t tid = threadIdx.x;
     const uint32_t wave = tid >> 6, lane = tid & 63;
 
-    for (uint32_t i = tid; i < im.lvl_words; i += kWG) {
+    uint32_t *s_top = (uint32_t *)(lds + a.off_top);
+    const uint32_t top_rw = im.top_rw;
+    const bool top = TOP;  // the first K levels through the bitmapped nodes
+    for (uint32_t i = tid; i < (top ? 0u : im.lvl_words); i += kWG) {
         const uint2 e = ((const uint2 *)im.lvl)[i];
         s_bits[i] = e.x;
         s_rank[i] = e.y;
     }
+    for (uint32_t i = tid; i < (TOP ? a.top_words : 0u); i += kWG) s_top[i] = im.top[i];
     if (!IDENT)
         for (uint32_t i = tid; i < 256; i += kWG) s_sym[i] = im.sym[i];
 
@@ -145,6 +149,37 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
                 }
                 qn += (uint32_t)__popcll(m);
             }
+        } else if (top) {
+            // the first K symbols through the bitmapped nodes of depths
+            // 0 .. K-1: at each node the symbol's bit must be set, and the
+            // child is the first child + the set bits below it
+            for (int j = 0; j < BPL; j++) {
+                const uint32_t pl = lb + j;
+                const uint64_t p = tile_lo + pl;
+                // the K bytes lie in one text
+                bool ok = p >= lo_valid && p + K <= hi_valid &&
+                          (!T.dirty || range_clear(s_bnd, pl + 1, pl + K));
+                uint32_t v = 0;
+                for (uint32_t d = 0; d < K && ok; d++) {
+                    const uint32_t byte = s_text[pl + d];
+                    const uint32_t sy = IDENT ? byte : s_sym[byte];
+                    const uint32_t *rec = s_top + v * top_rw;
+                    const uint32_t wi = min(sy >> 5, top_rw - 2);  // in the node's bitmap
+                    const uint32_t word = rec[wi];
+                    // (0xff marks a byte outside a compressed alphabet)
+                    ok = (IDENT || sy != 0xffu) && ((word >> (sy & 31)) & 1u);
+                    uint32_t below = (uint32_t)__builtin_popcount(word & ((1u << (sy & 31)) - 1u));
+                    for (uint32_t q = 0; q < wi; q++) below += (uint32_t)__builtin_popcount(rec[q]);
+                    v = rec[top_rw - 1] + below;
+                }
+                const unsigned long long m = __ballot(ok);
+                if (ok) {
+                    const uint32_t r = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    wq[qn + r] = (pl << 18) | (v - im.lvl_start);
+                }
+                qn += (uint32_t)__popcll(m);
+            }
         } else {
             uint32_t w[BPL / 4 + 4];
 #pragma unroll
@@ -205,7 +240,10 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
             const uint32_t ent = wq[e];
             const uint32_t pl = ent >> 18;
             uint32_t v = 0, d = 0;
-            if (K) {
+            if (K && top) {
+                v = im.lvl_start + (ent & 0x3ffffu);
+                d = K;
+            } else if (K) {
                 const uint32_t code = ent & 0x3ffffu;
                 const uint32_t bits = s_bits[code >> 5];
                 const uint32_t below = bits & ((1u << (code & 31)) - 1u);
@@ -416,8 +454,11 @@ void lds_layout(ScanArgs &a, uint32_t bpl) {
         off += (bytes + 15u) & ~15u;
         return o;
     };
-    a.off_bits = take(4 * a.im.lvl_words);
-    a.off_rank = take(4 * a.im.lvl_words);
+    // the first K levels: the level index, or the bitmapped top nodes
+    const uint32_t lw = a.top_words ? 0u : a.im.lvl_words;
+    a.off_bits = take(4 * lw);
+    a.off_rank = take(4 * lw);
+    a.off_top = take(4 * a.top_words);
     a.off_sym = take(a.im.identity ? 0 : 256);
     a.off_text = take(tile + a.halo + 16);
     a.off_bnd = take(4 * ((tile + a.halo) / 32 + 2));
@@ -428,7 +469,10 @@ void lds_layout(ScanArgs &a, uint32_t bpl) {
 
 template <int BPL, bool IDENT>
 static hipError_t launch_scan_t(const ScanArgs &a, uint32_t grid, hipStream_t s) {
-    hipLaunchKernelGGL((scan_tiles<BPL, IDENT>), dim3(grid), dim3(kWG), a.lds_total, s, a);
+    if (a.top_words)
+        hipLaunchKernelGGL((scan_tiles<BPL, IDENT, true>), dim3(grid), dim3(kWG), a.lds_total, s, a);
+    else
+        hipLaunchKernelGGL((scan_tiles<BPL, IDENT, false>), dim3(grid), dim3(kWG), a.lds_total, s, a);
     return hipGetLastError();
 }
 
@@ -443,22 +487,22 @@ hipError_t launch_scan(const ScanArgs &a, uint32_t bpl, uint32_t grid, hipStream
 }
 
 template <int BPL, bool IDENT>
-static const void *scan_fn() {
-    return (const void *)scan_tiles<BPL, IDENT>;
+static const void *scan_fn(bool top) {
+    return top ? (const void *)scan_tiles<BPL, IDENT, true> : (const void *)scan_tiles<BPL, IDENT, false>;
 }
 
-static const void *scan_fn_for(uint32_t bpl, bool id) {
+static const void *scan_fn_for(uint32_t bpl, bool id, bool top) {
     switch (bpl) {
-        case 4: return id ? scan_fn<4, true>() : scan_fn<4, false>();
-        case 8: return id ? scan_fn<8, true>() : scan_fn<8, false>();
-        case 16: return id ? scan_fn<16, true>() : scan_fn<16, false>();
+        case 4: return id ? scan_fn<4, true>(top) : scan_fn<4, false>(top);
+        case 8: return id ? scan_fn<8, true>(top) : scan_fn<8, false>(top);
+        case 16: return id ? scan_fn<16, true>(top) : scan_fn<16, false>(top);
         default: return nullptr;
     }
 }
 
 hipError_t prepare_kernels(uint32_t bpl, uint32_t lds_bytes) {
-    for (int id = 0; id < 2; id++) {
-        const void *fn = scan_fn_for(bpl, id != 0);
+    for (int v = 0; v < 4; v++) {
+        const void *fn = scan_fn_for(bpl, (v & 1) != 0, (v & 2) != 0);
         if (!fn) return hipErrorInvalidValue;
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_bytes);
@@ -467,9 +511,9 @@ hipError_t prepare_kernels(uint32_t bpl, uint32_t lds_bytes) {
     return hipSuccess;
 }
 
-int max_wg_per_cu(uint32_t bpl, uint32_t lds_bytes) {
+int max_wg_per_cu(uint32_t bpl, uint32_t lds_bytes, bool top) {
     int n = 0;
-    const void *fn = scan_fn_for(bpl, true);
+    const void *fn = scan_fn_for(bpl, true, top);
     if (!fn) return 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kWG, lds_bytes) != hipSuccess || n < 1)
         n = 1;

@@ -31,11 +31,13 @@ struct ImageView {
     const uint32_t *pfx4;     // prefix-4 filter bitmap (2^pfx4_log2 bits)
     const uint32_t *q16;      // four-symbol filter: bitmap words (2^q16_lw)
     const uint4 *qfp;         // four-symbol filter: buckets of 8 x 16-bit fingerprints
+    const uint32_t *top;      // bitmapped nodes of depths 0 .. K-1: top_rw words each
     uint32_t K, b, identity, lvl_words;
     uint32_t lvl_start, max_len, n_nodes, fold_syms;
     uint32_t pfx4_log2, pfx4_mul;     // prefix-4 filter: 2^pfx4_log2 bits, hash multiplier
     uint32_t q16_lw, qfp_lb;          // four-symbol filter sizes (0 = none)
     uint32_t qa, qb, qalph, q16_mul;  // its symbol map, alphabet bytes and hash multiplier
+    uint32_t top_nodes, top_rw;       // bitmapped top nodes: count, words per node
 };
 
 struct ScanArgs {
@@ -62,6 +64,7 @@ struct ScanArgs {
     uint32_t pfx4_words, off_pfx4;    // LDS prefix-4 filter (instead of the child records)
     uint32_t q16_words;               // four-symbol filter words in LDS (mode 3; 0 = other modes)
     uint32_t lvl_lds;                 // level-index words kept in LDS (0 in mode 3)
+    uint32_t top_words, off_top;      // tile kernel: bitmapped top nodes in LDS (0 = level index)
     // outputs
     pfac_match *stage;
     uint64_t stage_cap;
@@ -124,7 +127,7 @@ hipError_t launch_walk_units(const ScanArgs &a, hipStream_t s);
 int max_wave_wg_per_cu(const ScanArgs &a, uint32_t waves);
 
 // Largest resident workgroups per CU for this layout.
-int max_wg_per_cu(uint32_t bpl, uint32_t lds_bytes);
+int max_wg_per_cu(uint32_t bpl, uint32_t lds_bytes, bool top);
 hipError_t prepare_kernels(uint32_t bpl, uint32_t lds_bytes);
 
 }  // namespace pfac

@@ -65,6 +65,14 @@ struct DeviceImageHost {
     uint32_t lvl_start = 0;            // first node id of depth K
     std::vector<uint32_t> lvl;         // 2 * lvl_words: {bits, rank before}
     std::vector<uint8_t> sym;          // 256: symbol code, 0xff = byte unused
+    // The same K levels as bitmapped nodes (the node format of Design and
+    // Implementation, with the bitmap narrowed to the 2^b symbols): node
+    // v < lvl_start has top_rw words, the bitmap of its children's symbols
+    // (at least one word) and then the id of its first child; the child on
+    // symbol s is the first child + the set bits below s.
+    uint32_t top_rw = 0;
+    uint32_t top_nodes = 0;            // nodes of depths 0 .. K-1
+    std::vector<uint32_t> top;
     uint32_t alphabet = 0;
     uint32_t n_term = 0;
     // Prefix filter of the wave kernel.  With K >= 1 it is a table of E-bit

@@ -252,6 +252,19 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
         I.lvl[2 * w + 1] = run;
         run += (uint32_t)__builtin_popcount(I.lvl[2 * w]);
     }
+    // the same K levels as bitmapped nodes: node v < lvl_start holds the
+    // bitmap of its children's symbols and the id of its first child
+    I.top_rw = std::max(1u, (1u << I.b) / 32) + 1;
+    I.top_nodes = I.lvl_start;
+    I.top.assign((size_t)I.top_nodes * I.top_rw, 0);
+    for (uint32_t v = 0; v < I.top_nodes; v++) {
+        uint32_t *rec = &I.top[(size_t)v * I.top_rw];
+        for (uint32_t e = T.row_ptr[v]; e < T.row_ptr[v + 1]; e++) {
+            const uint32_t s = I.sym[T.labels[e]];
+            rec[s >> 5] |= 1u << (s & 31);
+        }
+        rec[I.top_rw - 1] = T.row_ptr[v] + 1;
+    }
     I.krec.assign(v1 - v0, 0);
     for (uint32_t v = v0; v < v1; v++) {
         const uint32_t e0 = T.row_ptr[v], nc = T.row_ptr[v + 1] - e0;

@@ -173,3 +173,38 @@ def test_placement_depths_reach_the_requested_level_index():
             got.append(d)
         assert got == depths
         t.close()
+
+
+def test_bitmapped_top_nodes_footprint_and_limits():
+    """The bitmapped-node encoding of the first K levels: its size is the
+    number of nodes of depth < K times (bitmap words + first child), the
+    narrow bitmapped footprint uses the alphabet's bits, and a tuning whose
+    top nodes would not fit in LDS is refused without changing the trie."""
+    from synth import workloads
+    wl = workloads.c1_plain_small(n_text=1024)
+    pats = wl.patterns.as_list()
+    t = pf.Trie(pats, host_only=True)
+    for bits, K in ((8, 1), (16, 2)):
+        t.set_tuning(kernel=0, index_bits=bits, top_nodes=1)
+        st = t.stats()
+        assert st["index_depth"] == K
+        upper = 1 + len({p[:d] for p in pats for d in range(1, K)})  # nodes of depth < K
+        assert st["bytes_top_nodes"] == upper * 9 * 4
+        assert st["bytes_level_index"] == 8 * ((1 << (8 * K)) // 32)
+        assert st["bytes_bitmap_narrow"] == 36 * st["nodes"] == st["bytes_bitmap36"]
+    t.close()
+
+    dna = workloads.c3_dna(n_text=4096, k=30_000, n_plants=10)
+    pats = dna.patterns.as_list()
+    t = pf.Trie(pats, host_only=True)
+    st = t.stats()
+    assert st["bytes_bitmap_narrow"] == 5 * st["nodes"]  # 4-bit bitmap in one byte + 4
+    t.set_tuning(kernel=0, index_bits=12, top_nodes=1)  # K = 6, two words per node
+    st = t.stats()
+    upper = 1 + len({p[:d] for p in pats for d in range(1, 6)})
+    assert st["index_depth"] == 6 and st["bytes_top_nodes"] == upper * 8
+    before = t.tuning()
+    with pytest.raises(pf.PfacError):
+        t.set_tuning(index_bits=18)  # K = 9: ~39,000 nodes x 8 bytes do not fit
+    assert t.tuning() == before and t.stats()["index_depth"] == 6
+    t.close()

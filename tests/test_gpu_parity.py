@@ -168,7 +168,7 @@ def test_misaligned_text_addresses(pad):
     assert np.array_equal(counts, oracle.counts(wl.text.size, want))
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2])
+@pytest.mark.parametrize("kernel", [0, 1, 2, "0t"])
 @pytest.mark.parametrize("case", [
     "empty_text", "short_text", "no_patterns", "length_one", "duplicates", "nested_runs",
     "all_windows", "sigma1_long", "long_patterns", "match_at_end", "dense_candidates",
@@ -211,7 +211,10 @@ def test_edge_cases(case, kernel):
         text = bytes(rng.integers(0, 200, 8191).astype(np.uint8)) + b"tail!"
     text = np.frombuffer(text, dtype=np.uint8).copy()
     trie = pf.Trie(pats)
-    trie.set_tuning(kernel=kernel)
+    if kernel == "0t":  # tile kernel, first levels through the bitmapped nodes
+        trie.set_tuning(kernel=0, index_bits=8, top_nodes=1)
+    else:
+        trie.set_tuning(kernel=kernel)
     say(f"edge {case} kernel {kernel}: n={text.size} k={len(pats)} K={trie.stats()['index_depth']}")
     got, counts = gpu_scan(trie, text)
     want = oracle.brute(text, pats, threads=8)

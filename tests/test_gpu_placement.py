@@ -1,8 +1,8 @@
 """Trie placement (how many trie levels the level index resolves in LDS, down
 to none): every depth the benchmark's placement ablation measures gives the
 oracle's match list, on each workload's pattern set at a reduced text size,
-single texts and batches, for the tile kernel and for the wave kernels with
-the filter at depth 0 and 1."""
+single texts and batches, for the tile kernel (level index or bitmapped
+nodes) and for the wave kernels with the filter at depth 0 and 1."""
 
 import numpy as np
 import pytest
@@ -42,6 +42,11 @@ def _points(st):
         t = lds_depth_tuning(st, d)
         if t is not None:
             pts.append((d, t))
+    # the tile kernel with the first levels through the bitmapped nodes
+    for d in range(1, 10):
+        t = lds_depth_tuning(st, d)
+        if t is not None:
+            pts.append((d, dict(t, top_nodes=1)))
     # the wave kernels with the filter on the root's children only, and one level
     for d in (0, 1):
         t = lds_depth_tuning(st, d)
@@ -66,7 +71,13 @@ def test_every_lds_depth(name):
         f"{len(pts)} points")
     assert want.n > 0
     for d, t in pts:
-        trie.set_tuning(**t)
+        try:
+            trie.set_tuning(**t)
+        except pf.PfacError:
+            # bitmapped top nodes too large for LDS: refused, tuning unchanged
+            assert t.get("top_nodes") and trie.stats()["bytes_top_nodes"] > 0
+            say(f"  depth {d} {t}: refused (LDS)")
+            continue
         assert trie.stats()["index_depth"] == d, t
         say(f"  depth {d} {t}")
         if n_texts > 1:

@@ -1,8 +1,9 @@
 """Seeded random parity: many small pattern sets and texts drawn over
 alphabets of 2 to 256 bytes, pattern lengths that do and do not reach the
 filters' minimum lengths, planted copies and partial copies, scanned by the
-tile kernel, the fused wave kernel and the split wave kernels (with each of
-their second filter stages), single and batched, each against the oracle's
+tile kernel (first levels through the level index or the bitmapped nodes),
+the fused wave kernel and the split wave kernels (with each of their second
+filter stages), single and batched, each against the oracle's
 brute force."""
 
 import numpy as np
@@ -45,7 +46,8 @@ def _case(seed):
 
 
 TUNINGS = [dict(kernel=0), dict(kernel=1, child_check=1), dict(kernel=2, child_check=0),
-           dict(kernel=2, child_check=1), dict(kernel=2, child_check=2, chunks_per_unit=4)]
+           dict(kernel=2, child_check=1), dict(kernel=2, child_check=2, chunks_per_unit=4),
+           dict(kernel=0, index_bits=8, top_nodes=1)]
 
 
 @pytest.mark.parametrize("seed", range(20))
