@@ -22,9 +22,10 @@ one request at a time (c5); ``--no-extras`` / ``--no-serving`` leave them out.
 ``--placement c1,c2,...`` prints instead one line with the trie-placement
 ablation: the tile kernel with 0, 1, 2, ... trie levels resolved in LDS by
 the level index or by bitmapped nodes (the rest walked through the node
-records in global memory), the default launch and the autotuned one, on each
-workload, every point checked against the oracle, with the trie's footprint
-in each encoding.
+records in global memory), images truncated at depths 4, 8 and 16 (tails
+verified against the pattern bytes), the default launch and the autotuned
+one, on each workload, every point checked against the oracle, with the
+trie's footprint in each encoding.
 """
 
 from __future__ import annotations
@@ -409,6 +410,11 @@ def placement_ablation(pf, torch, names, steps, warmup, threads):
         # the same depths through the bitmapped nodes (where they fit in LDS)
         points += [(f"tile kernel, bitmapped nodes depth {d}", t and dict(t, top_nodes=1))
                    for d, t in ((d, lds_depth_tuning(st, d)) for d in range(1, 10))]
+        # images truncated at depth D (tails verified), level index as deep as allowed up to 8
+        deep = max([d for d in range(1, 9) if lds_depth_tuning(st, d) is not None], default=0)
+        for D in (4, 8, 16):
+            t = lds_depth_tuning(st, min(deep, D))
+            points.append((f"tile kernel, image truncated at depth {D}", t and dict(t, trunc_depth=D)))
         points = [(lab, t) for lab, t in points if t is not None]
         points.append(("library default", default))
         trie.set_tuning(**default)
@@ -456,12 +462,15 @@ def placement_ablation(pf, torch, names, steps, warmup, threads):
                 "lds_bytes": int(s2["lds_bytes"]), "scan_kernel": int(s2["scan_kernel"]),
                 "top_lds_bytes": int(s2["bytes_top_nodes"] if tn.get("top_nodes")
                                      else s2["bytes_level_index"]),
+                "image_bytes": int(s2["bytes_device"]), "node_bytes": int(s2["bytes_nodes"]),
+                "tail_bytes": int(s2["bytes_tails"]),
                 "tuning": {k: int(v) for k, v in tn.items()},
                 "ms_per_scan": round(ms, 5), "gbit_s": round(gbit, 2),
                 "hbm_frac": round(n / ms / 1e6 / HBM_PEAK_GBS, 4),
                 "main_kernel_ms": round(kms, 5), "parity_with_oracle": same})
             log(f"  {label:28s} K={int(s2['index_depth'])} {gbit:10.2f} Gbit/s "
-                f"({ms:.4f} ms/scan, kernel {kms:.4f} ms) parity={same}")
+                f"({ms:.4f} ms/scan, kernel {kms:.4f} ms) image {int(s2['bytes_device'])} B "
+                f"parity={same}")
         rows.append(res)
         del text, offs, out
         trie.close()
@@ -479,7 +488,7 @@ def main():
     ap.add_argument("--retune", action="store_true", help="ignore the cached autotune choice")
     ap.add_argument("--tuning", default=None,
                     help="kernel,bytes_per_lane,index_bits,fold_bits,wg_per_cu,waves_per_wg,"
-                         "chunks_per_unit,child_check[,top_nodes]")
+                         "chunks_per_unit,child_check[,top_nodes[,trunc_depth]]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true",
@@ -546,7 +555,7 @@ def main():
 
     if args.tuning:
         names = ["kernel", "bytes_per_lane", "index_bits", "fold_bits", "wg_per_cu", "waves_per_wg",
-                 "chunks_per_unit", "child_check", "top_nodes"]
+                 "chunks_per_unit", "child_check", "top_nodes", "trunc_depth"]
         trie.set_tuning(**dict(zip(names, (int(x) for x in args.tuning.split(",")))))
         tuning, tuned_now = trie.tuning(), False
     else:

@@ -98,6 +98,10 @@ typedef struct {
     uint64_t bytes_top_nodes;     /* LDS bytes of the same K levels as bitmapped nodes (nodes of
                                      depths 0 .. K-1, bitmap over the index's 2^symbol_bits
                                      symbols padded to 32-bit words, + first child) */
+    uint64_t trunc_depth;         /* depth the device image is truncated at (0 = whole trie) */
+    uint64_t bytes_nodes;         /* 16-byte node records in the device image */
+    uint64_t bytes_tails;         /* truncated image: tail entries + the pattern bytes after the
+                                     truncation depth that the walk verifies */
 } pfac_stats;
 
 /* Launch parameters chosen by hand or by pfac_autotune. */
@@ -126,6 +130,13 @@ typedef struct {
                                   Implementation, bitmapped-node figure: K dependent lookups,
                                   child = first child + set bits below the symbol).  Setting 1
                                   fails with PFAC_EINVAL when those nodes do not fit in LDS */
+    uint32_t trunc_depth;      /* 0 = the whole trie on the device; D = 1..255: the device image
+                                  keeps only nodes of depths 0..D (Design and Implementation,
+                                  step III, truncation) and each depth-D node with children
+                                  lists the terminal nodes below it; the walk verifies the text
+                                  against their pattern bytes, longest first, so results stay
+                                  exact.  Scans then use the tile kernel (kernel is ignored) and
+                                  the level index depth is at most D */
 } pfac_tuning;
 
 /* ----------------------------------------------------------------- errors */

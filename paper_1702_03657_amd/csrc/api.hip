@@ -121,7 +121,9 @@ static int upload_image(pfac_trie *t) {
     size_t o_q16 = align256(o_pfx4 + std::max<size_t>(I.pfx4.size(), 1) * 4);
     size_t o_qfp = align256(o_q16 + std::max<size_t>(I.q16.size(), 1) * 4);
     size_t o_top = align256(o_qfp + std::max<size_t>(I.qfp.size(), 16) * 2);
-    size_t total = align256(o_top + std::max<size_t>(I.top.size(), 1) * 4);
+    size_t o_tail = align256(o_top + std::max<size_t>(I.top.size(), 1) * 4);
+    size_t o_tailb = align256(o_tail + std::max<size_t>(I.tail.size(), 4) * 4);
+    size_t total = align256(o_tailb + std::max<size_t>(I.tail_bytes.size(), 64));
     auto t0 = std::chrono::steady_clock::now();
     t->dev.release();
     HIP_TRY(t->dev.reserve(total));
@@ -149,6 +151,10 @@ static int upload_image(pfac_trie *t) {
         HIP_TRY(hipMemcpy(b + o_root, I.root_bits.data(), I.root_bits.size() * 4, hipMemcpyHostToDevice));
     if (!I.top.empty())
         HIP_TRY(hipMemcpy(b + o_top, I.top.data(), I.top.size() * 4, hipMemcpyHostToDevice));
+    if (!I.tail.empty())
+        HIP_TRY(hipMemcpy(b + o_tail, I.tail.data(), I.tail.size() * 4, hipMemcpyHostToDevice));
+    if (!I.tail_bytes.empty())
+        HIP_TRY(hipMemcpy(b + o_tailb, I.tail_bytes.data(), I.tail_bytes.size(), hipMemcpyHostToDevice));
     ImageView &v = t->view;
     v.node = (const uint4 *)(b + o_node);
     v.label = b + o_label;
@@ -174,6 +180,8 @@ static int upload_image(pfac_trie *t) {
     v.top = (const uint32_t *)(b + o_top);
     v.top_nodes = I.top_nodes;
     v.top_rw = I.top_rw;
+    v.tail = (const uint4 *)(b + o_tail);
+    v.tail_bytes = b + o_tailb;
     v.fold_syms = I.fold_syms;
     v.K = I.K;
     v.b = I.b;
@@ -212,7 +220,7 @@ static int build_common(const uint8_t *data, const uint64_t *offsets, uint32_t k
             delete t;
             return PFAC_EINVAL;
         }
-        pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->img);
+        pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->tuning.trunc_depth, t->img);
     } catch (const std::bad_alloc &) {
         delete t;
         return PFAC_ENOMEM;
@@ -361,6 +369,9 @@ extern "C" int pfac_trie_stats(const pfac_trie *t, pfac_stats *o) {
     o->bytes_bitmap_narrow = N * ((((uint64_t)1 << bc) + 7) / 8 + 4);
     o->bytes_level_index = 8ull * t->img.lvl_words;
     o->bytes_top_nodes = 4ull * t->img.top.size();
+    o->trunc_depth = t->img.trunc_depth;
+    o->bytes_nodes = 4ull * t->img.node.size();
+    o->bytes_tails = 4ull * t->img.tail.size() + t->img.tail_bytes.size();
     return PFAC_OK;
 }
 
@@ -397,17 +408,18 @@ static bool valid_tuning(const pfac_tuning *p) {
            (p->waves_per_wg == 4 || p->waves_per_wg == 8 || p->waves_per_wg == 12 ||
             p->waves_per_wg == 16) &&
            p->chunks_per_unit >= 1 && p->chunks_per_unit <= 64 && p->child_check <= 2 &&
-           p->top_nodes <= 1;
+           p->top_nodes <= 1 && p->trunc_depth <= 255;
 }
 
 extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
     if (!t || !tn || !valid_tuning(tn)) return PFAC_EINVAL;
-    const bool repack = tn->index_bits != t->tuning.index_bits || tn->fold_bits != t->tuning.fold_bits;
+    const bool repack = tn->index_bits != t->tuning.index_bits || tn->fold_bits != t->tuning.fold_bits ||
+                        tn->trunc_depth != t->tuning.trunc_depth;
     const pfac_tuning old = t->tuning;
     t->tuning = *tn;
     if (repack) {
         try {
-            pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->img);
+            pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->tuning.trunc_depth, t->img);
         } catch (const std::bad_alloc &) {
             t->tuning = old;
             return PFAC_ENOMEM;
@@ -416,7 +428,7 @@ extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
     if (tn->kernel == 0 && tn->top_nodes && layout_for(t).lds_total > t->lds_limit) {
         // the bitmapped top nodes do not fit: keep the previous tuning
         t->tuning = old;
-        if (repack) pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->img);
+        if (repack) pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->tuning.trunc_depth, t->img);
         return PFAC_EINVAL;
     }
     if (repack && !t->host_only) return upload_image(t);
@@ -533,6 +545,7 @@ static hipError_t prep_wave(int mode, uint32_t bytes) { return prepare_wave_kern
 // Wave kernel when asked for and its LDS layout fits; the tile kernel otherwise.
 static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out) {
     if (t->tuning.kernel != 1 && t->tuning.kernel != 2) return false;
+    if (t->img.trunc_depth) return false;  // tail nodes: the tile kernel's walk only
     if (t->crs.max_len > 0xffff) return false;  // walk limits are 16-bit
     const ScanArgs a = layout_for(t, waves_out);
     return a.lds_total <= t->lds_limit;
@@ -839,6 +852,14 @@ extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *tex
                         for (uint32_t cc : {0u, 1u, 2u})
                             cands.push_back({kernel, 16, bits, fold, 0, waves, g, cc});
         for (uint32_t bpl : {8u, 16u}) cands.push_back({0, bpl, bits, 8, 0, 16, 16, 1});
+    }
+    // a truncated image is a footprint choice: keep it, and scan it with the
+    // tile kernel, the only one whose walk verifies tails
+    if (start.trunc_depth) {
+        cands.erase(std::remove_if(cands.begin(), cands.end(),
+                                   [](const pfac_tuning &c) { return c.kernel != 0; }),
+                    cands.end());
+        for (auto &c : cands) c.trunc_depth = start.trunc_depth;
     }
     float best_ms = 1e30f;
     pfac_tuning best_t = start;

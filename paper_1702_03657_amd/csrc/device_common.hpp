@@ -125,6 +125,34 @@ __device__ __forceinline__ bool range_clear(const uint32_t *bnd, uint32_t a, uin
     return any == 0;
 }
 
+// Tail node of a truncated image: the text from window offset q on against
+// the node's entries, longest first; the first equal one gives the pattern
+// list of the walk, else `hit` (the deepest terminal node above) stands.
+__device__ __forceinline__ uint2 verify_tails(const ImageView &im, const uint8_t *gbase,
+                                              const Tile &T, uint32_t q, uint32_t first,
+                                              uint32_t count, uint2 hit) {
+    for (uint32_t i = 0; i < count; i++) {
+        const uint4 e = im.tail[first + i];
+        const uint32_t len = e.y;
+        bool eq;
+        if (q + len <= T.win) {
+            // in the window, with no text boundary inside
+            eq = (!T.dirty || range_clear(T.bnd, q, q + len)) &&
+                 chain_equal(T.text, q, im.tail_bytes, e.x, len);
+        } else {
+            // past the window: the next boundary must not fall inside
+            eq = (q >= T.win || !T.dirty || range_clear(T.bnd, q, T.win)) &&
+                 T.lo + q + len <= T.next_bnd;
+            for (uint32_t b = 0; b < len && eq; b++) {
+                const uint32_t c = q + b < T.win ? (uint32_t)T.text[q + b] : (uint32_t)gbase[T.lo + q + b];
+                eq = c == im.tail_bytes[e.x + b];
+            }
+        }
+        if (eq) return make_uint2(e.z, e.w);
+    }
+    return hit;
+}
+
 // Walk from node v at depth d for the start position at window offset pl.
 // Returns the pattern list of the deepest terminal node passed as
 // (offset, stored length); length 0 means no pattern ends on the walk.
@@ -135,7 +163,10 @@ __device__ __forceinline__ uint2 walk(const ImageView &im, const uint8_t *gbase,
         const uint4 r = im.node[v];
         if (r.z & kTermFlagD) hit = make_uint2(r.w, r.z >> kCountShiftD);
         const uint32_t nc = r.z & 0xffffu;
-        if (nc == 0) break;
+        if (nc == 0) {
+            if (r.x) hit = verify_tails(im, gbase, T, pl + d, r.x - 1, r.y, hit);
+            break;
+        }
         const uint32_t q = pl + d;
         const bool skip = (r.z & kSkipFlagD) != 0;
         if (skip) {

@@ -32,6 +32,8 @@ struct ImageView {
     const uint32_t *q16;      // four-symbol filter: bitmap words (2^q16_lw)
     const uint4 *qfp;         // four-symbol filter: buckets of 8 x 16-bit fingerprints
     const uint32_t *top;      // bitmapped nodes of depths 0 .. K-1: top_rw words each
+    const uint4 *tail;        // truncated image: tail entries (byte offset, length, list)
+    const uint8_t *tail_bytes;
     uint32_t K, b, identity, lvl_words;
     uint32_t lvl_start, max_len, n_nodes, fold_syms;
     uint32_t pfx4_log2, pfx4_mul;     // prefix-4 filter: 2^pfx4_log2 bits, hash multiplier

@@ -73,6 +73,14 @@ struct DeviceImageHost {
     uint32_t top_rw = 0;
     uint32_t top_nodes = 0;            // nodes of depths 0 .. K-1
     std::vector<uint32_t> top;
+    // Truncated image (trunc_depth D > 0): only nodes of depths 0..D; a
+    // depth-D node with children has x = 1 + its first tail entry, y = the
+    // number of entries, no children.  Entry (4 words): offset of the bytes
+    // after depth D in tail_bytes, their count, the root-path pattern list of
+    // the terminal node they reach (offset, stored length); longest first.
+    uint32_t trunc_depth = 0;
+    std::vector<uint32_t> tail;
+    std::vector<uint8_t> tail_bytes;
     uint32_t alphabet = 0;
     uint32_t n_term = 0;
     // Prefix filter of the wave kernel.  With K >= 1 it is a table of E-bit
@@ -120,6 +128,7 @@ constexpr uint32_t kPfx4Mul = 0x9E3779B1u;
 // Derives the device image from the CRS trie for a level index of at most
 // `index_bits` bits and a prefix filter of `fold_bits` (0, 8 or 16) bits per
 // entry.
-void pack_image(const CrsTrie &t, uint32_t index_bits, uint32_t fold_bits, DeviceImageHost &img);
+void pack_image(const CrsTrie &t, uint32_t index_bits, uint32_t fold_bits, uint32_t trunc_depth,
+                DeviceImageHost &img);
 
 }  // namespace pfac

@@ -89,11 +89,13 @@ static uint32_t ceil_log2(uint32_t x) {
     return b;
 }
 
-void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
+void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits, uint32_t trunc_depth,
                 DeviceImageHost &I) {
     I = DeviceImageHost{};
     const uint32_t N = T.n_nodes();
     const uint32_t E = T.n_edges();
+    // truncation applies when some node lies deeper than trunc_depth
+    const uint32_t D = (trunc_depth >= 1 && T.level_start.size() > (size_t)trunc_depth + 2) ? trunc_depth : 0u;
 
     // node records and terminal ordinals
     I.node.assign(4ull * N, 0);
@@ -123,8 +125,10 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
     // w = the node reached after len labels).  No pattern ends strictly
     // inside the run, so comparing the text with the stored labels in bulk
     // reaches the same node as walking them one by one, and a mismatch ends
-    // the walk with nothing reported.
-    {
+    // the walk with nothing reported.  (A truncated image walks node by
+    // node: no run may cross the truncation depth.)
+    if (D) I.chain.assign(40, 0);
+    if (!D) {
         std::vector<uint32_t> parent0(N, kNone);
         for (uint32_t v = 0; v < N; v++)
             for (uint32_t e = T.row_ptr[v]; e < T.row_ptr[v + 1]; e++) parent0[e + 1] = v;
@@ -199,6 +203,50 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
     I.pout_ptr.assign(1, 0);
     if (I.pout_ids.empty()) I.pout_ids.push_back(0);
 
+    // Truncation (Design and Implementation, step III) kept exact: only the
+    // nodes of depths 0..D stay; a depth-D node with children becomes a tail
+    // node whose record lists every terminal node below it (its pattern's
+    // bytes after depth D, their count, and the node's root-path pattern
+    // list), longest first.  The walk compares the text with each in turn;
+    // the first one equal gives the list of every pattern matching there.
+    if (D) {
+        I.trunc_depth = D;
+        const uint32_t t0 = T.level_start[D], t1 = T.level_start[D + 1];
+        std::vector<uint32_t> anc(N, kNone);  // depth-D ancestor of deeper nodes
+        std::vector<std::vector<std::pair<uint32_t, uint32_t>>> under(t1 - t0);  // (depth, node)
+        for (size_t d = D + 1; d + 1 < T.level_start.size(); d++) {
+            for (uint32_t v = T.level_start[d]; v < T.level_start[d + 1]; v++) {
+                const uint32_t p = parent[v];
+                anc[v] = d == D + 1 ? p : anc[p];
+                if (ord_of[v] != kNone) under[anc[v] - t0].push_back({(uint32_t)d, v});
+            }
+        }
+        for (uint32_t t = t0; t < t1; t++) {
+            if (T.row_ptr[t + 1] == T.row_ptr[t]) continue;  // a leaf: nothing below
+            auto &L = under[t - t0];
+            std::sort(L.begin(), L.end(), [](const std::pair<uint32_t, uint32_t> &x,
+                                             const std::pair<uint32_t, uint32_t> &y) {
+                return x.first != y.first ? x.first > y.first : x.second < y.second;
+            });
+            uint32_t *rec = &I.node[4ull * t];
+            rec[0] = 1u + (uint32_t)(I.tail.size() / 4);
+            rec[1] = (uint32_t)L.size();
+            rec[2] &= ~kNcMask;
+            for (const auto &dv : L) {
+                const uint32_t v = dv.second, len = dv.first - D;
+                const uint8_t *pb = T.pat_data.data() + T.pat_off[T.rep[v]];
+                I.tail.push_back((uint32_t)I.tail_bytes.size());
+                I.tail.push_back(len);
+                I.tail.push_back(I.node[4ull * v + 3]);
+                I.tail.push_back(I.node[4ull * v + 2] >> kCountShift);
+                I.tail_bytes.insert(I.tail_bytes.end(), pb + D, pb + dv.first);
+            }
+        }
+        I.node.resize(4ull * t1);
+        I.label.resize(std::max<size_t>(1, t1 - 1));
+    }
+    I.tail_bytes.resize(I.tail_bytes.size() + 40, 0);  // the kernels read whole words past the end
+
     // alphabet and level index
     bool used[256] = {false};
     for (uint32_t e = 0; e < E; e++) used[T.labels[e]] = true;
@@ -208,6 +256,7 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
     uint32_t depth = (uint32_t)T.max_len;
     uint32_t k_cap = T.k ? (uint32_t)std::min<uint64_t>(T.min_len - 1, depth) : 0;
     k_cap = std::min(k_cap, 12u);
+    if (D) k_cap = std::min(k_cap, D);  // the index's nodes must stay in the image
     uint32_t K8 = std::min(index_bits / 8, k_cap);
     uint32_t Kc = std::min(index_bits / b_comp, k_cap);
     I.sym.assign(256, 0xff);

@@ -208,3 +208,33 @@ def test_bitmapped_top_nodes_footprint_and_limits():
         t.set_tuning(index_bits=18)  # K = 9: ~39,000 nodes x 8 bytes do not fit
     assert t.tuning() == before and t.stats()["index_depth"] == 6
     t.close()
+
+
+def test_truncated_image_sizes():
+    """A truncated image keeps the nodes of depths 0..D and, per distinct
+    pattern longer than D, one 16-byte tail entry and its bytes after D;
+    depths at or past the deepest node leave the whole trie, and the scan
+    falls back to the tile kernel."""
+    pats = [b"he", b"she", b"his", b"hers", b"hers", b"abcdefgh", b"abcdxyz", b"a"]
+    t = pf.Trie(pats, host_only=True)
+    full = t.stats()
+    assert full["trunc_depth"] == 0 and full["bytes_tails"] == 40
+    assert full["bytes_nodes"] == 16 * full["nodes"]
+    distinct = set(pats)
+    for D in range(1, 9):
+        t.set_tuning(trunc_depth=D)
+        st = t.stats()
+        deeper = [p for p in distinct if len(p) > D]
+        if max(len(p) for p in pats) <= D:
+            assert st["trunc_depth"] == 0 and st["bytes_nodes"] == full["bytes_nodes"]
+            continue
+        kept = 1 + len({p[:d] for p in pats for d in range(1, min(len(p), D) + 1)})
+        assert st["trunc_depth"] == D and st["scan_kernel"] == 0
+        assert st["index_depth"] <= D
+        assert st["bytes_nodes"] == 16 * kept
+        assert st["bytes_tails"] == 16 * len(deeper) + sum(len(p) - D for p in deeper) + 40
+    t.set_tuning(trunc_depth=0)
+    assert t.stats()["bytes_nodes"] == full["bytes_nodes"]
+    with pytest.raises(pf.PfacError):
+        t.set_tuning(trunc_depth=256)
+    t.close()

@@ -168,7 +168,7 @@ def test_misaligned_text_addresses(pad):
     assert np.array_equal(counts, oracle.counts(wl.text.size, want))
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, "0t"])
+@pytest.mark.parametrize("kernel", [0, 1, 2, "0t", "0d"])
 @pytest.mark.parametrize("case", [
     "empty_text", "short_text", "no_patterns", "length_one", "duplicates", "nested_runs",
     "all_windows", "sigma1_long", "long_patterns", "match_at_end", "dense_candidates",
@@ -213,6 +213,8 @@ def test_edge_cases(case, kernel):
     trie = pf.Trie(pats)
     if kernel == "0t":  # tile kernel, first levels through the bitmapped nodes
         trie.set_tuning(kernel=0, index_bits=8, top_nodes=1)
+    elif kernel == "0d":  # image truncated at depth 2, tails verified
+        trie.set_tuning(kernel=0, trunc_depth=2)
     else:
         trie.set_tuning(kernel=kernel)
     say(f"edge {case} kernel {kernel}: n={text.size} k={len(pats)} K={trie.stats()['index_depth']}")
@@ -221,6 +223,40 @@ def test_edge_cases(case, kernel):
     assert_same(got, want)
     if text.size:
         assert np.array_equal(counts, oracle.counts(text.size, want))
+
+
+TRUNC_CASES = {
+    "c1": lambda: workloads.c1_plain_small(n_text=(1 << 18) + 77, k=100, n_plants=400),
+    "c2": lambda: workloads.c2_signature_set(n_text=(1 << 21) + 5, mean_gap=1024),
+    "c3": lambda: workloads.c3_dna(n_text=(1 << 20) + 5, k=20_000, n_plants=2000),
+    "c4": lambda: workloads.c4_batched(n_small=2000, n_large=2, large_lo=1 << 16,
+                                       large_hi=1 << 18, rate=1 / 256),
+}
+
+
+@pytest.mark.parametrize("name", sorted(TRUNC_CASES))
+def test_truncated_images(name):
+    """Images truncated at several depths (tails verified against the
+    pattern bytes) give the oracle's list, single texts and batches."""
+    wl = TRUNC_CASES[name]()
+    offs = wl.offsets.astype(np.uint64)
+    batch = len(offs) > 2
+    want = oracle.bucketed(wl.text, wl.patterns, offsets=wl.offsets if batch else None, threads=8)
+    assert want.n > 100
+    trie = pf.Trie(wl.patterns)
+    for D in (1, 2, 3, 5, 8, 12, 20, 40):
+        trie.set_tuning(kernel=0, trunc_depth=D, index_bits=16)
+        st = trie.stats()
+        say(f"truncated {name} D={D}: depth {st['trunc_depth']} K={st['index_depth']} "
+            f"nodes {st['bytes_nodes']} tails {st['bytes_tails']}")
+        if batch:
+            got, n = gpu_scan_batch(trie, wl.text, offs)
+            assert n == want.n
+            assert_same(got, want, with_text=True)
+        else:
+            got, counts = gpu_scan(trie, wl.text, pad_front=D % 16)
+            assert_same(got, want)
+            assert np.array_equal(counts, oracle.counts(wl.text.size, want))
 
 
 @pytest.mark.parametrize("kernel", [1, 2])
