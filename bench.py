@@ -23,9 +23,10 @@ one request at a time (c5); ``--no-extras`` / ``--no-serving`` leave them out.
 ablation: the tile kernel with 0, 1, 2, ... trie levels resolved in LDS by
 the level index or by bitmapped nodes (the rest walked through the node
 records in global memory), images truncated at depths 4, 8 and 16 (tails
-verified against the pattern bytes), the default launch and the autotuned
-one, on each workload, every point checked against the oracle, with the
-trie's footprint in each encoding.
+verified against the pattern bytes), the merged DAG image, the default
+launch and the autotuned one, on each workload, every point checked against
+the oracle, with the trie's footprint in each encoding.  ``--footprint
+1000,10000,...`` prints the footprint curve (host only, no GPU).
 """
 
 from __future__ import annotations
@@ -356,7 +357,7 @@ def lds_depth_tuning(stats, depth):
     if bits > 18 or depth > int(stats["min_len"]) - 1:
         return None
     return dict(kernel=0, bytes_per_lane=16, index_bits=bits, fold_bits=0, wg_per_cu=0,
-                child_check=0, top_nodes=0)
+                child_check=0, top_nodes=0, trunc_depth=0, dag=0)
 
 
 PLACEMENT_WORKLOADS = {
@@ -367,6 +368,37 @@ PLACEMENT_WORKLOADS = {
     # the serving pattern set over its first 64 requests, as one batch
     "c5": lambda w: w.c5_requests(64),
 }
+
+
+FOOTPRINT_FAMILIES = {
+    # name: (pattern lengths, byte distribution, numpy seed index)
+    "c1-like": ((4, 16), "uniform", 0),
+    "c2-like": ((8, 64), "mix", 1),
+    "c3-like": ((20, 32), "acgt", 2),
+}
+
+
+def footprint_curve(pf, ks):
+    """Trie footprints against the number of patterns (host only): the CRS
+    trie, the merged DAG in CRS form, 36-byte bitmapped nodes and the dense
+    256-entry table, for seeded pattern sets of each family."""
+    from synth import workloads
+    rows = []
+    for fam, ((lo, hi), dist, idx) in FOOTPRINT_FAMILIES.items():
+        for k in ks:
+            pats = workloads.make_patterns(workloads.rng_for(200 + idx), k, lo, hi, dist)
+            t = pf.Trie(pats, host_only=True)
+            st = t.stats()
+            rows.append({"family": fam, "k": k, "nodes": int(st["nodes"]),
+                         "dag_nodes": int(st["dag_nodes"]), "dag_edges": int(st["dag_edges"]),
+                         "bytes_crs": int(st["bytes_crs"]), "bytes_dag_crs": int(st["bytes_dag_crs"]),
+                         "bytes_bitmap36": int(st["bytes_bitmap36"]),
+                         "bytes_bitmap_narrow": int(st["bytes_bitmap_narrow"]),
+                         "bytes_dense256": int(st["bytes_dense256"])})
+            log(f"footprint {fam} k={k}: nodes {st['nodes']} dag {st['dag_nodes']} "
+                f"crs {st['bytes_crs']} dag_crs {st['bytes_dag_crs']}")
+            t.close()
+    return rows
 
 
 def placement_ablation(pf, torch, names, steps, warmup, threads):
@@ -414,7 +446,10 @@ def placement_ablation(pf, torch, names, steps, warmup, threads):
         deep = max([d for d in range(1, 9) if lds_depth_tuning(st, d) is not None], default=0)
         for D in (4, 8, 16):
             t = lds_depth_tuning(st, min(deep, D))
-            points.append((f"tile kernel, image truncated at depth {D}", t and dict(t, trunc_depth=D)))
+            points.append((f"tile kernel, image truncated at depth {D}", t and dict(t, trunc_depth=D, dag=0)))
+        # the merged DAG image (suffix and end-node merging, ids from edge ranks)
+        t = lds_depth_tuning(st, deep)
+        points.append(("tile kernel, merged DAG image", t and dict(t, dag=1)))
         points = [(lab, t) for lab, t in points if t is not None]
         points.append(("library default", default))
         trie.set_tuning(**default)
@@ -424,7 +459,9 @@ def placement_ablation(pf, torch, names, steps, warmup, threads):
                "footprint_bytes": {"crs": int(st["bytes_crs"]), "dense256": int(st["bytes_dense256"]),
                                    "bitmap36": int(st["bytes_bitmap36"]),
                                    "bitmap_narrow": int(st["bytes_bitmap_narrow"]),
+                                   "dag_crs": int(st["bytes_dag_crs"]),
                                    "device_image": int(st["bytes_device"])},
+               "nodes": int(st["nodes"]), "dag_nodes": int(st["dag_nodes"]),
                "points": []}
         for label, tn in points:
             try:
@@ -463,7 +500,7 @@ def placement_ablation(pf, torch, names, steps, warmup, threads):
                 "top_lds_bytes": int(s2["bytes_top_nodes"] if tn.get("top_nodes")
                                      else s2["bytes_level_index"]),
                 "image_bytes": int(s2["bytes_device"]), "node_bytes": int(s2["bytes_nodes"]),
-                "tail_bytes": int(s2["bytes_tails"]),
+                "tail_bytes": int(s2["bytes_tails"]), "dag_nodes": int(s2["dag_nodes"]),
                 "tuning": {k: int(v) for k, v in tn.items()},
                 "ms_per_scan": round(ms, 5), "gbit_s": round(gbit, 2),
                 "hbm_frac": round(n / ms / 1e6 / HBM_PEAK_GBS, 4),
@@ -488,7 +525,7 @@ def main():
     ap.add_argument("--retune", action="store_true", help="ignore the cached autotune choice")
     ap.add_argument("--tuning", default=None,
                     help="kernel,bytes_per_lane,index_bits,fold_bits,wg_per_cu,waves_per_wg,"
-                         "chunks_per_unit,child_check[,top_nodes[,trunc_depth]]")
+                         "chunks_per_unit,child_check[,top_nodes[,trunc_depth[,dag]]]")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true",
@@ -501,6 +538,9 @@ def main():
     ap.add_argument("--serving-budget", type=int, default=1 << 30, help="HBM bytes for request texts")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of the text size (counter calibration)")
+    ap.add_argument("--footprint", default=None, metavar="k1,k2,...",
+                    help="instead of the headline line: trie footprints (CRS, merged DAG, bitmapped, "
+                         "dense) for seeded pattern sets of these sizes, host only, one JSON line")
     ap.add_argument("--placement", default=None, metavar="c1,c2,...",
                     help="instead of the headline line: the trie-placement ablation (LDS depth "
                          "0, 1, 2, ... of the tile kernel, default and autotuned launches) on "
@@ -513,6 +553,12 @@ def main():
                                    "text range with no exchange, so more GPUs are not measured "
                                    "here (run with --gpus 1)"}))
         sys.exit(2)
+
+    if args.footprint:
+        import paper_1702_03657_amd as pf
+        rows = footprint_curve(pf, [int(x) for x in args.footprint.split(",")])
+        print(json.dumps({"footprint_curve": rows}), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -555,7 +601,7 @@ def main():
 
     if args.tuning:
         names = ["kernel", "bytes_per_lane", "index_bits", "fold_bits", "wg_per_cu", "waves_per_wg",
-                 "chunks_per_unit", "child_check", "top_nodes", "trunc_depth"]
+                 "chunks_per_unit", "child_check", "top_nodes", "trunc_depth", "dag"]
         trie.set_tuning(**dict(zip(names, (int(x) for x in args.tuning.split(",")))))
         tuning, tuned_now = trie.tuning(), False
     else:

@@ -102,6 +102,13 @@ typedef struct {
     uint64_t bytes_nodes;         /* 16-byte node records in the device image */
     uint64_t bytes_tails;         /* truncated image: tail entries + the pattern bytes after the
                                      truncation depth that the walk verifies */
+    uint64_t dag_nodes;           /* the trie with equal subtries merged (Design and
+                                     Implementation, steps IV and V: suffix and end-node
+                                     merging): nodes ... */
+    uint64_t dag_edges;           /* ... and edges */
+    uint64_t bytes_dag_crs;       /* that DAG in CRS form with exact pattern ids: row pointers,
+                                     labels, children, rank added per edge, terminal flags and
+                                     the k ids in sorted-string order */
 } pfac_stats;
 
 /* Launch parameters chosen by hand or by pfac_autotune. */
@@ -137,6 +144,13 @@ typedef struct {
                                   against their pattern bytes, longest first, so results stay
                                   exact.  Scans then use the tile kernel (kernel is ignored) and
                                   the level index depth is at most D */
+    uint32_t dag;              /* 1 = the device image is the merged DAG (steps IV and V) with
+                                  pattern identities kept on the edges: each edge adds the
+                                  number of distinct pattern strings sorting before its subtrie,
+                                  so a walk sums to the rank of its deepest pattern string, whose
+                                  root-path pattern list the image keeps.  Scans use the tile
+                                  kernel; cannot be combined with top_nodes or trunc_depth
+                                  (PFAC_EINVAL) */
 } pfac_tuning;
 
 /* ----------------------------------------------------------------- errors */

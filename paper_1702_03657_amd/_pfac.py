@@ -52,6 +52,8 @@ class pfac_stats(ctypes.Structure):
         ("bytes_bitmap_narrow", ctypes.c_uint64), ("bytes_level_index", ctypes.c_uint64),
         ("bytes_top_nodes", ctypes.c_uint64), ("trunc_depth", ctypes.c_uint64),
         ("bytes_nodes", ctypes.c_uint64), ("bytes_tails", ctypes.c_uint64),
+        ("dag_nodes", ctypes.c_uint64), ("dag_edges", ctypes.c_uint64),
+        ("bytes_dag_crs", ctypes.c_uint64),
     ]
 
     def as_dict(self):
@@ -63,7 +65,8 @@ class pfac_tuning(ctypes.Structure):
                 ("index_bits", ctypes.c_uint32), ("fold_bits", ctypes.c_uint32),
                 ("wg_per_cu", ctypes.c_uint32), ("waves_per_wg", ctypes.c_uint32),
                 ("chunks_per_unit", ctypes.c_uint32), ("child_check", ctypes.c_uint32),
-                ("top_nodes", ctypes.c_uint32), ("trunc_depth", ctypes.c_uint32)]
+                ("top_nodes", ctypes.c_uint32), ("trunc_depth", ctypes.c_uint32),
+                ("dag", ctypes.c_uint32)]
 
 
 class PfacError(RuntimeError):

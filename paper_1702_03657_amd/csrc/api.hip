@@ -54,6 +54,8 @@ struct DeviceBuf {
     }
 };
 
+constexpr uint64_t kNoSize = ~0ull;
+
 struct pfac_trie {
     CrsTrie crs;
     DeviceImageHost img;
@@ -68,6 +70,9 @@ struct pfac_trie {
     double build_s = 0, upload_s = 0;
     std::map<uint32_t, pfac_tuning> tuned;  // by log2 size bucket
     std::mutex mu;
+    // size of the merged DAG, computed on the first stats call
+    mutable std::mutex dag_mu;
+    mutable uint64_t dag_nodes = kNoSize, dag_edges = 0;
 };
 
 struct pfac_workspace {
@@ -123,7 +128,13 @@ static int upload_image(pfac_trie *t) {
     size_t o_top = align256(o_qfp + std::max<size_t>(I.qfp.size(), 16) * 2);
     size_t o_tail = align256(o_top + std::max<size_t>(I.top.size(), 1) * 4);
     size_t o_tailb = align256(o_tail + std::max<size_t>(I.tail.size(), 4) * 4);
-    size_t total = align256(o_tailb + std::max<size_t>(I.tail_bytes.size(), 64));
+    size_t o_dnode = align256(o_tailb + std::max<size_t>(I.tail_bytes.size(), 64));
+    size_t o_dlabel = align256(o_dnode + std::max<size_t>(I.dnode.size(), 4) * 4);
+    size_t o_dchild = align256(o_dlabel + std::max<size_t>(I.dlabel.size(), 1) + 16);
+    size_t o_dradd = align256(o_dchild + std::max<size_t>(I.dchild.size(), 1) * 4);
+    size_t o_rlist = align256(o_dradd + std::max<size_t>(I.dradd.size(), 1) * 4);
+    size_t o_ldag = align256(o_rlist + std::max<size_t>(I.rank_list.size(), 2) * 4);
+    size_t total = align256(o_ldag + std::max<size_t>(I.lvl_dag.size(), 2) * 4);
     auto t0 = std::chrono::steady_clock::now();
     t->dev.release();
     HIP_TRY(t->dev.reserve(total));
@@ -155,6 +166,15 @@ static int upload_image(pfac_trie *t) {
         HIP_TRY(hipMemcpy(b + o_tail, I.tail.data(), I.tail.size() * 4, hipMemcpyHostToDevice));
     if (!I.tail_bytes.empty())
         HIP_TRY(hipMemcpy(b + o_tailb, I.tail_bytes.data(), I.tail_bytes.size(), hipMemcpyHostToDevice));
+    if (I.dag) {
+        HIP_TRY(hipMemcpy(b + o_dnode, I.dnode.data(), I.dnode.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b + o_dlabel, I.dlabel.data(), I.dlabel.size(), hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b + o_dchild, I.dchild.data(), I.dchild.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b + o_dradd, I.dradd.data(), I.dradd.size() * 4, hipMemcpyHostToDevice));
+        HIP_TRY(hipMemcpy(b + o_rlist, I.rank_list.data(), I.rank_list.size() * 4, hipMemcpyHostToDevice));
+        if (!I.lvl_dag.empty())
+            HIP_TRY(hipMemcpy(b + o_ldag, I.lvl_dag.data(), I.lvl_dag.size() * 4, hipMemcpyHostToDevice));
+    }
     ImageView &v = t->view;
     v.node = (const uint4 *)(b + o_node);
     v.label = b + o_label;
@@ -182,6 +202,13 @@ static int upload_image(pfac_trie *t) {
     v.top_rw = I.top_rw;
     v.tail = (const uint4 *)(b + o_tail);
     v.tail_bytes = b + o_tailb;
+    v.dnode = (const uint4 *)(b + o_dnode);
+    v.dlabel = b + o_dlabel;
+    v.dchild = (const uint32_t *)(b + o_dchild);
+    v.dradd = (const uint32_t *)(b + o_dradd);
+    v.rank_list = (const uint2 *)(b + o_rlist);
+    v.lvl_dag = (const uint2 *)(b + o_ldag);
+    v.dag = I.dag;
     v.fold_syms = I.fold_syms;
     v.K = I.K;
     v.b = I.b;
@@ -220,7 +247,8 @@ static int build_common(const uint8_t *data, const uint64_t *offsets, uint32_t k
             delete t;
             return PFAC_EINVAL;
         }
-        pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->tuning.trunc_depth, t->img);
+        pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->tuning.trunc_depth, t->tuning.dag,
+                       t->img);
     } catch (const std::bad_alloc &) {
         delete t;
         return PFAC_ENOMEM;
@@ -372,6 +400,15 @@ extern "C" int pfac_trie_stats(const pfac_trie *t, pfac_stats *o) {
     o->trunc_depth = t->img.trunc_depth;
     o->bytes_nodes = 4ull * t->img.node.size();
     o->bytes_tails = 4ull * t->img.tail.size() + t->img.tail_bytes.size();
+    {
+        // the merged DAG in CRS form: row pointers, labels, children, rank
+        // added per edge, terminal flags, and the k ids in string order
+        std::lock_guard<std::mutex> lock(t->dag_mu);
+        if (t->dag_nodes == kNoSize) dag_size(c, t->dag_nodes, t->dag_edges);
+        o->dag_nodes = t->dag_nodes;
+        o->dag_edges = t->dag_edges;
+        o->bytes_dag_crs = 4 * (t->dag_nodes + 1) + 9 * t->dag_edges + 4 * (t->dag_nodes + 1) + 4ull * c.k;
+    }
     return PFAC_OK;
 }
 
@@ -408,18 +445,20 @@ static bool valid_tuning(const pfac_tuning *p) {
            (p->waves_per_wg == 4 || p->waves_per_wg == 8 || p->waves_per_wg == 12 ||
             p->waves_per_wg == 16) &&
            p->chunks_per_unit >= 1 && p->chunks_per_unit <= 64 && p->child_check <= 2 &&
-           p->top_nodes <= 1 && p->trunc_depth <= 255;
+           p->top_nodes <= 1 && p->trunc_depth <= 255 && p->dag <= 1 &&
+           !(p->dag && (p->top_nodes || p->trunc_depth));
 }
 
 extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
     if (!t || !tn || !valid_tuning(tn)) return PFAC_EINVAL;
     const bool repack = tn->index_bits != t->tuning.index_bits || tn->fold_bits != t->tuning.fold_bits ||
-                        tn->trunc_depth != t->tuning.trunc_depth;
+                        tn->trunc_depth != t->tuning.trunc_depth || tn->dag != t->tuning.dag;
     const pfac_tuning old = t->tuning;
     t->tuning = *tn;
     if (repack) {
         try {
-            pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->tuning.trunc_depth, t->img);
+            pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->tuning.trunc_depth, t->tuning.dag,
+                       t->img);
         } catch (const std::bad_alloc &) {
             t->tuning = old;
             return PFAC_ENOMEM;
@@ -428,7 +467,8 @@ extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
     if (tn->kernel == 0 && tn->top_nodes && layout_for(t).lds_total > t->lds_limit) {
         // the bitmapped top nodes do not fit: keep the previous tuning
         t->tuning = old;
-        if (repack) pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->tuning.trunc_depth, t->img);
+        if (repack) pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->tuning.trunc_depth, t->tuning.dag,
+                       t->img);
         return PFAC_EINVAL;
     }
     if (repack && !t->host_only) return upload_image(t);
@@ -545,7 +585,7 @@ static hipError_t prep_wave(int mode, uint32_t bytes) { return prepare_wave_kern
 // Wave kernel when asked for and its LDS layout fits; the tile kernel otherwise.
 static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out) {
     if (t->tuning.kernel != 1 && t->tuning.kernel != 2) return false;
-    if (t->img.trunc_depth) return false;  // tail nodes: the tile kernel's walk only
+    if (t->img.trunc_depth || t->img.dag) return false;  // tails, DAG: the tile kernel's walk only
     if (t->crs.max_len > 0xffff) return false;  // walk limits are 16-bit
     const ScanArgs a = layout_for(t, waves_out);
     return a.lds_total <= t->lds_limit;
@@ -621,7 +661,7 @@ static int enqueue_scan(const Launch &L, bool reserve) {
         } else {
             const int slot = bpl == 4 ? 0 : bpl == 8 ? 1 : 2;
             if (a.lds_total > 64 * 1024) HIP_TRY(grant_lds(slot, a.lds_total, prep_tile, (int)bpl));
-            occ = max_wg_per_cu(bpl, a.lds_total, a.top_words != 0);
+            occ = max_wg_per_cu(bpl, a.lds_total, a.top_words ? 1 : a.im.dag ? 2 : 0);
             want = n_tiles;
         }
         if (per_cu == 0 || per_cu > occ) per_cu = occ;

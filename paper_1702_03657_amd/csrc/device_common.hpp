@@ -216,6 +216,54 @@ __device__ __forceinline__ uint2 walk(const ImageView &im, const uint8_t *gbase,
     return hit;
 }
 
+// Walk of the merged DAG from DAG node v at depth d with rank R so far: each
+// edge taken adds its rank, and the rank at the deepest terminal node passed
+// names the pattern string whose root-path pattern list is returned (length
+// 0: no pattern ends on the walk).
+__device__ __forceinline__ uint2 walk_dag(const ImageView &im, const uint8_t *gbase,
+                                          const Tile &T, uint32_t pl, uint32_t v, uint32_t R,
+                                          uint32_t d) {
+    uint32_t last = kNoneD;
+    for (;;) {
+        const uint4 r = im.dnode[v];
+        if (r.z & kTermFlagD) last = R;
+        const uint32_t nc = r.z & 0xffffu;
+        if (nc == 0) break;
+        const uint32_t q = pl + d;
+        uint32_t c;
+        if (q < T.win) {
+            // a boundary at q > pl starts the next text; at q == pl it starts this one
+            if (T.dirty && d != 0 && ((T.bnd[q >> 5] >> (q & 31)) & 1u)) break;
+            c = T.text[q];
+        } else {
+            const uint64_t g = T.lo + q;
+            if (g >= T.next_bnd) break;
+            c = gbase[g];
+        }
+        uint32_t j;
+        if (nc <= 4) {
+            const uint32_t x = r.x ^ (c * 0x01010101u);
+            const uint32_t m = (x - 0x01010101u) & ~x & 0x80808080u;  // lowest flag = first zero byte
+            if (m == 0) break;
+            j = (uint32_t)__builtin_ctz(m) >> 3;
+            if (j >= nc) break;
+        } else {
+            const uint8_t *lab = im.dlabel + r.y;
+            uint32_t lo = 0, hi = nc;
+            while (lo < hi) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (lab[mid] < c) lo = mid + 1; else hi = mid;
+            }
+            if (lo == nc || lab[lo] != c) break;
+            j = lo;
+        }
+        R += im.dradd[r.y + j];
+        v = im.dchild[r.y + j];
+        d++;
+    }
+    return last == kNoneD ? make_uint2(0, 0) : im.rank_list[last];
+}
+
 // Text holding frame position g (batch): the last text starting at or before
 // g, by binary search over the starts with the answer known to be in
 // [lo, hi).

@@ -30,7 +30,7 @@ namespace pfac {
 
 // ------------------------------------------------------------------- scan
 
-template <int BPL, bool IDENT, bool TOP>
+template <int BPL, bool IDENT, bool TOP, bool DAG>
 __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
     constexpr uint32_t TILE = kWG * BPL;
     extern __shared__ __align__(16) uint8_t lds[];
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
         for (uint32_t e = lane; e < qn; e += 64) {
             const uint32_t ent = wq[e];
             const uint32_t pl = ent >> 18;
-            uint32_t v = 0, d = 0;
+            uint32_t v = 0, d = 0, R = 0;
             if (K && top) {
                 v = im.lvl_start + (ent & 0x3ffffu);
                 d = K;
@@ -247,10 +247,18 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
                 const uint32_t code = ent & 0x3ffffu;
                 const uint32_t bits = s_bits[code >> 5];
                 const uint32_t below = bits & ((1u << (code & 31)) - 1u);
-                v = im.lvl_start + s_rank[code >> 5] + (uint32_t)__builtin_popcount(below);
+                const uint32_t rank = s_rank[code >> 5] + (uint32_t)__builtin_popcount(below);
+                if (DAG) {
+                    // the DAG node and the rank so far of this depth-K node
+                    const uint2 vr = im.lvl_dag[rank];
+                    v = vr.x;
+                    R = vr.y;
+                } else {
+                    v = im.lvl_start + rank;
+                }
                 d = K;
             }
-            const uint2 h = walk(im, a.base, T, pl, v, d);
+            const uint2 h = DAG ? walk_dag(im, a.base, T, pl, v, R, d) : walk(im, a.base, T, pl, v, d);
             if (h.y) {
                 const uint32_t slot = atomicAdd(&s_mn, 1u);
                 if (slot < kMatchCap) s_match[slot] = make_uint2(pl | (h.y << 16), h.x);
@@ -306,7 +314,7 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
                 const uint32_t pl = r * kWG + tid;
                 const uint64_t p = tile_lo + pl;
                 if (p < lo_valid || p >= hi_valid) continue;
-                const uint2 h = walk(im, a.base, T, pl, 0, 0);
+                const uint2 h = DAG ? walk_dag(im, a.base, T, pl, 0, 0, 0) : walk(im, a.base, T, pl, 0, 0);
                 if (h.y) mine += hit_list(im, h).y;
             }
             uint32_t total;
@@ -325,7 +333,7 @@ __global__ __launch_bounds__(kWG) void scan_tiles(const ScanArgs a) {
                 const uint64_t p = tile_lo + pl;
                 uint2 ids = make_uint2(0, 0);
                 if (p >= lo_valid && p < hi_valid) {
-                    const uint2 h = walk(im, a.base, T, pl, 0, 0);
+                    const uint2 h = DAG ? walk_dag(im, a.base, T, pl, 0, 0, 0) : walk(im, a.base, T, pl, 0, 0);
                     if (h.y) ids = hit_list(im, h);
                 }
                 const uint32_t c = ids.y;
@@ -470,9 +478,11 @@ void lds_layout(ScanArgs &a, uint32_t bpl) {
 template <int BPL, bool IDENT>
 static hipError_t launch_scan_t(const ScanArgs &a, uint32_t grid, hipStream_t s) {
     if (a.top_words)
-        hipLaunchKernelGGL((scan_tiles<BPL, IDENT, true>), dim3(grid), dim3(kWG), a.lds_total, s, a);
+        hipLaunchKernelGGL((scan_tiles<BPL, IDENT, true, false>), dim3(grid), dim3(kWG), a.lds_total, s, a);
+    else if (a.im.dag)
+        hipLaunchKernelGGL((scan_tiles<BPL, IDENT, false, true>), dim3(grid), dim3(kWG), a.lds_total, s, a);
     else
-        hipLaunchKernelGGL((scan_tiles<BPL, IDENT, false>), dim3(grid), dim3(kWG), a.lds_total, s, a);
+        hipLaunchKernelGGL((scan_tiles<BPL, IDENT, false, false>), dim3(grid), dim3(kWG), a.lds_total, s, a);
     return hipGetLastError();
 }
 
@@ -486,23 +496,26 @@ hipError_t launch_scan(const ScanArgs &a, uint32_t bpl, uint32_t grid, hipStream
     }
 }
 
+// variant 0: level index, 1: bitmapped top nodes, 2: level index + DAG walk
 template <int BPL, bool IDENT>
-static const void *scan_fn(bool top) {
-    return top ? (const void *)scan_tiles<BPL, IDENT, true> : (const void *)scan_tiles<BPL, IDENT, false>;
+static const void *scan_fn(int var) {
+    return var == 1 ? (const void *)scan_tiles<BPL, IDENT, true, false>
+         : var == 2 ? (const void *)scan_tiles<BPL, IDENT, false, true>
+                    : (const void *)scan_tiles<BPL, IDENT, false, false>;
 }
 
-static const void *scan_fn_for(uint32_t bpl, bool id, bool top) {
+static const void *scan_fn_for(uint32_t bpl, bool id, int var) {
     switch (bpl) {
-        case 4: return id ? scan_fn<4, true>(top) : scan_fn<4, false>(top);
-        case 8: return id ? scan_fn<8, true>(top) : scan_fn<8, false>(top);
-        case 16: return id ? scan_fn<16, true>(top) : scan_fn<16, false>(top);
+        case 4: return id ? scan_fn<4, true>(var) : scan_fn<4, false>(var);
+        case 8: return id ? scan_fn<8, true>(var) : scan_fn<8, false>(var);
+        case 16: return id ? scan_fn<16, true>(var) : scan_fn<16, false>(var);
         default: return nullptr;
     }
 }
 
 hipError_t prepare_kernels(uint32_t bpl, uint32_t lds_bytes) {
-    for (int v = 0; v < 4; v++) {
-        const void *fn = scan_fn_for(bpl, (v & 1) != 0, (v & 2) != 0);
+    for (int v = 0; v < 6; v++) {
+        const void *fn = scan_fn_for(bpl, (v & 1) != 0, v >> 1);
         if (!fn) return hipErrorInvalidValue;
         hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                            (int)lds_bytes);
@@ -511,9 +524,9 @@ hipError_t prepare_kernels(uint32_t bpl, uint32_t lds_bytes) {
     return hipSuccess;
 }
 
-int max_wg_per_cu(uint32_t bpl, uint32_t lds_bytes, bool top) {
+int max_wg_per_cu(uint32_t bpl, uint32_t lds_bytes, int var) {
     int n = 0;
-    const void *fn = scan_fn_for(bpl, true, top);
+    const void *fn = scan_fn_for(bpl, true, var);
     if (!fn) return 1;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, fn, kWG, lds_bytes) != hipSuccess || n < 1)
         n = 1;

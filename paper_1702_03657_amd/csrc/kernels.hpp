@@ -34,6 +34,13 @@ struct ImageView {
     const uint32_t *top;      // bitmapped nodes of depths 0 .. K-1: top_rw words each
     const uint4 *tail;        // truncated image: tail entries (byte offset, length, list)
     const uint8_t *tail_bytes;
+    const uint4 *dnode;       // merged image: DAG nodes (labels4, first edge, nc | term, 0)
+    const uint8_t *dlabel;    // per DAG edge: label, child, rank added
+    const uint32_t *dchild;
+    const uint32_t *dradd;
+    const uint2 *rank_list;   // per distinct pattern string: root-path pattern list
+    const uint2 *lvl_dag;     // per depth-K node of the level index: DAG node, rank so far
+    uint32_t dag;
     uint32_t K, b, identity, lvl_words;
     uint32_t lvl_start, max_len, n_nodes, fold_syms;
     uint32_t pfx4_log2, pfx4_mul;     // prefix-4 filter: 2^pfx4_log2 bits, hash multiplier
@@ -129,7 +136,7 @@ hipError_t launch_walk_units(const ScanArgs &a, hipStream_t s);
 int max_wave_wg_per_cu(const ScanArgs &a, uint32_t waves);
 
 // Largest resident workgroups per CU for this layout.
-int max_wg_per_cu(uint32_t bpl, uint32_t lds_bytes, bool top);
+int max_wg_per_cu(uint32_t bpl, uint32_t lds_bytes, int var);  // var: 0 level index, 1 top nodes, 2 DAG
 hipError_t prepare_kernels(uint32_t bpl, uint32_t lds_bytes);
 
 }  // namespace pfac

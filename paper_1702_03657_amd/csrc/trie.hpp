@@ -81,6 +81,16 @@ struct DeviceImageHost {
     uint32_t trunc_depth = 0;
     std::vector<uint32_t> tail;
     std::vector<uint8_t> tail_bytes;
+    // Merged image (dag = 1): the trie's equal subtries shared as one DAG
+    // node.  dnode per node: labels of the first four edges, first edge,
+    // nc | kTermFlag, 0; per edge: label, child DAG node, rank added.
+    // rank_list[2r], [2r+1]: root-path pattern list (offset, stored length) of
+    // the r-th distinct pattern string in sorted order; lvl_dag[2i], [2i+1]:
+    // DAG node and rank so far of the level index's i-th depth-K node.
+    uint32_t dag = 0;
+    std::vector<uint32_t> dnode;
+    std::vector<uint8_t> dlabel;
+    std::vector<uint32_t> dchild, dradd, rank_list, lvl_dag;
     uint32_t alphabet = 0;
     uint32_t n_term = 0;
     // Prefix filter of the wave kernel.  With K >= 1 it is a table of E-bit
@@ -129,6 +139,8 @@ constexpr uint32_t kPfx4Mul = 0x9E3779B1u;
 // `index_bits` bits and a prefix filter of `fold_bits` (0, 8 or 16) bits per
 // entry.
 void pack_image(const CrsTrie &t, uint32_t index_bits, uint32_t fold_bits, uint32_t trunc_depth,
-                DeviceImageHost &img);
+                uint32_t dag, DeviceImageHost &img);
+// Nodes and edges of the trie with equal subtries merged (the DAG of pack_image's dag = 1).
+void dag_size(const CrsTrie &t, uint64_t &nodes, uint64_t &edges);
 
 }  // namespace pfac

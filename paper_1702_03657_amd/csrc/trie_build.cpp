@@ -10,6 +10,8 @@
 #include <algorithm>
 #include <cstring>
 #include <numeric>
+#include <string>
+#include <unordered_map>
 
 #include "trie.hpp"
 
@@ -89,8 +91,8 @@ static uint32_t ceil_log2(uint32_t x) {
     return b;
 }
 
-void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits, uint32_t trunc_depth,
-                DeviceImageHost &I) {
+static void pack_core(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits, uint32_t trunc_depth,
+                      DeviceImageHost &I) {
     I = DeviceImageHost{};
     const uint32_t N = T.n_nodes();
     const uint32_t E = T.n_edges();
@@ -435,6 +437,138 @@ void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits, uint3
         else
             reinterpret_cast<uint16_t *>(I.ftab.data())[code] |= (uint16_t)(1u << bit);
     }
+}
+
+// Suffix and end-node merging (Design and Implementation, steps IV and V):
+// trie nodes whose subtries are equal (same terminal flag, same labels to
+// equal subtries) become one DAG node, so all leaves become a single end node
+// and equal suffixes are stored once.  Pattern identities survive on the
+// edges: each edge adds the number of distinct pattern strings that sort
+// before its subtrie among its parent's (the parent's own string, then the
+// subtries of smaller labels), so a walk sums to the rank of the string it
+// spells, and rank_list[rank] gives that string's root-path pattern list.
+// Equivalence classes of trie nodes (equal subtries), children first
+// (breadth-first ids: children are larger); per class a trie node of it and
+// the number of distinct pattern strings in its subtrie.
+static void dag_classes(const CrsTrie &T, std::vector<uint32_t> &cls, std::vector<uint32_t> &cls_rep,
+                        std::vector<uint32_t> &cls_strings) {
+    const uint32_t N = T.n_nodes();
+    auto term = [&](uint32_t v) -> uint32_t { return T.term_ptr[v + 1] > T.term_ptr[v] ? 1u : 0u; };
+    cls.assign(N, 0);
+    cls_rep.clear();
+    cls_strings.clear();
+    std::unordered_map<std::string, uint32_t> seen;
+    seen.reserve(N);
+    std::string key;
+    for (uint32_t v = N; v-- > 0;) {
+        key.assign(1, (char)term(v));
+        uint32_t strings = term(v);
+        for (uint32_t e = T.row_ptr[v]; e < T.row_ptr[v + 1]; e++) {
+            const uint32_t c = cls[e + 1];
+            key.push_back((char)T.labels[e]);
+            key.append((const char *)&c, 4);
+            strings += cls_strings[c];
+        }
+        auto it = seen.find(key);
+        if (it == seen.end()) {
+            const uint32_t id = (uint32_t)cls_rep.size();
+            seen.emplace(key, id);
+            cls_rep.push_back(v);
+            cls_strings.push_back(strings);
+            cls[v] = id;
+        } else {
+            cls[v] = it->second;
+        }
+    }
+}
+
+void dag_size(const CrsTrie &T, uint64_t &nodes, uint64_t &edges) {
+    std::vector<uint32_t> cls, rep, strings;
+    dag_classes(T, cls, rep, strings);
+    nodes = rep.size();
+    edges = 0;
+    for (uint32_t v : rep) edges += T.row_ptr[v + 1] - T.row_ptr[v];
+}
+
+static void build_dag(const CrsTrie &T, DeviceImageHost &I) {
+    const uint32_t N = T.n_nodes();
+    auto term = [&](uint32_t v) -> uint32_t { return T.term_ptr[v + 1] > T.term_ptr[v] ? 1u : 0u; };
+    std::vector<uint32_t> cls, cls_rep, cls_strings;
+    dag_classes(T, cls, cls_rep, cls_strings);
+    // DAG nodes numbered breadth first from the root's class
+    std::vector<uint32_t> newid(cls_rep.size(), kNone), order;
+    newid[cls[0]] = 0;
+    order.push_back(cls[0]);
+    for (size_t i = 0; i < order.size(); i++) {
+        const uint32_t v = cls_rep[order[i]];
+        for (uint32_t e = T.row_ptr[v]; e < T.row_ptr[v + 1]; e++) {
+            const uint32_t c = cls[e + 1];
+            if (newid[c] == kNone) {
+                newid[c] = (uint32_t)order.size();
+                order.push_back(c);
+            }
+        }
+    }
+    I.dag = 1;
+    I.dnode.assign(4 * order.size(), 0);
+    I.dlabel.clear();
+    I.dchild.clear();
+    I.dradd.clear();
+    for (size_t i = 0; i < order.size(); i++) {
+        const uint32_t v = cls_rep[order[i]];
+        const uint32_t e0 = T.row_ptr[v], nc = T.row_ptr[v + 1] - e0;
+        uint32_t x = 0;
+        for (uint32_t j = 0; j < 4; j++) x |= (uint32_t)(nc ? T.labels[e0 + std::min(j, nc - 1)] : 0) << (8 * j);
+        I.dnode[4 * i + 0] = x;
+        I.dnode[4 * i + 1] = (uint32_t)I.dlabel.size();
+        I.dnode[4 * i + 2] = nc | (term(v) ? kTermFlag : 0u);
+        uint32_t run = term(v);
+        for (uint32_t e = e0; e < e0 + nc; e++) {
+            I.dlabel.push_back(T.labels[e]);
+            I.dchild.push_back(newid[cls[e + 1]]);
+            I.dradd.push_back(run);
+            run += cls_strings[cls[e + 1]];
+        }
+    }
+    // rank of every trie node's string (parents before children)
+    std::vector<uint32_t> R(N, 0);
+    for (uint32_t v = 0; v < N; v++) {
+        uint32_t run = R[v] + term(v);
+        for (uint32_t e = T.row_ptr[v]; e < T.row_ptr[v + 1]; e++) {
+            R[e + 1] = run;
+            run += cls_strings[cls[e + 1]];
+        }
+    }
+    const uint32_t S = N ? cls_strings[cls[0]] : 0;
+    I.rank_list.assign(2ull * std::max(S, 1u), 0);
+    for (uint32_t v = 0; v < N; v++) {
+        if (!term(v)) continue;
+        I.rank_list[2ull * R[v]] = I.node[4ull * v + 3];
+        I.rank_list[2ull * R[v] + 1] = I.node[4ull * v + 2] >> kCountShift;
+    }
+    // the level index's depth-K nodes as (DAG node, rank so far)
+    I.lvl_dag.clear();
+    if (I.K) {
+        for (uint32_t v = T.level_start[I.K]; v < T.level_start[I.K + 1]; v++) {
+            I.lvl_dag.push_back(newid[cls[v]]);
+            I.lvl_dag.push_back(R[v]);
+        }
+    }
+    if (I.dlabel.empty()) {
+        I.dlabel.push_back(0);
+        I.dchild.push_back(0);
+        I.dradd.push_back(0);
+    }
+    // the trie's own node records are not read by the DAG walk
+    I.node.assign(4, 0);
+    I.label.assign(1, 0);
+    I.chain.assign(40, 0);
+}
+
+void pack_image(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits, uint32_t trunc_depth,
+                uint32_t dag, DeviceImageHost &I) {
+    pack_core(T, index_bits, fold_bits, dag ? 0u : trunc_depth, I);
+    if (dag) build_dag(T, I);
 }
 
 }  // namespace pfac

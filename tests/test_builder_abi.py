@@ -238,3 +238,53 @@ def test_truncated_image_sizes():
     with pytest.raises(pf.PfacError):
         t.set_tuning(trunc_depth=256)
     t.close()
+
+
+def _dag_size_reference(pats):
+    """Nodes and edges of the trie with equal subtries merged, from a plain
+    dict trie: a subtrie is named by (terminal?, sorted (label, child name))."""
+    root = {}
+    for p in pats:
+        node = root
+        for c in p:
+            node = node.setdefault(c, {})
+        node[None] = True
+    names = {}
+
+    def name(node):
+        key = (None in node, tuple((c, name(ch)) for c, ch in sorted(
+            (c, ch) for c, ch in node.items() if c is not None)))
+        return names.setdefault(key, len(names))
+
+    name(root)
+    return len(names), sum(len(k[1]) for k in names)
+
+
+def test_merged_dag_sizes():
+    """Suffix and end-node merging: closed forms (all strings of length L over
+    s symbols: L + 1 nodes, s * L edges; a single pattern stays a chain) and a
+    dict-trie reference on random sets with shared suffixes and duplicates."""
+    import itertools
+    pats = [bytes(t) for t in itertools.product(b"ACGT", repeat=5)]
+    st = pf.Trie(pats, host_only=True).stats()
+    assert st["nodes"] == sum(4 ** d for d in range(6))
+    assert (st["dag_nodes"], st["dag_edges"]) == (6, 4 * 5)
+    st = pf.Trie([b"abcdef"], host_only=True).stats()
+    assert (st["dag_nodes"], st["dag_edges"]) == (7, 6)
+    rng = np.random.default_rng(11)
+    for trial in range(5):
+        suf = [bytes(rng.integers(97, 100, int(n)).astype(np.uint8)) for n in rng.integers(1, 6, 20)]
+        pats = [bytes(rng.integers(97, 101, int(n)).astype(np.uint8)) + suf[int(rng.integers(0, 20))]
+                for n in rng.integers(0, 6, 300)]
+        pats += pats[:10]  # duplicates
+        st = pf.Trie(pats, host_only=True).stats()
+        assert (st["dag_nodes"], st["dag_edges"]) == _dag_size_reference(pats), trial
+        assert st["bytes_dag_crs"] == 8 * (st["dag_nodes"] + 1) + 9 * st["dag_edges"] + 4 * len(pats)
+    t = pf.Trie([b"ab", b"cb"], host_only=True)
+    with pytest.raises(pf.PfacError):
+        t.set_tuning(dag=1, top_nodes=1)
+    with pytest.raises(pf.PfacError):
+        t.set_tuning(dag=1, trunc_depth=1)
+    t.set_tuning(dag=1)
+    assert t.stats()["scan_kernel"] == 0
+    t.close()

@@ -168,7 +168,7 @@ def test_misaligned_text_addresses(pad):
     assert np.array_equal(counts, oracle.counts(wl.text.size, want))
 
 
-@pytest.mark.parametrize("kernel", [0, 1, 2, "0t", "0d"])
+@pytest.mark.parametrize("kernel", [0, 1, 2, "0t", "0d", "0g"])
 @pytest.mark.parametrize("case", [
     "empty_text", "short_text", "no_patterns", "length_one", "duplicates", "nested_runs",
     "all_windows", "sigma1_long", "long_patterns", "match_at_end", "dense_candidates",
@@ -215,6 +215,8 @@ def test_edge_cases(case, kernel):
         trie.set_tuning(kernel=0, index_bits=8, top_nodes=1)
     elif kernel == "0d":  # image truncated at depth 2, tails verified
         trie.set_tuning(kernel=0, trunc_depth=2)
+    elif kernel == "0g":  # merged DAG image, ranks on the edges
+        trie.set_tuning(kernel=0, dag=1)
     else:
         trie.set_tuning(kernel=kernel)
     say(f"edge {case} kernel {kernel}: n={text.size} k={len(pats)} K={trie.stats()['index_depth']}")
@@ -255,6 +257,32 @@ def test_truncated_images(name):
             assert_same(got, want, with_text=True)
         else:
             got, counts = gpu_scan(trie, wl.text, pad_front=D % 16)
+            assert_same(got, want)
+            assert np.array_equal(counts, oracle.counts(wl.text.size, want))
+
+
+@pytest.mark.parametrize("name", sorted(TRUNC_CASES))
+def test_merged_dag_images(name):
+    """The merged DAG image (equal subtries shared, pattern ids recovered
+    from the ranks on the edges) gives the oracle's list at several level
+    index depths and tile sizes, single texts and batches."""
+    wl = TRUNC_CASES[name]()
+    offs = wl.offsets.astype(np.uint64)
+    batch = len(offs) > 2
+    want = oracle.bucketed(wl.text, wl.patterns, offsets=wl.offsets if batch else None, threads=8)
+    trie = pf.Trie(wl.patterns)
+    full = trie.stats()
+    for bits, bpl in ((1, 16), (8, 4), (16, 16), (18, 8)):
+        trie.set_tuning(kernel=0, dag=1, index_bits=bits, bytes_per_lane=bpl)
+        st = trie.stats()
+        say(f"dag {name} bits={bits} bpl={bpl}: K={st['index_depth']} dag nodes {st['dag_nodes']} "
+            f"of {full['nodes']}, image {st['bytes_device']} vs {full['bytes_device']}")
+        if batch:
+            got, n = gpu_scan_batch(trie, wl.text, offs)
+            assert n == want.n
+            assert_same(got, want, with_text=True)
+        else:
+            got, counts = gpu_scan(trie, wl.text, pad_front=bits % 16)
             assert_same(got, want)
             assert np.array_equal(counts, oracle.counts(wl.text.size, want))
 

@@ -2,7 +2,7 @@
 alphabets of 2 to 256 bytes, pattern lengths that do and do not reach the
 filters' minimum lengths, planted copies and partial copies, scanned by the
 tile kernel (first levels through the level index or the bitmapped nodes,
-whole or truncated image),
+whole, truncated or merged into a DAG),
 the fused wave kernel and the split wave kernels (with each of their second
 filter stages), single and batched, each against the oracle's
 brute force."""
@@ -49,7 +49,8 @@ def _case(seed):
 TUNINGS = [dict(kernel=0), dict(kernel=1, child_check=1), dict(kernel=2, child_check=0),
            dict(kernel=2, child_check=1), dict(kernel=2, child_check=2, chunks_per_unit=4),
            dict(kernel=0, index_bits=8, top_nodes=1),
-           dict(kernel=0, index_bits=16, top_nodes=0, trunc_depth=3)]
+           dict(kernel=0, index_bits=16, top_nodes=0, trunc_depth=3),
+           dict(kernel=0, index_bits=16, top_nodes=0, trunc_depth=0, dag=1)]
 
 
 @pytest.mark.parametrize("seed", range(20))
