@@ -352,13 +352,18 @@ def test_batch_long_patterns_small_texts(tuning):
     assert_same(got, want, with_text=True)
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+GRAPH_TUNINGS = {"1": dict(kernel=1), "2": dict(kernel=2), "0": dict(kernel=0),
+                 "0t": dict(kernel=0, index_bits=8, top_nodes=1), "0d": dict(kernel=0, trunc_depth=6),
+                 "0g": dict(kernel=0, dag=1)}
+
+
+@pytest.mark.parametrize("kernel", sorted(GRAPH_TUNINGS))
 def test_batch_graph_replays_are_identical(kernel):
     rng = np.random.default_rng(9)
     wl = workloads.c4_batched(n_small=2000, n_large=3, large_lo=1 << 16, large_hi=1 << 18,
                               k=2000, rate=1 / 512)
     trie = pf.Trie(wl.patterns)
-    trie.set_tuning(kernel=kernel)
+    trie.set_tuning(**GRAPH_TUNINGS[kernel])
     want = oracle.bucketed(wl.text, wl.patterns, offsets=wl.offsets, threads=8)
     say(f"graph: {wl.n_texts} texts {wl.text.size} bytes, {want.n} matches")
     results, n = gpu_scan_batch(trie, wl.text, wl.offsets, graph_replays=4)

@@ -49,12 +49,16 @@ def _server(trie, budget, arena, max_batch):
     return pf.Server(trie, buf, budget, max_batch, cs, xs), buf
 
 
-@pytest.mark.parametrize("kernel", [1, 2])
+SERVER_TUNINGS = {"1": dict(kernel=1), "2": dict(kernel=2), "0d": dict(kernel=0, trunc_depth=8),
+                  "0g": dict(kernel=0, dag=1)}
+
+
+@pytest.mark.parametrize("kernel", sorted(SERVER_TUNINGS))
 def test_mix_equals_alone(kernel):
     pats = workloads.make_patterns(np.random.default_rng(5), 2000, 8, 64, "uniform")
     texts = _requests(11, 48, 1024, 512 * 1024, pats)
     trie = pf.Trie(pats)
-    trie.set_tuning(kernel=kernel)
+    trie.set_tuning(**SERVER_TUNINGS[kernel])
     budget = 2 << 20  # smaller than the sum: several batches and ring wrap-around
     srv, _buf = _server(trie, budget, budget + (16 << 20), 16)
     say(f"server kernel {kernel}: {len(texts)} requests, {sum(t.size for t in texts)} bytes")
