@@ -10,14 +10,19 @@ text and the trie already resident in HBM.  Prints one JSON line:
   library around it on the launch stream, against the MI355X HBM peak;
   ``traffic`` comes from committed rocprofv3 FETCH_SIZE / WRITE_SIZE counts
   when they were taken on the current kernel source;
-* ``cpu_baseline``: the oracle's bucketed matcher on the machine's host cores.
+* ``cpu_baseline``: the oracle's bucketed matcher on the machine's host cores
+  (with the textbook Aho-Corasick automaton's rate beside it);
+* ``ms_per_step_median`` / ``_min`` over the timed steps, and the timed
+  kernel's rate against a measured read-only streaming probe as well as the
+  HBM peak.
 
 Workloads (seeded synthetic data, see synth/workloads.py): ``c2`` (default,
 10,000 patterns of 8-64 bytes, 70% printable bytes, 256 MiB text), ``c1``,
 ``c3`` (1 GiB DNA text, 100,000 patterns).  The line also carries the batched
 vs plain per-text comparison (c4: 65,600 texts in one graph-captured launch
 against one launch per text) and the serving loop's p50/p99 latency against
-one request at a time (c5); ``--no-extras`` / ``--no-serving`` leave them out.
+one request at a time (c5, offered at 0.5 / 0.8 / 0.95 of the measured
+capacity); ``--no-extras`` / ``--no-serving`` leave them out.
 
 ``--placement c1,c2,...`` prints instead one line with the trie-placement
 ablation: the tile kernel with 0, 1, 2, ... trie levels resolved in LDS by
@@ -123,15 +128,49 @@ def traffic_from_profiles(kernel, workload, tuning):
     return d.get("hbm_bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(oracle, wl, threads):
-    """Bucketed oracle over the whole text on `threads` host threads."""
+    """Bucketed oracle over the whole text on `threads` host threads, and the
+    textbook Aho-Corasick automaton (one thread per contiguous range of start
+    positions) beside it."""
     tm = [0.0, 0.0]
     m = oracle.bucketed(wl.text, wl.patterns, threads=threads, timing=tm)
     gbps = wl.text.size * 8 / tm[1] / 1e9
+    ta = [0.0, 0.0]
+    ac = oracle.aho_corasick(wl.text, wl.patterns, threads=threads, timing=ta)
     return {"value": round(gbps, 3), "unit": "Gbit/s", "cores": threads, "kind": "oracle",
             "sample": f"bucketed matcher (first-min(len,8)-byte index + memcmp) over the whole "
                       f"{wl.text.size} B text; index build {tm[0]:.3f}s excluded; "
-                      f"{m.n} matches"}, m
+                      f"{m.n} matches",
+            "nproc": os.cpu_count(), "cpu_model": cpu_model(),
+            "aho_corasick_gbit_s": round(wl.text.size * 8 / ta[1] / 1e9, 3),
+            "aho_corasick_same_matches": bool(ac.n == m.n)}, m
+
+
+def streaming_probe(torch, text, reps=10):
+    """Read-only streaming rate of the box: torch's float32 sum over the text's
+    bytes read as float32 words (the values do not matter, only the reads)."""
+    x = text[: (text.numel() // 4) * 4].view(torch.float32)
+    for _ in range(2):
+        x.sum()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        x.sum()
+    e1.record()
+    torch.cuda.synchronize()
+    return x.numel() * 4 / (e0.elapsed_time(e1) / reps / 1e3) / 1e9
 
 
 def run_copy_probe(torch, nbytes):
@@ -237,10 +276,13 @@ def _percentiles(lat_s):
     return round(float(np.percentile(a, 50)), 3), round(float(np.percentile(a, 99)), 3)
 
 
-def extras_serving(pf, torch, n_requests, rates, budget_bytes):
-    """C5: Poisson arrivals at fixed offered rates into the continuous-batching
-    server, against one request at a time (copy in, scan, copy out, next) on
-    the same arrival trace."""
+def extras_serving(pf, torch, n_requests, rates, budget_bytes, rhos=(0.5, 0.8, 0.95)):
+    """C5: Poisson arrivals into the continuous-batching server, against one
+    request at a time (copy in, scan, copy out, next) on the same arrival
+    trace.  The offered rates are `rates` (requests/s) when given, else the
+    fractions `rhos` of the measured capacity (host-to-device copy plus one
+    batched scan of every request).  Latency percentiles leave out the first
+    5% of the requests."""
     import threading
 
     import numpy as np
@@ -280,6 +322,32 @@ def extras_serving(pf, torch, n_requests, rates, budget_bytes):
             if n:
                 out_host[:16 * min(n, cap)].copy_(out[:16 * min(n, cap)])
         return n
+
+    # capacity: every request body copied in, then scanned as one batch
+    allreq = torch.empty(total + 16, dtype=torch.uint8, device="cuda")
+    offs_dev = torch.from_numpy(offs.astype(np.int64)).cuda()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    cap_b = 1 << 23
+    out_b = torch.empty(cap_b * 16, dtype=torch.uint8, device="cuda")
+    ws_b = pf.Workspace()
+    with torch.cuda.stream(stream):
+        for rep in range(2):  # the second pass is the measured one
+            e0.record(stream)
+            allreq[:total].copy_(host, non_blocking=True)
+            e1.record(stream)
+            pf.pfac_scan_batch(trie, ws_b, allreq, offs_dev, n_requests, total, out_b, cap_b, cnt, stream)
+            e2.record(stream)
+            stream.synchronize()
+    h2d_s, scan_s = e0.elapsed_time(e1) / 1e3, e1.elapsed_time(e2) / 1e3
+    capacity = total / (h2d_s + scan_s)  # bytes per second
+    res["capacity"] = {"h2d_gbit_s": round(total * 8 / h2d_s / 1e9, 2),
+                       "batched_scan_gbit_s": round(total * 8 / scan_s / 1e9, 2),
+                       "capacity_gbit_s": round(capacity * 8 / 1e9, 2)}
+    del allreq, out_b
+    ws_b.close()
+    if not rates:
+        rates = [round(r * capacity / float(sizes.mean()), 1) for r in rhos]
+        res["rho"] = list(rhos)
 
     # the server
     arena = torch.empty(budget_bytes + (256 << 20), dtype=torch.uint8, device="cuda")
@@ -324,8 +392,9 @@ def extras_serving(pf, torch, n_requests, rates, budget_bytes):
             ready.release()
         th.join()
         end_srv = time.perf_counter() - start
-        p50b, p99b = _percentiles(lat_base)
-        p50s, p99s = _percentiles(lat_srv)
+        skip = n_requests // 20  # warm-up requests left out of the percentiles
+        p50b, p99b = _percentiles(lat_base[skip:])
+        p50s, p99s = _percentiles(lat_srv[skip:])
         res["points"].append({
             "offered_req_s": rate,
             "offered_gbit_s": round(sizes.mean() * 8 * rate / 1e9, 2),
@@ -533,8 +602,11 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving loop (c5) against one request at a time")
     ap.add_argument("--serving-requests", type=int, default=200)
-    ap.add_argument("--serving-rates", default="1000,4000,8000",
-                    help="offered requests per second, one measurement per rate")
+    ap.add_argument("--serving-rates", default=None,
+                    help="offered requests per second, one measurement per rate (default: the "
+                         "--serving-rho fractions of the measured capacity)")
+    ap.add_argument("--serving-rho", default="0.5,0.8,0.95",
+                    help="offered load as fractions of the measured capacity")
     ap.add_argument("--serving-budget", type=int, default=1 << 30, help="HBM bytes for request texts")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain copy of the text size (counter calibration)")
@@ -625,14 +697,16 @@ def main():
     for a, b in kev:  # creates the HIP events; the library re-records them around the kernel
         a.record(stream)
         b.record(stream)
-    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    s0, s1 = sev[0], sev[-1]
     torch.cuda.synchronize()
     s0.record(stream)
     for i in range(args.steps):
         ws.set_timing(kev[i][0], kev[i][1])
         pf.pfac_scan(trie, ws, text, n, out, cap, cnt, None, stream)
-    s1.record(stream)
+        sev[i + 1].record(stream)
     torch.cuda.synchronize()
+    step_ms = [sev[i].elapsed_time(sev[i + 1]) for i in range(args.steps)]
     ws.set_timing(None, None)
     total_ms = s0.elapsed_time(s1)
     ms_per_step = total_ms / args.steps
@@ -655,6 +729,7 @@ def main():
 
     if args.copy_probe:
         run_copy_probe(torch, n)
+    probe = streaming_probe(torch, text)
 
     line = {
         "metric": "Gbit/s scanned on 1 MI355X (plain PFAC scan, text resident in HBM)",
@@ -664,6 +739,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step_median": round(statistics.median(step_ms), 5),
+        "ms_per_step_min": round(min(step_ms), 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -691,6 +768,8 @@ def main():
             "kernel_source_sha256_16": kernel_hash(kernel_name),
             "kernel_ms": round(kernel_ms, 5),
             "algorithmic_bytes_per_launch": alg_bytes,
+            "streaming_probe_gb_s": round(probe, 1),
+            "frac_of_probe": round(achieved / probe, 4),
         },
         "h2d_gbit_s": round(n * 8 / (h2d_ms / 1e3) / 1e9, 2),
         "trie": {
@@ -717,9 +796,10 @@ def main():
             pf, torch, max(3, args.steps // 5),
             0 if args.no_cpu_baseline else (args.cpu_threads or min(16, os.cpu_count() or 1)))
     if not args.no_serving:
-        line["serving"] = extras_serving(pf, torch, args.serving_requests,
-                                         [float(x) for x in args.serving_rates.split(",")],
-                                         args.serving_budget)
+        line["serving"] = extras_serving(
+            pf, torch, args.serving_requests,
+            [float(x) for x in args.serving_rates.split(",")] if args.serving_rates else None,
+            args.serving_budget, [float(x) for x in args.serving_rho.split(",")])
 
     print(json.dumps(line), flush=True)
 
