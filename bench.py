@@ -110,9 +110,10 @@ def choose_tuning(pf, trie, ws, text_dev, n, workload, device_name, retune):
     return best, True
 
 
-def traffic_from_profiles(kernel, workload, tuning):
-    """HBM bytes per scan-kernel launch from committed counter summaries, when
-    they were taken on the current source of that kernel with the same tuning."""
+def profile_counts(kernel, workload, tuning):
+    """Committed counter summary of a scan kernel (HBM bytes, VALU
+    instructions per launch), when it was taken on the current source of that
+    kernel with the same tuning; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -125,7 +126,7 @@ def traffic_from_profiles(kernel, workload, tuning):
         return None  # the kernel changed since the counters were taken
     if d.get("tuning") != {k: int(v) for k, v in tuning.items()}:
         return None  # taken with another launch configuration
-    return d.get("hbm_bytes_per_launch")
+    return d
 
 
 def cpu_model():
@@ -725,7 +726,16 @@ def main():
     alg_bytes = n + image_bytes + (0 if split else 16 * n_matches)
     achieved = alg_bytes / (kernel_ms / 1e3) / 1e9
     kernel_name = "scan_waves" if int(st["scan_kernel"]) in (1, 2) else "scan_tiles"
-    traffic = traffic_from_profiles(kernel_name, args.workload, tuning)
+    counts = profile_counts(kernel_name, args.workload, tuning)
+    traffic = counts.get("hbm_bytes_per_launch") if counts else None
+    # the filter's other ceiling: VALU issue (wave64 instructions, 4 cycles
+    # each on one of 4 SIMDs per CU: CUs * 2.4 GHz per second)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    issue = None
+    if counts and counts.get("valu_insts_per_launch"):
+        issue_ms = counts["valu_insts_per_launch"] / (n_cu * 2.4e9) * 1e3
+        issue = {"valu_insts_per_launch": counts["valu_insts_per_launch"], "cus": n_cu,
+                 "issue_bound_ms": round(issue_ms, 5), "frac": round(issue_ms / kernel_ms, 4)}
 
     if args.copy_probe:
         run_copy_probe(torch, n)
@@ -770,6 +780,7 @@ def main():
             "algorithmic_bytes_per_launch": alg_bytes,
             "streaming_probe_gb_s": round(probe, 1),
             "frac_of_probe": round(achieved / probe, 4),
+            "valu_issue": issue,
         },
         "h2d_gbit_s": round(n * 8 / (h2d_ms / 1e3) / 1e9, 2),
         "trie": {
