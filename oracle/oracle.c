@@ -448,9 +448,11 @@ void *orc_match(int algo, const uint8_t *text, const uint64_t *toff, uint32_t n_
     } else {
         uint64_t w = 0;
         for (uint64_t q = 0; q < n_items; q++) {
-            memcpy(res->all.pos + w, lists[q].pos, lists[q].n * sizeof(uint64_t));
-            memcpy(res->all.id + w, lists[q].id, lists[q].n * sizeof(uint32_t));
-            memcpy(res->all.tid + w, lists[q].tid, lists[q].n * sizeof(uint32_t));
+            if (lists[q].n) {  /* an empty list may hold no buffers at all */
+                memcpy(res->all.pos + w, lists[q].pos, lists[q].n * sizeof(uint64_t));
+                memcpy(res->all.id + w, lists[q].id, lists[q].n * sizeof(uint32_t));
+                memcpy(res->all.tid + w, lists[q].tid, lists[q].n * sizeof(uint32_t));
+            }
             w += lists[q].n;
             ol_free(&lists[q]);
         }
