@@ -652,10 +652,11 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                 // key of position j = bits [2j, 2j + 32), one LDS word of the
                 // filter per position, two bits of it tested.
                 const uint32_t qa = im.qa, qb = im.qb;
+                // 2-bit symbols of the four bytes of x in one byte: a dot
+                // product of the per-byte symbols with weights 1, 4, 16, 64
                 auto pack4 = [&](uint32_t x) -> uint32_t {
                     const uint32_t t = ((x >> qa) ^ (x >> qb)) & 0x03030303u;
-                    const uint32_t u = t | (t >> 6);
-                    return (u | (u >> 12)) & 0xffu;
+                    return __builtin_amdgcn_udot4(t, 0x40100401u, 0u, false);
                 };
                 const uint32_t P0 = pack4(w[0]) | pack4(w[1]) << 8 | pack4(w[2]) << 16 | pack4(w[3]) << 24;
                 const uint32_t P1 = pack4(w[4]) | pack4(w[5]) << 8 | pack4(w[6]) << 16 | pack4(w[7]) << 24;
@@ -719,8 +720,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                                     const uint32_t x = __builtin_amdgcn_alignbyte(d[k + 1], d[k], pl & 3u);
                                     const uint32_t t = ((x >> qa) ^ (x >> qb)) & 0x03030303u;
                                     valid = valid && __builtin_amdgcn_perm(0u, im.qalph, t) == x;
-                                    const uint32_t u = t | (t >> 6);
-                                    key |= ((u | (u >> 12)) & 0xffu) << (8 * k);
+                                    key |= __builtin_amdgcn_udot4(t, 0x40100401u, 0u, false) << (8 * k);
                                 }
                                 pass2 = valid;
                             }
