@@ -25,10 +25,12 @@
  *     unless their name ends in _sync.
  *   - The caller owns every buffer it passes; the library owns the objects
  *     it returns until the matching *_free call.
- *   - A trie is immutable after pfac_build and may be shared by many streams
- *     and threads.  A workspace serializes: calls that share a workspace must
- *     be issued on one stream (or otherwise ordered); calls on different
- *     workspaces may overlap.
+ *   - A trie changes only through pfac_trie_set_tuning and pfac_autotune,
+ *     which may rebuild and re-upload its device image: they must not run
+ *     while a scan with that trie is in flight or being issued.  Otherwise a
+ *     trie may be shared by many streams and threads.  A workspace
+ *     serializes: calls that share a workspace must be issued on one stream
+ *     (or otherwise ordered); calls on different workspaces may overlap.
  */
 #ifndef PFAC_H
 #define PFAC_H
@@ -200,8 +202,11 @@ int pfac_trie_export(const pfac_trie *t, uint32_t *row_ptr, uint8_t *labels, uin
 /* Free a trie and its device image.  NULL is ignored. */
 void pfac_trie_free(pfac_trie *t);
 
-/* Current / new launch parameters.  Setting them may rebuild the level
- * index on the host and re-upload it (synchronous). */
+/* Current / new launch parameters.  Setting them may rebuild the device
+ * image on the host and re-upload it (synchronous: no scan with this trie
+ * may be in flight).  Errors: PFAC_EINVAL (NULL, a field out of range,
+ * dag combined with top_nodes or trunc_depth, or bitmapped top nodes that do
+ * not fit in LDS; the previous tuning stays), PFAC_ENOMEM, PFAC_EDEVICE. */
 int pfac_trie_get_tuning(const pfac_trie *t, pfac_tuning *out);
 int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tuning);
 
