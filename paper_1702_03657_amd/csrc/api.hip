@@ -453,22 +453,22 @@ extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
     if (!t || !tn || !valid_tuning(tn)) return PFAC_EINVAL;
     const bool repack = tn->index_bits != t->tuning.index_bits || tn->fold_bits != t->tuning.fold_bits ||
                         tn->trunc_depth != t->tuning.trunc_depth || tn->dag != t->tuning.dag;
-    const pfac_tuning old = t->tuning;
-    t->tuning = *tn;
+    // the new image is built aside; the trie changes only once it is complete
+    DeviceImageHost fresh;
     if (repack) {
         try {
-            pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->tuning.trunc_depth, t->tuning.dag,
-                       t->img);
+            pack_image(t->crs, tn->index_bits, tn->fold_bits, tn->trunc_depth, tn->dag, fresh);
         } catch (const std::bad_alloc &) {
-            t->tuning = old;
             return PFAC_ENOMEM;
         }
+        std::swap(t->img, fresh);  // `fresh` keeps the previous image
     }
+    const pfac_tuning old = t->tuning;
+    t->tuning = *tn;
     if (tn->kernel == 0 && tn->top_nodes && layout_for(t).lds_total > t->lds_limit) {
-        // the bitmapped top nodes do not fit: keep the previous tuning
+        // the bitmapped top nodes do not fit: the previous tuning and image stay
         t->tuning = old;
-        if (repack) pack_image(t->crs, t->tuning.index_bits, t->tuning.fold_bits, t->tuning.trunc_depth, t->tuning.dag,
-                       t->img);
+        if (repack) std::swap(t->img, fresh);
         return PFAC_EINVAL;
     }
     if (repack && !t->host_only) return upload_image(t);
