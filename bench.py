@@ -149,13 +149,20 @@ def cpu_baseline(oracle, wl, threads):
     gbps = wl.text.size * 8 / tm[1] / 1e9
     ta = [0.0, 0.0]
     ac = oracle.aho_corasick(wl.text, wl.patterns, threads=threads, timing=ta)
+    extra = {}
+    if wl.text.size <= (8 << 20):
+        # small texts: the literal definition (every pattern at every position) too
+        tb = [0.0, 0.0]
+        br = oracle.brute(wl.text, wl.patterns, threads=threads, timing=tb)
+        extra = {"brute_force_gbit_s": round(wl.text.size * 8 / tb[1] / 1e9, 3),
+                 "brute_force_same_matches": bool(br.n == m.n)}
     return {"value": round(gbps, 3), "unit": "Gbit/s", "cores": threads, "kind": "oracle",
             "sample": f"bucketed matcher (first-min(len,8)-byte index + memcmp) over the whole "
                       f"{wl.text.size} B text; index build {tm[0]:.3f}s excluded; "
                       f"{m.n} matches",
             "nproc": os.cpu_count(), "cpu_model": cpu_model(),
             "aho_corasick_gbit_s": round(wl.text.size * 8 / ta[1] / 1e9, 3),
-            "aho_corasick_same_matches": bool(ac.n == m.n)}, m
+            "aho_corasick_same_matches": bool(ac.n == m.n), **extra}, m
 
 
 def streaming_probe(torch, text, reps=10):
