@@ -22,6 +22,10 @@ static thread_local int g_last_hip = 0;
 
 static int hip_fail(hipError_t e) {
     g_last_hip = (int)e;
+    // the error is reported here (and by pfac_last_hip_error); clear the
+    // runtime's last-error state so that the caller's next HIP call does not
+    // see it again
+    (void)hipGetLastError();
     return e == hipErrorOutOfMemory ? PFAC_ENOMEM : PFAC_EDEVICE;
 }
 
@@ -536,6 +540,8 @@ extern "C" int pfac_workspace_reserve(pfac_workspace *w, uint64_t max_bytes, uin
                                       uint64_t max_matches) {
     (void)max_texts;
     if (!w) return PFAC_EINVAL;
+    // sizes whose byte counts would not even fit in 64 bits cannot be allocated
+    if (max_bytes > (1ull << 56) || max_matches > (1ull << 56)) return PFAC_ENOMEM;
     uint64_t n_tiles = (max_bytes + 16 + kWG * 4 - 1) / (kWG * 4);  // smallest tile
     return ws_reserve(w, n_tiles, max_matches, true);
 }

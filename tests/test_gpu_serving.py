@@ -113,3 +113,20 @@ def test_empty_request_and_limits():
     got, _ = srv.wait(rid, capacity=1024)
     assert_same(got, oracle.brute(t, pats))
     srv.close()
+
+
+def test_allocation_failure_leaves_the_workspace_usable():
+    """A reservation the device cannot hold fails with PFAC_ENOMEM (the
+    allocator's refusal, forced from the host with an impossible size) and the
+    same workspace then scans normally."""
+    pats = [b"abc", b"bcd", b"cd"]
+    trie = pf.Trie(pats)
+    ws = pf.Workspace()
+    # 1 TiB of staging (beyond the device), and sizes refused before any allocation
+    for max_bytes, max_matches in ((1 << 20, 1 << 36), (1 << 62, 1), (1 << 20, 1 << 62)):
+        with pytest.raises(pf.PfacError) as e:
+            ws.reserve(max_bytes, 1, max_matches)
+        assert e.value.code == pf.PFAC_ENOMEM
+    t = np.frombuffer(b"xabcdx" * 1000, dtype=np.uint8).copy()
+    got, _ = gpu_scan(trie, t, ws=ws)
+    assert_same(got, oracle.brute(t, pats))
