@@ -322,8 +322,8 @@ int pfac_server_create(const pfac_trie *t, void *arena_dev, uint64_t arena_bytes
 
 /*
  * Queue a scan of text_host[0 .. n).  The bytes are read until the request
- * completes, so the buffer must stay valid until pfac_server_wait returns
- * for it.  Returns the request id in *request_id.  PFAC_EINVAL if a single
+ * completes, so the buffer must stay valid until pfac_server_wait or
+ * pfac_server_cancel returns PFAC_OK for it.  Returns the request id in *request_id.  PFAC_EINVAL if a single
  * request can never fit the budget.
  */
 int pfac_server_submit(pfac_server *s, const uint8_t *text_host, uint64_t n,
@@ -335,17 +335,33 @@ int pfac_server_submit(pfac_server *s, const uint8_t *text_host, uint64_t n,
  * copied there (text_id = 0, positions relative to the request's text).
  * PFAC_ETRUNC when the count exceeds capacity (count still exact).
  * latency_s (optional) receives submit-to-completion seconds.  Returns
- * PFAC_EBUSY on timeout.  Each request may be waited for once.
+ * PFAC_EBUSY on timeout (the request stays queued and may be waited for
+ * again).  Each request may be waited for once, by one thread at a time:
+ * PFAC_EINVAL for an id already waited for, cancelled, unknown, or being
+ * waited for by another thread.
  */
 int pfac_server_wait(pfac_server *s, uint64_t request_id, int64_t timeout_ms,
                      pfac_match *out_host, uint64_t capacity, uint64_t *n_matches,
                      double *latency_s);
 
+/*
+ * Withdraw a request that is not being waited for.  A request still queued
+ * for the budget is dropped at once; one admitted but not yet in a batch
+ * leaves the ring once its copy has landed; one whose batch is running is
+ * finished by the device and its matches are dropped (the call returns when
+ * that batch ends); a completed one has its matches dropped.  After
+ * PFAC_OK the text buffer is no longer read and the id is released: waiting
+ * for it or cancelling it again returns PFAC_EINVAL.  PFAC_EINVAL also for
+ * an unknown id and for a request another thread is waiting for.
+ */
+int pfac_server_cancel(pfac_server *s, uint64_t request_id);
+
 /* Counters since creation: requests completed, batches launched, text bytes scanned. */
 int pfac_server_stats(const pfac_server *s, uint64_t *requests, uint64_t *batches,
                       uint64_t *bytes);
 
-/* Finish every queued request, stop the worker and free the server. */
+/* Finish every queued request, stop the worker and free the server.  No other
+ * call on the server may run during or after it. */
 void pfac_server_free(pfac_server *s);
 
 #ifdef __cplusplus

@@ -110,6 +110,7 @@ SIGNATURES = [
     ("pfac_server_submit", ctypes.c_int, [_vp, _vp, _u64, _p(_u64)]),
     ("pfac_server_wait", ctypes.c_int,
      [_vp, _u64, _i64, _vp, _u64, _p(_u64), _p(ctypes.c_double)]),
+    ("pfac_server_cancel", ctypes.c_int, [_vp, _u64]),
     ("pfac_server_stats", ctypes.c_int, [_vp, _p(_u64), _p(_u64), _p(_u64)]),
     ("pfac_server_free", None, [_vp]),
 ]
@@ -387,11 +388,17 @@ class Server:
         lat = ctypes.c_double(0)
         rc = load().pfac_server_wait(self.handle, request_id, timeout_ms, out.ctypes.data,
                                      capacity, ctypes.byref(n), ctypes.byref(lat))
-        self._keep.pop(request_id, None)
+        if rc != PFAC_EBUSY:  # on a timeout the text is still read
+            self._keep.pop(request_id, None)
         if rc == PFAC_ETRUNC:
             raise PfacError("pfac_server_wait", rc)
         check("pfac_server_wait", rc)
         return out[:int(n.value)].copy(), float(lat.value)
+
+    def cancel(self, request_id: int) -> None:
+        """Withdraw a request: its text is no longer read and its matches are dropped."""
+        check("pfac_server_cancel", load().pfac_server_cancel(self.handle, request_id))
+        self._keep.pop(request_id, None)
 
     def stats(self) -> dict:
         r, b, y = _u64(0), _u64(0), _u64(0)

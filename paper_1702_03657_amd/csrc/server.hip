@@ -44,6 +44,7 @@ struct Req {
     std::vector<pfac_match> res;
     uint64_t n_matches = 0;
     int rc = PFAC_OK;
+    bool claimed = false;     // a caller waits for it or cancels it
 };
 
 struct Slot {
@@ -407,10 +408,14 @@ extern "C" int pfac_server_wait(pfac_server *s, uint64_t request_id, int64_t tim
     auto it = s->by_id.find(request_id);
     if (it == s->by_id.end()) return PFAC_EINVAL;
     Req *r = it->second;
+    if (r->claimed) return PFAC_EINVAL;  // another thread waits for it or cancels it
+    // while claimed nobody else erases the entry, so `it` stays valid
+    r->claimed = true;
     auto done = [&] { return r->st == St::Done; };
     if (timeout_ms < 0) {
         s->cv_done.wait(lock, done);
     } else if (!s->cv_done.wait_for(lock, std::chrono::milliseconds(timeout_ms), done)) {
+        r->claimed = false;
         return PFAC_EBUSY;
     }
     s->by_id.erase(it);
@@ -424,6 +429,41 @@ extern "C" int pfac_server_wait(pfac_server *s, uint64_t request_id, int64_t tim
     if (r->copied) (void)hipEventDestroy(r->copied);
     delete r;
     return rc;
+}
+
+extern "C" int pfac_server_cancel(pfac_server *s, uint64_t request_id) {
+    if (!s) return PFAC_EINVAL;
+    std::unique_lock<std::mutex> lock(s->mu);
+    auto it = s->by_id.find(request_id);
+    if (it == s->by_id.end() || it->second->claimed) return PFAC_EINVAL;
+    Req *r = it->second;
+    r->claimed = true;
+    bool copy_in_flight = false;
+    switch (r->st) {
+    case St::Queued:  // never admitted: no copy was issued
+        s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
+        break;
+    case St::Copying:
+        // admitted but in no batch yet: batches skip it from now on and its
+        // ring bytes are released in ring order; the copy may still run
+        r->st = St::Done;
+        copy_in_flight = true;
+        s->release_locked();
+        s->cv_work.notify_one();
+        break;
+    case St::Scanning:  // its batch runs to the end; the results are dropped
+        s->cv_done.wait(lock, [&] { return r->st == St::Done; });
+        break;
+    case St::Done:
+        break;
+    }
+    s->by_id.erase(it);
+    lock.unlock();
+    // the server holds no reference to r any more
+    if (copy_in_flight) (void)hipEventSynchronize(r->copied);
+    if (r->copied) (void)hipEventDestroy(r->copied);
+    delete r;
+    return PFAC_OK;
 }
 
 extern "C" int pfac_server_stats(const pfac_server *s, uint64_t *requests, uint64_t *batches,

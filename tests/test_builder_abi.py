@@ -104,6 +104,7 @@ def test_error_codes(lib):
     lib.pfac_workspace_free(None)
     lib.pfac_graph_free(None)
     lib.pfac_server_free(None)
+    assert lib.pfac_server_cancel(None, 1) == pf.PFAC_EINVAL
     t = pf.Trie([b"abc"], host_only=True)
     # a host-only trie cannot scan
     rc = lib.pfac_scan(t.handle, None, None, 0, None, 0, None, None, None)

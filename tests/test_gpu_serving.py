@@ -1,7 +1,7 @@
 """GPU tests of the serving loop (pfac_server_*): every request's result is
 the same as the oracle's for that text alone and as a scan of it alone on the
-GPU, whatever the mix it was batched with, the ring wrap-around, the budget
-and the overflow fallback."""
+GPU, whatever the mix it was batched with, the ring wrap-around, the budget,
+the overflow fallback and the cancellation of other requests."""
 
 import math
 
@@ -130,3 +130,58 @@ def test_allocation_failure_leaves_the_workspace_usable():
     t = np.frombuffer(b"xabcdx" * 1000, dtype=np.uint8).copy()
     got, _ = gpu_scan(trie, t, ws=ws)
     assert_same(got, oracle.brute(t, pats))
+
+
+def test_cancel_leaves_the_rest_exact():
+    """Requests cancelled while queued behind a text that holds the whole
+    budget, while in flight and after completion: their ids are released,
+    every other request gets the oracle's matches, and the server keeps
+    serving with a consistent ring."""
+    pats = workloads.make_patterns(np.random.default_rng(7), 500, 6, 32, "uniform")
+    budget = 16 << 20
+    rng = np.random.default_rng(23)
+    big = rng.integers(0, 256, budget, dtype=np.uint8)
+    for at in rng.integers(0, budget - 64, 200):
+        p = pats[int(rng.integers(0, len(pats)))]
+        big[at:at + len(p)] = np.frombuffer(p, dtype=np.uint8)
+    small = _requests(22, 30, 4096, 256 * 1024, pats)
+    trie = pf.Trie(pats)
+    srv, _buf = _server(trie, budget, budget + (16 << 20), 8)
+    texts = {srv.submit(big): big}
+    first = srv.submit(small[0])
+    srv.cancel(first)  # the big text holds the whole budget: still queued
+    ids = [srv.submit(t) for t in small[1:]]
+    texts.update(zip(ids, small[1:]))
+    cancelled = [first] + ids[2::3]
+    for rid in cancelled[1:]:
+        srv.cancel(rid)
+        del texts[rid]
+    # one waited for with a zero timeout first (pending behind the big text), then cancelled
+    late = srv.submit(big)
+    try:
+        srv.wait(late, timeout_ms=0)
+    except pf.PfacError as e:
+        assert e.code == pf.PFAC_EBUSY
+        srv.cancel(late)
+    cancelled.append(late)
+    say(f"cancel: {len(texts)} kept, {len(cancelled)} cancelled")
+    for rid, t in texts.items():
+        got, _ = srv.wait(rid, capacity=1 << 16)
+        assert_same(got, oracle.bucketed(t, pats, threads=8))
+    # requests never scanned are not counted
+    assert srv.stats()["requests"] < len(texts) + len(cancelled)
+    for rid in cancelled:
+        for call in (srv.wait, srv.cancel):
+            with pytest.raises(pf.PfacError) as e:
+                call(rid)
+            assert e.value.code == pf.PFAC_EINVAL
+    done = srv.submit(small[1])
+    import time
+    time.sleep(0.2)
+    srv.cancel(done)  # completed and never waited for: the matches are dropped
+    # the ring is consistent: a second pass over every small text is exact
+    again = [srv.submit(t) for t in small]
+    for rid, t in zip(again, small):
+        got, _ = srv.wait(rid, capacity=1 << 16)
+        assert_same(got, oracle.bucketed(t, pats, threads=8))
+    srv.close()
