@@ -125,8 +125,18 @@ struct pfac_server {
             used += r->ring_len;
             in_ring.push_back(r);
             r->st = St::Copying;
-            (void)hipMemcpyAsync(ring + off, r->host, r->n, hipMemcpyHostToDevice, xs);
-            (void)hipEventRecord(r->copied, xs);
+            if (hipMemcpyAsync(ring + off, r->host, r->n, hipMemcpyHostToDevice, xs) != hipSuccess ||
+                hipEventRecord(r->copied, xs) != hipSuccess) {
+                // no batch takes it; its ring bytes are released in ring order
+                // once the copy stream has drained past it
+                (void)hipStreamSynchronize(xs);
+                (void)hipGetLastError();
+                r->rc = PFAC_EDEVICE;
+                r->st = St::Done;
+                r->t_done = clk::now();
+                release_locked();
+                cv_done.notify_all();
+            }
         }
     }
 
@@ -217,23 +227,28 @@ struct pfac_server {
         const uint64_t cnt = *S.count_host;
         std::vector<uint64_t> start(S.reqs.size() + 1, 0);
         if (cnt <= S.out_cap) {
+            int copy_rc = PFAC_OK;
             if (cnt) {
                 // the batch has ended (its event was seen): copy on our own stream,
                 // behind nothing queued on the compute or copy streams
-                (void)hipMemcpyAsync(S.out_host, S.out_dev, cnt * sizeof(pfac_match),
-                                     hipMemcpyDeviceToHost, ds);
-                (void)hipStreamSynchronize(ds);
+                if (hipMemcpyAsync(S.out_host, S.out_dev, cnt * sizeof(pfac_match),
+                                   hipMemcpyDeviceToHost, ds) != hipSuccess ||
+                    hipStreamSynchronize(ds) != hipSuccess) {
+                    (void)hipGetLastError();
+                    copy_rc = PFAC_EDEVICE;
+                }
             }
             // records are sorted by text id: split by a linear sweep
             uint64_t k = 0;
             for (size_t i = 0; i < S.reqs.size(); i++) {
                 Req *r = S.reqs[i];
+                r->rc = copy_rc;
+                if (copy_rc != PFAC_OK) continue;
                 uint64_t a = k;
                 while (k < cnt && S.out_host[k].text_id == i) k++;
                 r->res.assign(S.out_host + a, S.out_host + k);
                 for (auto &m : r->res) m.text_id = 0;
                 r->n_matches = k - a;
-                r->rc = PFAC_OK;
             }
         } else {
             for (Req *r : S.reqs) rescan_alone(r, S.ws);

@@ -185,3 +185,43 @@ def test_cancel_leaves_the_rest_exact():
         got, _ = srv.wait(rid, capacity=1 << 16)
         assert_same(got, oracle.bucketed(t, pats, threads=8))
     srv.close()
+
+
+def test_random_submit_wait_cancel():
+    """A seeded random mix of submits, zero-timeout waits, waits and cancels
+    over a small ring: every request that is waited for gets the oracle's
+    matches, whatever was cancelled around it and in whatever state."""
+    pats = workloads.make_patterns(np.random.default_rng(8), 300, 4, 24, "uniform")
+    texts = _requests(31, 120, 256, 96 * 1024, pats, rate=1 / 256)
+    trie = pf.Trie(pats)
+    budget = 256 << 10
+    srv, _buf = _server(trie, budget, budget + (8 << 20), 6)
+    rng = np.random.default_rng(41)
+    pending = {}  # id -> text index
+    n_checked = n_cancelled = 0
+    for i, t in enumerate(texts):
+        pending[srv.submit(t)] = i
+        for _ in range(int(rng.integers(0, 3))):
+            if not pending:
+                break
+            rid = list(pending)[int(rng.integers(0, len(pending)))]
+            op = int(rng.integers(0, 3))
+            if op == 0:
+                srv.cancel(rid)
+                del pending[rid]
+                n_cancelled += 1
+                continue
+            try:
+                got, _ = srv.wait(rid, capacity=1 << 14, timeout_ms=0 if op == 1 else -1)
+            except pf.PfacError as e:
+                assert op == 1 and e.code == pf.PFAC_EBUSY
+                continue
+            assert_same(got, oracle.bucketed(texts[pending.pop(rid)], pats, threads=8))
+            n_checked += 1
+    for rid, i in pending.items():
+        got, _ = srv.wait(rid, capacity=1 << 14)
+        assert_same(got, oracle.bucketed(texts[i], pats, threads=8))
+        n_checked += 1
+    say(f"random serving: {n_checked} checked, {n_cancelled} cancelled")
+    assert n_checked + n_cancelled == len(texts) and n_cancelled > 10
+    srv.close()
