@@ -107,3 +107,50 @@ def test_full_size_serving_requests():
         assert np.array_equal(got["pos"], want["pos"][sel]), i
         assert np.array_equal(got["pattern_id"], want["id"][sel]), i
     srv.close()
+
+
+def test_positions_beyond_4_gib():
+    """64-bit positions: a text of 2^32 + 2^20 + 4,109 bytes (zeros, with a random
+    stretch across byte 2^32 and planted copies straddling it, at both ends
+    and inside the stretch), scanned whole and as a batch of three texts
+    whose boundaries lie on both sides of 2^32, against the oracle's lists."""
+    import torch
+    rng = np.random.default_rng(77)
+    pats = workloads.make_patterns(rng, 300, 6, 24, "uniform")
+    plist = pats.as_list()
+    n = (1 << 32) + (1 << 20) + 4096 + 13
+    text = np.zeros(n, dtype=np.uint8)
+    lo = (1 << 32) - (1 << 20)
+    text[lo:lo + (2 << 20)] = rng.integers(0, 256, 2 << 20, dtype=np.uint8)
+    at = [0, (1 << 32) - 3, (1 << 32) - 1, 1 << 32, (1 << 32) + 7, n - len(plist[5])]
+    at += rng.integers(lo, lo + (2 << 20) - 32, 200).tolist()
+    for i, p in enumerate(at):
+        q = plist[(5 + 7 * i) % len(plist)] if p != n - len(plist[5]) else plist[5]
+        text[p:p + len(q)] = np.frombuffer(q, dtype=np.uint8)
+    say(f"beyond 4 GiB: {n} bytes, {len(at)} plants")
+    want = oracle.bucketed(text, pats, threads=16)
+    assert (want["pos"] >= (1 << 32)).sum() > 50 and want.n > 150
+    trie = pf.Trie(pats)
+    dev = torch.from_numpy(text).cuda()
+    cap = want.n + 1024
+    out = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    ws = pf.Workspace()
+    default = trie.tuning()
+    for tn in (default, dict(default, kernel=0)):  # the library's choice, then the tile kernel
+        trie.set_tuning(**tn)
+        say(f"  kernel {trie.stats()['scan_kernel']}")
+        rc, got_n = pf.pfac_scan_sync(trie, ws, dev, n, out, cap)
+        assert rc == pf.PFAC_OK and got_n == want.n
+        assert_same(pf.matches_to_numpy(out, got_n), want)
+    trie.set_tuning(**default)
+    # the same bytes as three texts: [0, 2^32 - 5), [2^32 - 5, 2^32 + 100), the rest
+    offs = np.array([0, (1 << 32) - 5, (1 << 32) + 100, n], dtype=np.uint64)
+    want_b = oracle.bucketed(text, pats, offsets=offs, threads=16)
+    offs_dev = torch.from_numpy(offs.view(np.int64)).cuda()
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.current_stream()
+    pf.pfac_scan_batch(trie, ws, dev, offs_dev, 3, n, out, cap, cnt, s)
+    torch.cuda.synchronize()
+    assert int(cnt.item()) == want_b.n
+    assert_same(pf.matches_to_numpy(out, want_b.n), want_b, with_text=True)
+    del dev, out
