@@ -649,7 +649,7 @@ def placement_ablation(pf, torch, names, steps, warmup, threads):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
     ap.add_argument("--retune", action="store_true", help="ignore the cached autotune choice")
@@ -866,7 +866,7 @@ def main():
         line["parity_with_oracle"] = bool(same)
     if not args.no_extras:
         line["batched_vs_plain"] = extras_batched(
-            pf, torch, max(3, args.steps // 5),
+            pf, torch, max(3, min(10, args.steps // 5)),
             0 if args.no_cpu_baseline else (args.cpu_threads or min(16, os.cpu_count() or 1)))
     if not args.no_serving:
         line["serving"] = extras_serving(
