@@ -10,7 +10,7 @@ text and the trie already resident in HBM.  Prints one JSON line:
   library around it on the launch stream, against the MI355X HBM peak;
   ``traffic`` comes from committed rocprofv3 FETCH_SIZE / WRITE_SIZE counts
   when they were taken on the current kernel source;
-* ``cpu_baseline``: the oracle's bucketed matcher on the box's host cores
+* ``cpu_baseline``: the oracle's bucketed matcher on the machine's host cores
   (with the textbook Aho-Corasick automaton's rate beside it);
 * ``ms_per_step_median`` / ``_min`` over the timed steps, and the timed
   kernel's rate against a measured read-only streaming probe as well as the
@@ -213,7 +213,7 @@ def cpu_baseline(oracle, wl, threads):
 
 
 def streaming_probe(torch, text, reps=10):
-    """Read-only streaming rate of the box: torch's float32 sum over the text's
+    """Read-only streaming rate of the device: torch's float32 sum over the text's
     bytes read as float32 words (the values do not matter, only the reads)."""
     x = text[: (text.numel() // 4) * 4].view(torch.float32)
     for _ in range(2):
