@@ -24,6 +24,7 @@
 #include <vector>
 
 #include "../../include/pfac.h"
+#include "text_ring.hpp"
 
 namespace {
 
@@ -37,9 +38,7 @@ struct Req {
     uint64_t n = 0;
     clk::time_point t_submit, t_done;
     St st = St::Queued;
-    uint64_t ring_off = 0;    // start of the text in the ring
-    uint64_t ring_len = 0;    // bytes taken in the ring (text + wrap padding)
-    bool wraps = false;       // placed at 0, holding the unused end of the ring
+    pfac::TextRing::Span span;  // its bytes in the ring (admitted requests)
     hipEvent_t copied = nullptr;
     std::vector<pfac_match> res;
     uint64_t n_matches = 0;
@@ -67,7 +66,6 @@ struct pfac_server {
     const pfac_trie *t = nullptr;
     uint8_t *ring = nullptr;
     uint64_t ring_bytes = 0;
-    uint64_t budget = 0;
     uint32_t max_batch = 1;
     hipStream_t cs = nullptr, xs = nullptr;
     hipStream_t ds = nullptr;  // own stream for result copies (device to host)
@@ -81,48 +79,17 @@ struct pfac_server {
     std::deque<Req *> queue;     // submitted, not admitted (arrival order)
     std::deque<Req *> in_ring;   // admitted, ring order
     std::map<uint64_t, Req *> by_id;
-    uint64_t head = 0, tail = 0, used = 0;  // ring state (bytes)
+    pfac::TextRing place{0, 0};  // where admitted texts sit in `ring`
     uint64_t stat_req = 0, stat_batches = 0, stat_bytes = 0;
     std::thread worker;
-
-    // Ring of text bytes.  Occupied bytes are [head, tail) when not wrapped,
-    // else [head, ring_bytes) + [0, tail).  A request that does not fit
-    // before the end of the ring starts at 0 and also holds the unused end
-    // bytes until it is released.
-    bool wrapped = false;
-
-    bool ring_take(uint64_t n, uint64_t &off, uint64_t &pad) {
-        if (n > ring_bytes) return false;
-        if (!wrapped) {
-            if (ring_bytes - tail >= n) {
-                off = tail;
-                pad = 0;
-            } else if (head >= n) {
-                off = 0;
-                pad = ring_bytes - tail;
-            } else {
-                return false;
-            }
-        } else {
-            if (head - tail < n) return false;
-            off = tail;
-            pad = 0;
-        }
-        return used + n + pad <= budget;
-    }
 
     void admit_locked() {
         while (!queue.empty()) {
             Req *r = queue.front();
             uint64_t off = 0, pad = 0;
-            if (!ring_take(r->n, off, pad)) break;
+            if (!place.fits(r->n, off, pad)) break;
             queue.pop_front();
-            r->wraps = !wrapped && off == 0 && !in_ring.empty();
-            if (r->wraps) wrapped = true;
-            r->ring_off = off;
-            r->ring_len = r->n + pad;
-            tail = off + r->n;
-            used += r->ring_len;
+            r->span = place.place(r->n, off, pad, in_ring.empty());
             in_ring.push_back(r);
             r->st = St::Copying;
             if (hipMemcpyAsync(ring + off, r->host, r->n, hipMemcpyHostToDevice, xs) != hipSuccess ||
@@ -144,13 +111,7 @@ struct pfac_server {
         while (!in_ring.empty() && in_ring.front()->st == St::Done) {
             Req *r = in_ring.front();
             in_ring.pop_front();
-            used -= r->ring_len;
-            if (r->wraps) wrapped = false;
-            head = r->ring_off + r->n;
-            if (in_ring.empty()) {
-                head = tail = used = 0;
-                wrapped = false;
-            }
+            place.release(r->span, in_ring.empty());
         }
     }
 
@@ -167,7 +128,7 @@ struct pfac_server {
             if (r->st != St::Copying) break;
             if (!b.empty()) {
                 const Req *p = b.back();
-                if (p->ring_off + p->n != r->ring_off) break;  // ring wrapped
+                if (p->span.off + p->n != r->span.off) break;  // ring wrapped
             }
             b.push_back(r);
             if (b.size() >= max_batch) break;
@@ -175,7 +136,7 @@ struct pfac_server {
     }
 
     int launch(Slot &S, std::vector<Req *> &b) {
-        const uint64_t base = b.front()->ring_off;
+        const uint64_t base = b.front()->span.off;
         S.offsets_host[0] = 0;
         for (size_t i = 0; i < b.size(); i++)
             S.offsets_host[i + 1] = S.offsets_host[i] + b[i]->n;
@@ -204,7 +165,7 @@ struct pfac_server {
     // A request of a batch whose matches overflowed the slot: scan it alone.
     void rescan_alone(Req *r, pfac_workspace *ws) {
         uint64_t n = 0;
-        r->rc = pfac_scan_sync(t, ws, ring + r->ring_off, r->n, nullptr, 0, &n, nullptr, cs);
+        r->rc = pfac_scan_sync(t, ws, ring + r->span.off, r->n, nullptr, 0, &n, nullptr, cs);
         if (r->rc != PFAC_OK && r->rc != PFAC_ETRUNC) return;
         r->rc = PFAC_OK;
         r->res.resize(n);
@@ -215,7 +176,7 @@ struct pfac_server {
             return;
         }
         uint64_t n2 = 0;
-        r->rc = pfac_scan_sync(t, ws, ring + r->ring_off, r->n, d, n, &n2, nullptr, cs);
+        r->rc = pfac_scan_sync(t, ws, ring + r->span.off, r->n, d, n, &n2, nullptr, cs);
         if (r->rc == PFAC_OK &&
             hipMemcpy(r->res.data(), d, n * sizeof(pfac_match), hipMemcpyDeviceToHost) != hipSuccess)
             r->rc = PFAC_EDEVICE;
@@ -347,7 +308,7 @@ extern "C" int pfac_server_create(const pfac_trie *t, void *arena_dev, uint64_t 
     }
     s->ring = a;
     s->ring_bytes = budget_bytes;
-    s->budget = budget_bytes;
+    s->place = pfac::TextRing(budget_bytes, budget_bytes);
     int rc = PFAC_OK;
     for (int q = 0; q < 2 && rc == PFAC_OK; q++) {
         Slot &S = s->slot[q];

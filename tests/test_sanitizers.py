@@ -1,6 +1,6 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only):
-the trie builder with every device-image variant, and the oracle's three
-matchers.  Each is built into its own test binary with g++ / gcc (no GPU
+the trie builder with every device-image variant, the oracle's three
+matchers, and the serving loop's ring placement.  Each is built into its own test binary with g++ / gcc (no GPU
 code is compiled with a sanitizer); a memory or UB error aborts the run."""
 
 import os
@@ -42,3 +42,14 @@ def test_oracle_under_sanitizers(tmp_path):
                 os.path.join(ROOT, "oracle", "oracle.c"), "-lpthread", "-lm"],
                tmp_path, "sanitize_oracle")
     assert "ok" in out
+
+
+@pytest.mark.skipif(shutil.which("g++") is None, reason="no g++")
+def test_serving_ring_placement(tmp_path):
+    """The serving loop's ring placement (the server's own host class) in a
+    randomized simulation: arrivals, completions in any order, cancellations
+    of queued requests, release in placement order; every ring byte is
+    tracked, so an overlap, a budget overrun or a refused empty ring fails."""
+    out = _run(["g++", "-std=c++17", *SAN, os.path.join(NATIVE, "ring_sim.cpp")],
+               tmp_path, "ring_sim")
+    assert "ok" in out and "wrapped" in out
