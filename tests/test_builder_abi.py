@@ -289,3 +289,34 @@ def test_merged_dag_sizes():
     t.set_tuning(dag=1)
     assert t.stats()["scan_kernel"] == 0
     t.close()
+
+
+def test_host_allocation_failure_reports_enomem():
+    """An allocation the host cannot satisfy fails the build with PFAC_ENOMEM
+    and the library keeps working: a child process caps its address space a
+    little above its current size, builds a trie that needs more (300,000
+    patterns, about 12 M nodes), then a small one."""
+    import sys
+    script = r'''
+import resource, sys
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import paper_1702_03657_amd as pf
+from synth import workloads
+pats = workloads.make_patterns(np.random.default_rng(3), 300_000, 24, 64, "uniform")
+size = [int(l.split()[1]) * 1024 for l in open("/proc/self/status") if l.startswith("VmSize:")][0]
+cap = size + (256 << 20)
+resource.setrlimit(resource.RLIMIT_AS, (cap, cap))
+try:
+    pf.Trie(pats, host_only=True)
+    print("no failure")
+except pf.PfacError as e:
+    print("code", e.code)
+print("small", pf.Trie([b"abc", b"bcd"], host_only=True).stats()["nodes"])
+'''
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    run = subprocess.run([sys.executable, "-c", script, root], capture_output=True, text=True,
+                         timeout=300)
+    assert run.returncode == 0, run.stderr[-2000:]
+    assert f"code {pf.PFAC_ENOMEM}" in run.stdout, run.stdout
+    assert "small 7" in run.stdout, run.stdout
