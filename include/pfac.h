@@ -204,9 +204,13 @@ void pfac_trie_free(pfac_trie *t);
 
 /* Current / new launch parameters.  Setting them may rebuild the device
  * image on the host and re-upload it (synchronous: no scan with this trie
- * may be in flight).  Errors: PFAC_EINVAL (NULL, a field out of range,
- * dag combined with top_nodes or trunc_depth, or bitmapped top nodes that do
- * not fit in LDS; the previous tuning stays), PFAC_ENOMEM, PFAC_EDEVICE. */
+ * may be in flight).  The wave kernels (kernel 1, 2) run where they apply
+ * (whole, unmerged images with patterns of at most 65,535 bytes) and their
+ * tables fit in LDS; the tile kernel runs otherwise.  Errors: PFAC_EINVAL
+ * (NULL, a field out of range, dag combined with top_nodes or trunc_depth,
+ * or a tuning whose kernel does not fit in LDS, e.g. bitmapped top nodes or
+ * a level index too large; the previous tuning and image stay),
+ * PFAC_ENOMEM, PFAC_EDEVICE. */
 int pfac_trie_get_tuning(const pfac_trie *t, pfac_tuning *out);
 int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tuning);
 

@@ -316,20 +316,29 @@ extern "C" int pfac_build(const uint8_t *const *patterns, const uint64_t *length
     return build_common(data.data(), off.data(), n_patterns, flags, out);
 }
 
-// LDS layout of the kernel the tuning asks for.  The wave kernel drops to
-// fewer waves per workgroup, then drops the LDS child records, until its
-// tables and per-wave areas fit.
-static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr) {
-    ScanArgs a{};
-    a.im = t->view;
-    a.im.lvl_words = t->img.lvl_words;
-    a.im.identity = t->img.identity;
-    a.im.K = t->img.K;
-    a.im.b = t->img.b;
-    a.im.fold_syms = t->img.fold_syms;
-    a.halo = t->halo;
-    uint32_t waves = t->tuning.waves_per_wg;
-    if (t->tuning.kernel >= 1) {
+// LDS layout of the kernel a scan runs with the current tuning: the wave
+// kernel asked for (kernel 1 or 2) where it applies and fits, dropping to
+// fewer waves per workgroup, then dropping the LDS child records, until its
+// tables and per-wave areas fit; the tile kernel otherwise.  *wave_out says
+// which one it is.
+static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr, bool *wave_out = nullptr) {
+    auto common = [&]() {
+        ScanArgs a{};
+        a.im = t->view;
+        a.im.lvl_words = t->img.lvl_words;
+        a.im.identity = t->img.identity;
+        a.im.K = t->img.K;
+        a.im.b = t->img.b;
+        a.im.fold_syms = t->img.fold_syms;
+        a.halo = t->halo;
+        return a;
+    };
+    // tails and the merged DAG are walked by the tile kernel only, and the
+    // wave kernels' walk limits are 16-bit
+    const bool wave_ok = (t->tuning.kernel == 1 || t->tuning.kernel == 2) && !t->img.trunc_depth &&
+                         !t->img.dag && t->crs.max_len <= 0xffff;
+    if (wave_ok) {
+        ScanArgs a = common();
         a.fold = t->img.fold_bits;
         a.group = t->tuning.chunks_per_unit;
         // child_check 2: the prefix-4 filter where the image has one, else
@@ -341,17 +350,21 @@ static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr) {
         for (int with_rec = (t->tuning.child_check && t->img.K) ? 1 : 0; with_rec >= 0; with_rec--) {
             a.krec_words = with_rec && !pfx4 ? (uint32_t)t->img.krec.size() : 0u;
             a.pfx4_words = with_rec && pfx4 ? (uint32_t)t->img.pfx4.size() : 0u;
-            for (waves = t->tuning.waves_per_wg; waves >= 4; waves -= 4) {
+            for (uint32_t waves = t->tuning.waves_per_wg; waves >= 4; waves -= 4) {
                 wave_lds_layout(a, waves, t->lds_limit, t->tuning.kernel == 2);
-                if (a.lds_total <= t->lds_limit) break;
+                if (a.lds_total <= t->lds_limit) {
+                    if (waves_out) *waves_out = waves;
+                    if (wave_out) *wave_out = true;
+                    return a;
+                }
             }
-            if (a.lds_total <= t->lds_limit) break;
         }
-    } else {
-        a.top_words = t->tuning.top_nodes && t->img.K ? (uint32_t)t->img.top.size() : 0u;
-        lds_layout(a, t->tuning.bytes_per_lane);
     }
-    if (waves_out) *waves_out = std::max(4u, waves);
+    ScanArgs a = common();
+    a.top_words = t->tuning.top_nodes && t->img.K ? (uint32_t)t->img.top.size() : 0u;
+    lds_layout(a, t->tuning.bytes_per_lane);
+    if (waves_out) *waves_out = std::max(4u, t->tuning.waves_per_wg);
+    if (wave_out) *wave_out = false;
     return a;
 }
 
@@ -469,8 +482,10 @@ extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
     }
     const pfac_tuning old = t->tuning;
     t->tuning = *tn;
-    if (tn->kernel == 0 && tn->top_nodes && layout_for(t).lds_total > t->lds_limit) {
-        // the bitmapped top nodes do not fit: the previous tuning and image stay
+    if (layout_for(t).lds_total > t->lds_limit) {
+        // the kernel this tuning selects does not fit in LDS (e.g. bitmapped
+        // top nodes or a level index too large): the previous tuning and
+        // image stay
         t->tuning = old;
         if (repack) std::swap(t->img, fresh);
         return PFAC_EINVAL;
@@ -588,13 +603,12 @@ static hipError_t grant_lds(int slot, uint32_t bytes, hipError_t (*fn)(int, uint
 static hipError_t prep_tile(int bpl, uint32_t bytes) { return prepare_kernels((uint32_t)bpl, bytes); }
 static hipError_t prep_wave(int mode, uint32_t bytes) { return prepare_wave_kernel(mode, bytes); }
 
-// Wave kernel when asked for and its LDS layout fits; the tile kernel otherwise.
+// Wave kernel when asked for, applicable and its LDS layout fits; the tile
+// kernel otherwise.
 static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out) {
-    if (t->tuning.kernel != 1 && t->tuning.kernel != 2) return false;
-    if (t->img.trunc_depth || t->img.dag) return false;  // tails, DAG: the tile kernel's walk only
-    if (t->crs.max_len > 0xffff) return false;  // walk limits are 16-bit
-    const ScanArgs a = layout_for(t, waves_out);
-    return a.lds_total <= t->lds_limit;
+    bool wave = false;
+    (void)layout_for(t, waves_out, &wave);
+    return wave;
 }
 
 static bool uses_split(const pfac_trie *t) { return t->tuning.kernel == 2 && use_wave_kernel(t, nullptr); }

@@ -320,3 +320,30 @@ print("small", pf.Trie([b"abc", b"bcd"], host_only=True).stats()["nodes"])
     assert run.returncode == 0, run.stderr[-2000:]
     assert f"code {pf.PFAC_ENOMEM}" in run.stdout, run.stdout
     assert "small 7" in run.stdout, run.stdout
+
+
+FALLBACK_TUNINGS = [
+    # the four-symbol fold table at K = 9 alone is 256 KiB
+    dict(kernel=1, index_bits=18, fold_bits=8),
+    # tails and the merged DAG are walked by the tile kernel only
+    dict(kernel=2, index_bits=16, fold_bits=8, trunc_depth=8),
+    dict(kernel=2, index_bits=16, fold_bits=8, trunc_depth=0, dag=1),
+]
+
+
+def test_wave_tunings_that_cannot_apply_run_the_tile_kernel():
+    """A wave-kernel tuning whose kernel cannot run (tables too large for
+    LDS, a truncated or merged image, a pattern over 65,535 bytes) selects
+    the tile kernel with the tile kernel's own LDS layout, within the limit."""
+    pats = workloads.make_patterns(np.random.default_rng(4), 2000, 20, 32, "acgt")
+    t = pf.Trie(pats, host_only=True)
+    for tn in FALLBACK_TUNINGS:
+        t.set_tuning(**tn)
+        st = t.stats()
+        assert st["scan_kernel"] == 0 and 0 < st["lds_bytes"] <= 160 * 1024, (tn, st["lds_bytes"])
+    t.set_tuning(kernel=2, trunc_depth=0, dag=0)
+    assert t.stats()["scan_kernel"] == 2
+    long = pf.Trie([b"ab" * 35_000, b"abc"], host_only=True)
+    long.set_tuning(kernel=2)
+    st = long.stats()
+    assert st["scan_kernel"] == 0 and st["lds_bytes"] <= 160 * 1024

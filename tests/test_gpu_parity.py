@@ -410,3 +410,48 @@ def test_autotune_keeps_results():
     got, _ = gpu_scan(trie, wl.text, ws=ws, counts=False)
     want = oracle.bucketed(wl.text, wl.patterns, threads=8)
     assert_same(got, want)
+
+
+FALLBACKS = {
+    # the four-symbol fold table at K = 9 alone is 256 KiB
+    "k1_index18": dict(kernel=1, index_bits=18, fold_bits=8),
+    # tails and the merged DAG are walked by the tile kernel only
+    "k2_trunc8": dict(kernel=2, index_bits=16, fold_bits=8, trunc_depth=8),
+    "k2_dag": dict(kernel=2, index_bits=16, fold_bits=8, trunc_depth=0, dag=1),
+}
+
+
+@pytest.mark.parametrize("name", sorted(FALLBACKS) + ["k2_long_pattern"])
+def test_wave_tunings_that_cannot_apply(name):
+    """Wave-kernel tunings whose kernel cannot run select the tile kernel,
+    which must then scan with its own LDS layout: single texts and batches
+    against the oracle."""
+    rng = np.random.default_rng(61)
+    if name == "k2_long_pattern":
+        # a pattern over 65,535 bytes: beyond the wave kernels' 16-bit limits
+        base = bytes(rng.integers(0, 4, 70_001).astype(np.uint8))
+        pats = [base, base[:40], base[5:30], b"\x00\x01\x02"]
+        text = np.frombuffer((base * 3)[:180_000], dtype=np.uint8).copy()
+        tn = dict(kernel=2)
+    else:
+        pats = workloads.make_patterns(rng, 3000, 20, 32, "acgt").as_list()
+        text = rng.choice(np.frombuffer(b"ACGT", dtype=np.uint8), 300_000).astype(np.uint8)
+        for at in rng.integers(0, text.size - 40, 400):
+            p = pats[int(rng.integers(0, len(pats)))]
+            text[at:at + len(p)] = np.frombuffer(p, dtype=np.uint8)
+        tn = FALLBACKS[name]
+    trie = pf.Trie(pats)
+    trie.set_tuning(**tn)
+    st = trie.stats()
+    say(f"fallback {name}: kernel {st['scan_kernel']}, lds {st['lds_bytes']}, K {st['index_depth']}")
+    assert st["scan_kernel"] == 0
+    want = oracle.bucketed(text, pats, threads=8)
+    assert want.n > 0
+    got, counts = gpu_scan(trie, text)
+    assert_same(got, want)
+    assert np.array_equal(counts, oracle.counts(text.size, want))
+    offs = np.array([0, 1000, 1000, 77_777, text.size], dtype=np.uint64)
+    want_b = oracle.bucketed(text, pats, offsets=offs, threads=8)
+    got_b, n = gpu_scan_batch(trie, text, offs)
+    assert n == want_b.n
+    assert_same(got_b, want_b, with_text=True)
