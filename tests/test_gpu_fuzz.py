@@ -1,10 +1,13 @@
 """Seeded parity sweep: random pattern sets and texts (alphabets of 2 to 256
-bytes, planted copies and prefixes) scanned, single or batched, under random
-launch tunings (kernel, tile size, level-index bits, fold width, occupancy,
-waves, unit size, second filter stage, bitmapped top nodes, truncated and
-merged images), every result against the oracle's brute force.  Tunings the
-library refuses are skipped; every accepted one must give the oracle's list
-and, for single texts, its per-position counts."""
+bytes, planted copies and prefixes) scanned under random launch tunings
+(kernel, tile size, level-index bits, fold width, occupancy, waves, unit
+size, second filter stage, bitmapped top nodes, truncated and merged
+images), every result against the oracle's brute force.  Single texts start
+at any alignment and get an output buffer that may be too small (the exact
+count comes back, then a retry); batches run as one launch, one launch per
+text, or a graph replayed twice; one workspace serves all tunings of a case.
+Tunings the library refuses are skipped; every accepted one must give the
+oracle's list and, for single texts, its per-position counts."""
 
 import numpy as np
 import pytest
@@ -54,6 +57,8 @@ def test_random_sets_random_tunings(block):
             offs = np.concatenate([[0], cuts, [text.size]]).astype(np.uint64)
         want = oracle.brute(text, pats, offsets=offs, threads=8)
         trie = pf.Trie(pats)
+        ws = pf.Workspace()
+        pad = seed % 16
         for _ in range(5):
             t = _tuning(rng)
             try:
@@ -63,11 +68,20 @@ def test_random_sets_random_tunings(block):
             runs += 1
             where = f"seed {seed} tuning {t} k {len(pats)} n {text.size}"
             if offs is not None:
-                got, n = gpu_scan_batch(trie, text, offs)
+                mode = int(rng.integers(0, 3))
+                where += f" batch mode {mode}"
+                if mode == 2:
+                    res, n = gpu_scan_batch(trie, text, offs, ws=ws, pad_front=pad, graph_replays=2,
+                                            capacity=want.n + 16)
+                    got = res[-1]
+                    assert np.array_equal(res[0], got), where
+                else:
+                    got, n = gpu_scan_batch(trie, text, offs, ws=ws, pad_front=pad, plain=mode == 1)
                 assert n == want.n, where
                 assert np.array_equal(got["text_id"], want["text"]), where
             else:
-                got, counts = gpu_scan(trie, text)
+                cap = [None, 1, want.n // 2 + 1][int(rng.integers(0, 3))]
+                got, counts = gpu_scan(trie, text, ws=ws, pad_front=pad, capacity=cap)
                 assert got.size == want.n, where
                 if text.size:
                     assert np.array_equal(counts, oracle.counts(text.size, want)), where
