@@ -44,7 +44,14 @@ struct Req {
     uint64_t n_matches = 0;
     int rc = PFAC_OK;
     bool claimed = false;     // a caller waits for it or cancels it
+    bool orphan = false;      // released by its caller while still in the ring:
+                              // the worker frees it when it leaves the ring
 };
+
+void free_req(Req *r) {
+    if (r->copied) (void)hipEventDestroy(r->copied);
+    delete r;
+}
 
 struct Slot {
     uint64_t *offsets_dev = nullptr;   // max_batch + 1
@@ -112,7 +119,18 @@ struct pfac_server {
             Req *r = in_ring.front();
             in_ring.pop_front();
             place.release(r->span, in_ring.empty());
+            if (r->orphan) free_req(r);
         }
+    }
+
+    // The caller is done with r (waited for or cancelled, and Done): free it,
+    // or, while it still holds ring bytes behind requests not yet done,
+    // leave that to release_locked.  Called with the lock held.
+    void retire_locked(Req *r) {
+        if (std::find(in_ring.begin(), in_ring.end(), r) != in_ring.end())
+            r->orphan = true;
+        else
+            free_req(r);
     }
 
     // Admitted requests not yet scanned, contiguous in the ring, in ring
@@ -395,6 +413,8 @@ extern "C" int pfac_server_wait(pfac_server *s, uint64_t request_id, int64_t tim
         return PFAC_EBUSY;
     }
     s->by_id.erase(it);
+    // Done: the worker no longer writes r, and does not free it before it
+    // is retired below, so the results are copied unlocked
     lock.unlock();
     int rc = r->rc;
     *n_matches = r->n_matches;
@@ -402,8 +422,8 @@ extern "C" int pfac_server_wait(pfac_server *s, uint64_t request_id, int64_t tim
         std::memcpy(out_host, r->res.data(), std::min(capacity, r->n_matches) * sizeof(pfac_match));
     if (latency_s) *latency_s = std::chrono::duration<double>(r->t_done - r->t_submit).count();
     if (rc == PFAC_OK && r->n_matches > capacity) rc = PFAC_ETRUNC;
-    if (r->copied) (void)hipEventDestroy(r->copied);
-    delete r;
+    lock.lock();
+    s->retire_locked(r);
     return rc;
 }
 
@@ -413,20 +433,25 @@ extern "C" int pfac_server_cancel(pfac_server *s, uint64_t request_id) {
     auto it = s->by_id.find(request_id);
     if (it == s->by_id.end() || it->second->claimed) return PFAC_EINVAL;
     Req *r = it->second;
-    r->claimed = true;
-    bool copy_in_flight = false;
+    r->claimed = true;  // from here on nobody else erases or frees it
     switch (r->st) {
     case St::Queued:  // never admitted: no copy was issued
         s->queue.erase(std::find(s->queue.begin(), s->queue.end(), r));
         break;
-    case St::Copying:
+    case St::Copying: {
         // admitted but in no batch yet: batches skip it from now on and its
-        // ring bytes are released in ring order; the copy may still run
+        // ring bytes are released in ring order
         r->st = St::Done;
-        copy_in_flight = true;
         s->release_locked();
         s->cv_work.notify_one();
+        // its copy may still read the text: wait for it unlocked (r is not
+        // an orphan yet, so the worker does not free it meanwhile)
+        const hipEvent_t ev = r->copied;
+        lock.unlock();
+        (void)hipEventSynchronize(ev);
+        lock.lock();
         break;
+    }
     case St::Scanning:  // its batch runs to the end; the results are dropped
         s->cv_done.wait(lock, [&] { return r->st == St::Done; });
         break;
@@ -434,11 +459,7 @@ extern "C" int pfac_server_cancel(pfac_server *s, uint64_t request_id) {
         break;
     }
     s->by_id.erase(it);
-    lock.unlock();
-    // the server holds no reference to r any more
-    if (copy_in_flight) (void)hipEventSynchronize(r->copied);
-    if (r->copied) (void)hipEventDestroy(r->copied);
-    delete r;
+    s->retire_locked(r);
     return PFAC_OK;
 }
 
@@ -468,10 +489,9 @@ extern "C" void pfac_server_free(pfac_server *s) {
         if (S.done) (void)hipEventDestroy(S.done);
         pfac_workspace_free(S.ws);
     }
-    for (auto &kv : s->by_id) {
-        if (kv.second->copied) (void)hipEventDestroy(kv.second->copied);
-        delete kv.second;
-    }
+    // the worker has drained the ring (freeing its orphans): what is left
+    // are requests nobody waited for or cancelled
+    for (auto &kv : s->by_id) free_req(kv.second);
     if (s->ds) (void)hipStreamDestroy(s->ds);
     delete s;
 }

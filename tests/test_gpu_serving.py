@@ -225,3 +225,53 @@ def test_random_submit_wait_cancel():
     say(f"random serving: {n_checked} checked, {n_cancelled} cancelled")
     assert n_checked + n_cancelled == len(texts) and n_cancelled > 10
     srv.close()
+
+
+def test_random_servers_with_cancellation():
+    """Many small servers over seeded random pattern sets, launch tunings,
+    budgets and batch limits; requests are random slices of a random text,
+    a quarter of them cancelled right after a later submit (in whatever
+    state they are in), the rest waited for (with a time limit, so a lost
+    request fails instead of hanging) and compared with the oracle.  A
+    request cancelled or waited for while earlier ones still hold the ring
+    stays valid until it leaves the ring."""
+    import torch
+    from tests.test_gpu_fuzz import _tuning
+    from tests.test_gpu_random import _case
+    checked = cancelled = 0
+    for seed in range(7001, 7061):
+        pats, text = _case(seed)
+        if text.size < 64:
+            continue
+        rng = np.random.default_rng(seed)
+        trie = pf.Trie(pats)
+        for _ in range(10):
+            try:
+                trie.set_tuning(**_tuning(rng))
+                break
+            except pf.PfacError:
+                pass
+        budget = int(rng.integers(text.size // 4 + 64, text.size + 1))
+        max_batch = int(rng.choice([1, 2, 4, 16, 64]))
+        buf = torch.empty(budget + (8 << 20), dtype=torch.uint8, device="cuda")
+        srv = pf.Server(trie, buf, budget, max_batch, torch.cuda.Stream(), torch.cuda.Stream())
+        reqs, pending = [], {}
+        for i in range(int(rng.integers(5, 60))):
+            a = int(rng.integers(0, text.size))
+            b = min(text.size, a + int(rng.integers(0, min(budget, text.size) + 1)))
+            reqs.append(text[a:b].copy())
+            pending[srv.submit(reqs[-1])] = i
+            if rng.integers(0, 4) == 0:
+                rid = list(pending)[int(rng.integers(0, len(pending)))]
+                srv.cancel(rid)
+                del pending[rid]
+                cancelled += 1
+        for rid, i in pending.items():
+            want = oracle.brute(reqs[i], pats, threads=8)
+            got, _ = srv.wait(rid, capacity=want.n + 1, timeout_ms=30_000)
+            assert_same(got, want)
+            checked += 1
+        srv.close()
+        del buf
+    say(f"random servers: {checked} checked, {cancelled} cancelled")
+    assert checked > 500 and cancelled > 150
