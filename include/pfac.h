@@ -199,7 +199,8 @@ int pfac_trie_stats(const pfac_trie *t, pfac_stats *out);
 int pfac_trie_export(const pfac_trie *t, uint32_t *row_ptr, uint8_t *labels, uint32_t *child,
                      uint32_t *term_ptr, uint32_t *term_ids);
 
-/* Free a trie and its device image.  NULL is ignored. */
+/* Free a trie and its device image.  NULL is ignored.  Graphs captured
+ * with it must be freed first. */
 void pfac_trie_free(pfac_trie *t);
 
 /* Current / new launch parameters.  Setting them may rebuild the device
@@ -209,8 +210,9 @@ void pfac_trie_free(pfac_trie *t);
  * tables fit in LDS; the tile kernel runs otherwise.  Errors: PFAC_EINVAL
  * (NULL, a field out of range, dag combined with top_nodes or trunc_depth,
  * or a tuning whose kernel does not fit in LDS, e.g. bitmapped top nodes or
- * a level index too large; the previous tuning and image stay),
- * PFAC_ENOMEM, PFAC_EDEVICE. */
+ * a level index too large; the previous tuning and image stay), PFAC_EBUSY
+ * (the image would be rebuilt while a captured graph reads it), PFAC_ENOMEM,
+ * PFAC_EDEVICE. */
 int pfac_trie_get_tuning(const pfac_trie *t, pfac_tuning *out);
 int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tuning);
 
@@ -286,7 +288,13 @@ int pfac_scan_batch_plain(const pfac_trie *t, pfac_workspace *w, const uint8_t *
  * Capture pfac_scan_batch with these exact arguments into a HIP graph and
  * instantiate it.  Replays read the texts, offsets and outputs at the same
  * device addresses, so the caller may refill them between replays as long
- * as n_texts and total_bytes stay the same.
+ * as n_texts and total_bytes stay the same.  The graph allocates and owns
+ * its own scratch, so `w` is not used (it may be NULL) and stays free for
+ * other scans.  While the graph exists the trie's device image is pinned:
+ * a pfac_trie_set_tuning that would rebuild it (index_bits, fold_bits,
+ * trunc_depth or dag changed, as the autotuner may do) fails with
+ * PFAC_EBUSY, and the trie must outlive the graph.  Replays of one graph
+ * must not overlap each other.
  */
 int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w, const uint8_t *texts_dev,
                             const uint64_t *offsets_dev, uint32_t n_texts, uint64_t total_bytes,

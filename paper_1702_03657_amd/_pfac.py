@@ -320,14 +320,17 @@ def pfac_scan_batch_plain(trie: Trie, ws: Workspace, texts_dev, offsets_host: np
 class Graph:
     """``pfac_graph_create_batch``: a captured batched scan, replayed by ``launch``."""
 
-    def __init__(self, trie: Trie, ws: Workspace, texts_dev, offsets_dev, n_texts: int,
+    def __init__(self, trie: Trie, ws, texts_dev, offsets_dev, n_texts: int,
                  total_bytes: int, out_dev, capacity: int, n_matches_dev, stream=None):
+        """The graph owns its scratch (``ws`` is not used and may be None) and
+        pins the trie's device image until it is closed."""
         h = _vp()
         check("pfac_graph_create_batch", load().pfac_graph_create_batch(
-            trie.handle, ws.handle, _dptr(texts_dev), _dptr(offsets_dev), n_texts,
-            total_bytes, _dptr(out_dev), capacity, _dptr(n_matches_dev), _stream_ptr(stream),
-            ctypes.byref(h)))
+            trie.handle, ws.handle if ws is not None else None, _dptr(texts_dev),
+            _dptr(offsets_dev), n_texts, total_bytes, _dptr(out_dev), capacity,
+            _dptr(n_matches_dev), _stream_ptr(stream), ctypes.byref(h)))
         self.handle = h.value
+        self._trie = trie  # the trie must outlive the graph
 
     def launch(self, stream=None):
         check("pfac_graph_launch", load().pfac_graph_launch(self.handle, _stream_ptr(stream)))

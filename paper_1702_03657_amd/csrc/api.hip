@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstring>
 #include <map>
@@ -77,6 +78,8 @@ struct pfac_trie {
     // size of the merged DAG, computed on the first stats call
     mutable std::mutex dag_mu;
     mutable uint64_t dag_nodes = kNoSize, dag_edges = 0;
+    // captured graphs that read the current device image
+    mutable std::atomic<int> graphs{0};
 };
 
 struct pfac_workspace {
@@ -92,6 +95,8 @@ struct pfac_workspace {
 struct pfac_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    pfac_workspace *ws = nullptr;     // its own scratch, captured with it
+    const pfac_trie *t = nullptr;     // pinned: its image may not be replaced
 };
 
 extern "C" int pfac_last_hip_error(void) { return g_last_hip; }
@@ -470,6 +475,8 @@ extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
     if (!t || !tn || !valid_tuning(tn)) return PFAC_EINVAL;
     const bool repack = tn->index_bits != t->tuning.index_bits || tn->fold_bits != t->tuning.fold_bits ||
                         tn->trunc_depth != t->tuning.trunc_depth || tn->dag != t->tuning.dag;
+    // a captured graph reads the device image it was captured with
+    if (repack && t->graphs.load() > 0) return PFAC_EBUSY;
     // the new image is built aside; the trie changes only once it is complete
     DeviceImageHost fresh;
     if (repack) {
@@ -796,26 +803,35 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
                                        uint64_t *n_matches_dev, void *stream, pfac_graph **out) {
     if (!out) return PFAC_EINVAL;
     *out = nullptr;
-    int rc = check_scan_args(t, w, texts_dev, total_bytes, out_dev, capacity, n_matches_dev);
-    if (rc) return rc;
-    if (!offsets_dev) return PFAC_EINVAL;
-    rc = ws_reserve(w, tiles_for(total_bytes, 15, std::min(unit_bytes(t), kWaveChunk)), capacity,
-                    uses_split(t));
-    if (rc) return rc;
+    (void)w;  // the graph gets scratch of its own: `w` stays free for other scans
+    pfac_graph *g = new (std::nothrow) pfac_graph();
+    if (!g) return PFAC_ENOMEM;
+    int rc = pfac_workspace_create(&g->ws);
+    if (rc == PFAC_OK)
+        rc = check_scan_args(t, g->ws, texts_dev, total_bytes, out_dev, capacity, n_matches_dev);
+    if (rc == PFAC_OK && !offsets_dev) rc = PFAC_EINVAL;
+    if (rc == PFAC_OK)
+        rc = ws_reserve(g->ws, tiles_for(total_bytes, 15, std::min(unit_bytes(t), kWaveChunk)), capacity,
+                        uses_split(t));
+    if (rc != PFAC_OK) {
+        pfac_graph_free(g);
+        return rc;
+    }
+    g->t = t;
+    t->graphs++;
     hipStream_t s = (hipStream_t)stream;
     hipStream_t own = nullptr;
     if (!s) {
-        HIP_TRY(hipStreamCreateWithFlags(&own, hipStreamNonBlocking));
+        hipError_t ec = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
+        if (ec != hipSuccess) {
+            pfac_graph_free(g);
+            return hip_fail(ec);
+        }
         s = own;
-    }
-    pfac_graph *g = new (std::nothrow) pfac_graph();
-    if (!g) {
-        if (own) (void)hipStreamDestroy(own);
-        return PFAC_ENOMEM;
     }
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        Launch L{t, w, texts_dev, total_bytes, offsets_dev, n_texts, 0, out_dev, capacity,
+        Launch L{t, g->ws, texts_dev, total_bytes, offsets_dev, n_texts, 0, out_dev, capacity,
                  n_matches_dev, nullptr, nullptr, s};
         rc = enqueue_scan(L, false);
         hipError_t e2 = hipStreamEndCapture(s, &g->graph);
@@ -846,6 +862,8 @@ extern "C" void pfac_graph_free(pfac_graph *g) {
     if (!g) return;
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
+    pfac_workspace_free(g->ws);
+    if (g->t) g->t->graphs--;
     delete g;
 }
 

@@ -455,3 +455,51 @@ def test_wave_tunings_that_cannot_apply(name):
     got_b, n = gpu_scan_batch(trie, text, offs)
     assert n == want_b.n
     assert_same(got_b, want_b, with_text=True)
+
+
+def test_graph_owns_its_scratch_and_pins_the_image():
+    """A captured graph keeps replaying correctly while the workspace passed
+    at capture serves larger scans (the graph has scratch of its own), and
+    the trie's image cannot be rebuilt under it (PFAC_EBUSY) until it is
+    freed."""
+    import torch
+    rng = np.random.default_rng(91)
+    pats = workloads.make_patterns(rng, 500, 4, 24, "uniform").as_list()
+    small = rng.integers(0, 256, 100_000, dtype=np.uint8)
+    for at in rng.integers(0, small.size - 30, 300):
+        p = pats[int(rng.integers(0, len(pats)))]
+        small[at:at + len(p)] = np.frombuffer(p, dtype=np.uint8)
+    offs = np.array([0, 40_000, 40_000, small.size], dtype=np.uint64)
+    want = oracle.bucketed(small, pats, offsets=offs, threads=8)
+    trie = pf.Trie(pats)
+    ws = pf.Workspace()
+    text = torch.from_numpy(small).cuda()
+    offs_dev = torch.from_numpy(offs.view(np.int64)).cuda()
+    cap = want.n + 64
+    out = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    g = pf.Graph(trie, ws, text, offs_dev, 3, small.size, out, cap, cnt, s)
+    big = np.tile(small, 80)  # 8 MB: the same workspace grows for it
+    want_big = oracle.bucketed(big, pats, threads=8)
+    for rep in range(2):
+        got_big, _ = gpu_scan(trie, big, ws=ws, counts=False, capacity=want_big.n + 64)
+        assert_same(got_big, want_big)
+        out.fill_(0xAB)
+        torch.cuda.synchronize()
+        g.launch(s)
+        s.synchronize()
+        assert int(cnt.item()) == want.n, rep
+        assert_same(pf.matches_to_numpy(out, want.n), want, with_text=True)
+    tn = trie.tuning()
+    with pytest.raises(pf.PfacError) as e:
+        trie.set_tuning(index_bits=8 if tn["index_bits"] != 8 else 16)
+    assert e.value.code == pf.PFAC_EBUSY
+    trie.set_tuning(kernel=0)  # no rebuild: allowed, the graph keeps its own launch
+    g.launch(s)
+    s.synchronize()
+    assert int(cnt.item()) == want.n
+    g.close()
+    trie.set_tuning(index_bits=8 if tn["index_bits"] != 8 else 16)  # free to rebuild now
+    got, _ = gpu_scan(trie, small[:40_000], counts=False)
+    assert_same(got, oracle.bucketed(small[:40_000], pats, threads=8))
