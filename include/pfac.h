@@ -211,8 +211,8 @@ void pfac_trie_free(pfac_trie *t);
  * (NULL, a field out of range, dag combined with top_nodes or trunc_depth,
  * or a tuning whose kernel does not fit in LDS, e.g. bitmapped top nodes or
  * a level index too large; the previous tuning and image stay), PFAC_EBUSY
- * (the image would be rebuilt while a captured graph reads it), PFAC_ENOMEM,
- * PFAC_EDEVICE. */
+ * (the image would be rebuilt while a captured graph or a server reads it),
+ * PFAC_ENOMEM, PFAC_EDEVICE. */
 int pfac_trie_get_tuning(const pfac_trie *t, pfac_tuning *out);
 int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tuning);
 
@@ -327,6 +327,8 @@ int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev, uint
  * A worker thread admits queued requests in arrival order as budget and
  * slots free up, copies them to the device, and launches one batched scan
  * over every request whose copy has landed while the previous batch runs.
+ * The trie must outlive the server, and its device image is pinned while
+ * the server exists (see pfac_trie_set_tuning, PFAC_EBUSY).
  */
 int pfac_server_create(const pfac_trie *t, void *arena_dev, uint64_t arena_bytes,
                        uint64_t budget_bytes, uint32_t max_batch, void *compute_stream,

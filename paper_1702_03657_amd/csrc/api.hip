@@ -78,8 +78,8 @@ struct pfac_trie {
     // size of the merged DAG, computed on the first stats call
     mutable std::mutex dag_mu;
     mutable uint64_t dag_nodes = kNoSize, dag_edges = 0;
-    // captured graphs that read the current device image
-    mutable std::atomic<int> graphs{0};
+    // captured graphs and servers that read the current device image
+    mutable std::atomic<int> pins{0};
 };
 
 struct pfac_workspace {
@@ -475,8 +475,8 @@ extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
     if (!t || !tn || !valid_tuning(tn)) return PFAC_EINVAL;
     const bool repack = tn->index_bits != t->tuning.index_bits || tn->fold_bits != t->tuning.fold_bits ||
                         tn->trunc_depth != t->tuning.trunc_depth || tn->dag != t->tuning.dag;
-    // a captured graph reads the device image it was captured with
-    if (repack && t->graphs.load() > 0) return PFAC_EBUSY;
+    // captured graphs and servers read the device image they started with
+    if (repack && t->pins.load() > 0) return PFAC_EBUSY;
     // the new image is built aside; the trie changes only once it is complete
     DeviceImageHost fresh;
     if (repack) {
@@ -794,6 +794,11 @@ extern "C" int pfac_scan_batch_plain(const pfac_trie *t, pfac_workspace *w,
     return PFAC_OK;
 }
 
+namespace pfac {
+// Servers keep the image of their trie while they run (declared in server.hip).
+void trie_pin(const pfac_trie *t, int delta) { t->pins += delta; }
+}  // namespace pfac
+
 // ------------------------------------------------------------------- graphs
 
 extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
@@ -818,7 +823,7 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
         return rc;
     }
     g->t = t;
-    t->graphs++;
+    t->pins++;
     hipStream_t s = (hipStream_t)stream;
     hipStream_t own = nullptr;
     if (!s) {
@@ -863,7 +868,7 @@ extern "C" void pfac_graph_free(pfac_graph *g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     pfac_workspace_free(g->ws);
-    if (g->t) g->t->graphs--;
+    if (g->t) g->t->pins--;
     delete g;
 }
 

@@ -26,6 +26,11 @@
 #include "../../include/pfac.h"
 #include "text_ring.hpp"
 
+namespace pfac {
+// +1 / -1: a server runs on the trie's current device image (defined with the trie)
+void trie_pin(const pfac_trie *t, int delta);
+}  // namespace pfac
+
 namespace {
 
 using clk = std::chrono::steady_clock;
@@ -356,6 +361,7 @@ extern "C" int pfac_server_create(const pfac_trie *t, void *arena_dev, uint64_t 
         delete s;
         return rc;
     }
+    pfac::trie_pin(t, +1);
     s->worker = std::thread([s] { s->run(); });
     *out = s;
     return PFAC_OK;
@@ -493,5 +499,6 @@ extern "C" void pfac_server_free(pfac_server *s) {
     // are requests nobody waited for or cancelled
     for (auto &kv : s->by_id) free_req(kv.second);
     if (s->ds) (void)hipStreamDestroy(s->ds);
+    pfac::trie_pin(s->t, -1);
     delete s;
 }

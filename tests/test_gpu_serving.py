@@ -275,3 +275,24 @@ def test_random_servers_with_cancellation():
         del buf
     say(f"random servers: {checked} checked, {cancelled} cancelled")
     assert checked > 500 and cancelled > 150
+
+
+def test_server_pins_the_trie_image():
+    """While a server runs, a tuning that would rebuild its trie's device
+    image is refused (PFAC_EBUSY) and requests keep their results; after the
+    server is freed the image can be rebuilt."""
+    pats = [b"abc", b"bcd", b"zz"]
+    trie = pf.Trie(pats)
+    srv, _buf = _server(trie, 1 << 16, (1 << 16) + (1 << 20), 4)
+    t = np.frombuffer(b"xxabcdzzz" * 500, dtype=np.uint8).copy()
+    rid = srv.submit(t)
+    bits = trie.tuning()["index_bits"]
+    with pytest.raises(pf.PfacError) as e:
+        trie.set_tuning(index_bits=8 if bits != 8 else 16)
+    assert e.value.code == pf.PFAC_EBUSY
+    got, _ = srv.wait(rid, capacity=1 << 14)
+    assert_same(got, oracle.brute(t, pats))
+    srv.close()
+    trie.set_tuning(index_bits=8 if bits != 8 else 16)
+    got, _ = gpu_scan(trie, t, counts=False)
+    assert_same(got, oracle.brute(t, pats))
