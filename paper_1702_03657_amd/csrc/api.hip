@@ -145,45 +145,64 @@ static int upload_image(pfac_trie *t) {
     size_t o_ldag = align256(o_rlist + std::max<size_t>(I.rank_list.size(), 2) * 4);
     size_t total = align256(o_ldag + std::max<size_t>(I.lvl_dag.size(), 2) * 4);
     auto t0 = std::chrono::steady_clock::now();
-    t->dev.release();
-    HIP_TRY(t->dev.reserve(total));
-    uint8_t *b = (uint8_t *)t->dev.p;
-    HIP_TRY(hipMemcpy(b + o_node, I.node.data(), I.node.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b + o_label, I.label.data(), I.label.size(), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b + o_pptr, I.pout_ptr.data(), I.pout_ptr.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b + o_pids, I.pout_ids.data(), I.pout_ids.size() * 4, hipMemcpyHostToDevice));
-    if (!I.lvl.empty())
-        HIP_TRY(hipMemcpy(b + o_lvl, I.lvl.data(), I.lvl.size() * 4, hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy(b + o_sym, I.sym.data(), 256, hipMemcpyHostToDevice));
-    if (!I.ftab.empty())
-        HIP_TRY(hipMemcpy(b + o_ftab, I.ftab.data(), I.ftab.size(), hipMemcpyHostToDevice));
-    if (!I.krec.empty())
-        HIP_TRY(hipMemcpy(b + o_krec, I.krec.data(), I.krec.size() * 4, hipMemcpyHostToDevice));
-    if (!I.chain.empty())
-        HIP_TRY(hipMemcpy(b + o_chain, I.chain.data(), I.chain.size(), hipMemcpyHostToDevice));
-    if (!I.pfx4.empty())
-        HIP_TRY(hipMemcpy(b + o_pfx4, I.pfx4.data(), I.pfx4.size() * 4, hipMemcpyHostToDevice));
-    if (!I.q16.empty())
-        HIP_TRY(hipMemcpy(b + o_q16, I.q16.data(), I.q16.size() * 4, hipMemcpyHostToDevice));
-    if (!I.qfp.empty())
-        HIP_TRY(hipMemcpy(b + o_qfp, I.qfp.data(), I.qfp.size() * 2, hipMemcpyHostToDevice));
-    if (!I.root_bits.empty())
-        HIP_TRY(hipMemcpy(b + o_root, I.root_bits.data(), I.root_bits.size() * 4, hipMemcpyHostToDevice));
-    if (!I.top.empty())
-        HIP_TRY(hipMemcpy(b + o_top, I.top.data(), I.top.size() * 4, hipMemcpyHostToDevice));
-    if (!I.tail.empty())
-        HIP_TRY(hipMemcpy(b + o_tail, I.tail.data(), I.tail.size() * 4, hipMemcpyHostToDevice));
-    if (!I.tail_bytes.empty())
-        HIP_TRY(hipMemcpy(b + o_tailb, I.tail_bytes.data(), I.tail_bytes.size(), hipMemcpyHostToDevice));
-    if (I.dag) {
-        HIP_TRY(hipMemcpy(b + o_dnode, I.dnode.data(), I.dnode.size() * 4, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(b + o_dlabel, I.dlabel.data(), I.dlabel.size(), hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(b + o_dchild, I.dchild.data(), I.dchild.size() * 4, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(b + o_dradd, I.dradd.data(), I.dradd.size() * 4, hipMemcpyHostToDevice));
-        HIP_TRY(hipMemcpy(b + o_rlist, I.rank_list.data(), I.rank_list.size() * 4, hipMemcpyHostToDevice));
-        if (!I.lvl_dag.empty())
-            HIP_TRY(hipMemcpy(b + o_ldag, I.lvl_dag.data(), I.lvl_dag.size() * 4, hipMemcpyHostToDevice));
+    // the new image is built beside the old one, which stays usable if this fails
+    DeviceBuf fresh;
+    HIP_TRY(fresh.reserve(total));
+    uint8_t *b = (uint8_t *)fresh.p;
+#define CP(expr)                                   \
+    do {                                           \
+        hipError_t e_ = (expr);                    \
+        if (e_ != hipSuccess) return e_;           \
+    } while (0)
+    auto copy_all = [&]() -> hipError_t {
+        CP(hipMemcpy(b + o_node, I.node.data(), I.node.size() * 4, hipMemcpyHostToDevice));
+        CP(hipMemcpy(b + o_label, I.label.data(), I.label.size(), hipMemcpyHostToDevice));
+        CP(hipMemcpy(b + o_pptr, I.pout_ptr.data(), I.pout_ptr.size() * 4, hipMemcpyHostToDevice));
+        CP(hipMemcpy(b + o_pids, I.pout_ids.data(), I.pout_ids.size() * 4, hipMemcpyHostToDevice));
+        if (!I.lvl.empty())
+            CP(hipMemcpy(b + o_lvl, I.lvl.data(), I.lvl.size() * 4, hipMemcpyHostToDevice));
+        CP(hipMemcpy(b + o_sym, I.sym.data(), 256, hipMemcpyHostToDevice));
+        if (!I.ftab.empty())
+            CP(hipMemcpy(b + o_ftab, I.ftab.data(), I.ftab.size(), hipMemcpyHostToDevice));
+        if (!I.krec.empty())
+            CP(hipMemcpy(b + o_krec, I.krec.data(), I.krec.size() * 4, hipMemcpyHostToDevice));
+        if (!I.chain.empty())
+            CP(hipMemcpy(b + o_chain, I.chain.data(), I.chain.size(), hipMemcpyHostToDevice));
+        if (!I.pfx4.empty())
+            CP(hipMemcpy(b + o_pfx4, I.pfx4.data(), I.pfx4.size() * 4, hipMemcpyHostToDevice));
+        if (!I.q16.empty())
+            CP(hipMemcpy(b + o_q16, I.q16.data(), I.q16.size() * 4, hipMemcpyHostToDevice));
+        if (!I.qfp.empty())
+            CP(hipMemcpy(b + o_qfp, I.qfp.data(), I.qfp.size() * 2, hipMemcpyHostToDevice));
+        if (!I.root_bits.empty())
+            CP(hipMemcpy(b + o_root, I.root_bits.data(), I.root_bits.size() * 4, hipMemcpyHostToDevice));
+        if (!I.top.empty())
+            CP(hipMemcpy(b + o_top, I.top.data(), I.top.size() * 4, hipMemcpyHostToDevice));
+        if (!I.tail.empty())
+            CP(hipMemcpy(b + o_tail, I.tail.data(), I.tail.size() * 4, hipMemcpyHostToDevice));
+        if (!I.tail_bytes.empty())
+            CP(hipMemcpy(b + o_tailb, I.tail_bytes.data(), I.tail_bytes.size(), hipMemcpyHostToDevice));
+        if (I.dag) {
+            CP(hipMemcpy(b + o_dnode, I.dnode.data(), I.dnode.size() * 4, hipMemcpyHostToDevice));
+            CP(hipMemcpy(b + o_dlabel, I.dlabel.data(), I.dlabel.size(), hipMemcpyHostToDevice));
+            CP(hipMemcpy(b + o_dchild, I.dchild.data(), I.dchild.size() * 4, hipMemcpyHostToDevice));
+            CP(hipMemcpy(b + o_dradd, I.dradd.data(), I.dradd.size() * 4, hipMemcpyHostToDevice));
+            CP(hipMemcpy(b + o_rlist, I.rank_list.data(), I.rank_list.size() * 4, hipMemcpyHostToDevice));
+            if (!I.lvl_dag.empty())
+                CP(hipMemcpy(b + o_ldag, I.lvl_dag.data(), I.lvl_dag.size() * 4, hipMemcpyHostToDevice));
+        }
+        return hipSuccess;
+    };
+#undef CP
+    const hipError_t ce = copy_all();
+    if (ce != hipSuccess) {
+        fresh.release();
+        return hip_fail(ce);
     }
+    // no kernel may still be reading the image it replaces
+    if (t->dev.p) (void)hipDeviceSynchronize();
+    std::swap(t->dev, fresh);
+    fresh.release();
     ImageView &v = t->view;
     v.node = (const uint4 *)(b + o_node);
     v.label = b + o_label;
@@ -497,7 +516,14 @@ extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
         if (repack) std::swap(t->img, fresh);
         return PFAC_EINVAL;
     }
-    if (repack && !t->host_only) return upload_image(t);
+    if (repack && !t->host_only) {
+        const int rc = upload_image(t);
+        if (rc != PFAC_OK) {  // the previous device image is still in place
+            t->tuning = old;
+            std::swap(t->img, fresh);
+        }
+        return rc;
+    }
     return PFAC_OK;
 }
 
