@@ -44,9 +44,11 @@ struct DeviceBuf {
         p = nullptr;
         bytes = 0;
     }
-    // grow to at least `need` bytes; contents are not preserved
+    // grow to at least `need` bytes; contents are not preserved.  Work still
+    // queued on any stream may use the old buffer: the device drains first.
     hipError_t reserve(size_t need) {
         if (need <= bytes) return hipSuccess;
+        if (p) (void)hipDeviceSynchronize();
         release();
         size_t want = std::max<size_t>(need, 256);
         hipError_t e = hipMalloc(&p, want);
