@@ -223,7 +223,10 @@ int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tuning);
 int pfac_workspace_create(pfac_workspace **out);
 void pfac_workspace_free(pfac_workspace *w);
 /* Pre-size the scratch for texts of up to `max_bytes` bytes, `max_texts`
- * texts and `max_matches` matches, so later scans allocate nothing.
+ * texts and `max_matches` matches, so later scans allocate nothing.  Growing
+ * a workspace (here or inside a scan that needs more) first waits for the
+ * whole device, since queued work may still use the old buffers: reserve
+ * before capturing a stream that scans with it.
  * Errors: PFAC_EINVAL (w NULL), PFAC_ENOMEM (the device cannot hold it; the
  * workspace stays usable for smaller scans), PFAC_EDEVICE. */
 int pfac_workspace_reserve(pfac_workspace *w, uint64_t max_bytes, uint32_t max_texts,
