@@ -211,8 +211,9 @@ void pfac_trie_free(pfac_trie *t);
  * (NULL, a field out of range, dag combined with top_nodes or trunc_depth,
  * or a tuning whose kernel does not fit in LDS, e.g. bitmapped top nodes or
  * a level index too large; the previous tuning and image stay), PFAC_EBUSY
- * (the image would be rebuilt while a captured graph or a server reads it),
- * PFAC_ENOMEM, PFAC_EDEVICE. */
+ * (the image would be rebuilt while a captured graph reads it, or the tuning
+ * would change at all while a server uses the trie), PFAC_ENOMEM,
+ * PFAC_EDEVICE. */
 int pfac_trie_get_tuning(const pfac_trie *t, pfac_tuning *out);
 int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tuning);
 
@@ -316,6 +317,17 @@ void pfac_graph_free(pfac_graph *g);
 int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev, uint64_t n,
                   void *stream, pfac_tuning *best);
 
+/*
+ * pfac_autotune for the batched launch: every candidate scans the batch
+ * (texts_dev, offsets_dev, n_texts, total_bytes as in pfac_scan_batch) and
+ * its list is checked against the starting tuning's.  Cached per (trie,
+ * total size bucket, mean text size bucket), apart from single texts.
+ * Synchronous.  PFAC_EBUSY while a server uses the trie.
+ */
+int pfac_autotune_batch(pfac_trie *t, pfac_workspace *w, const uint8_t *texts_dev,
+                        const uint64_t *offsets_dev, uint32_t n_texts, uint64_t total_bytes,
+                        void *stream, pfac_tuning *best);
+
 /* ---------------------------------------------------------------- serving */
 
 /*
@@ -330,8 +342,11 @@ int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev, uint
  * A worker thread admits queued requests in arrival order as budget and
  * slots free up, copies them to the device, and launches one batched scan
  * over every request whose copy has landed while the previous batch runs.
- * The trie must outlive the server, and its device image is pinned while
- * the server exists (see pfac_trie_set_tuning, PFAC_EBUSY).
+ * The trie must outlive the server, and its tuning and device image are
+ * fixed while the server exists: pfac_trie_set_tuning with a different
+ * tuning, and pfac_autotune / pfac_autotune_batch, fail with PFAC_EBUSY.
+ * Device memory: the arena, plus the scratch of two batch slots that the
+ * server allocates itself (reported by pfac_server_stats).
  */
 int pfac_server_create(const pfac_trie *t, void *arena_dev, uint64_t arena_bytes,
                        uint64_t budget_bytes, uint32_t max_batch, void *compute_stream,
@@ -373,9 +388,15 @@ int pfac_server_wait(pfac_server *s, uint64_t request_id, int64_t timeout_ms,
  */
 int pfac_server_cancel(pfac_server *s, uint64_t request_id);
 
-/* Counters since creation: requests completed, batches launched, text bytes scanned. */
+/* Counters since creation: requests completed, batches launched, text bytes
+ * scanned; and device_bytes, the device memory the server allocated itself
+ * beyond the caller's arena: the scratch of its two batch slots, each sized
+ * for a batch of budget_bytes of text (about 0.65 bytes per text byte:
+ * per-chunk counts, inline records and walk candidates) plus match staging
+ * for the slot's output capacity (16 bytes per record).  Any pointer may be
+ * NULL. */
 int pfac_server_stats(const pfac_server *s, uint64_t *requests, uint64_t *batches,
-                      uint64_t *bytes);
+                      uint64_t *bytes, uint64_t *device_bytes);
 
 /* Finish every queued request, stop the worker and free the server.  No other
  * call on the server may run during or after it. */

@@ -102,6 +102,8 @@ static uint64_t load_key(const uint8_t *p, uint32_t m) {
     return x;
 }
 
+/* Hash-table index mixing: the 64-bit finalizer (fmix64) of Austin Appleby's
+ * published MurmurHash3. */
 static inline uint64_t hmix(uint64_t x) {
     x ^= x >> 33; x *= 0xff51afd7ed558ccdULL;
     x ^= x >> 33; x *= 0xc4ceb9fe1a85ec53ULL;

@@ -26,6 +26,7 @@ from ._pfac import (  # noqa: F401
     load,
     matches_to_numpy,
     pfac_autotune,
+    pfac_autotune_batch,
     pfac_scan,
     pfac_scan_batch,
     pfac_scan_batch_plain,

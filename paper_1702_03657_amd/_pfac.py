@@ -106,12 +106,14 @@ SIGNATURES = [
     ("pfac_graph_launch", ctypes.c_int, [_vp, _vp]),
     ("pfac_graph_free", None, [_vp]),
     ("pfac_autotune", ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _p(pfac_tuning)]),
+    ("pfac_autotune_batch", ctypes.c_int,
+     [_vp, _vp, _vp, _vp, _u32, _u64, _vp, _p(pfac_tuning)]),
     ("pfac_server_create", ctypes.c_int, [_vp, _vp, _u64, _u64, _u32, _vp, _vp, _p(_vp)]),
     ("pfac_server_submit", ctypes.c_int, [_vp, _vp, _u64, _p(_u64)]),
     ("pfac_server_wait", ctypes.c_int,
      [_vp, _u64, _i64, _vp, _u64, _p(_u64), _p(ctypes.c_double)]),
     ("pfac_server_cancel", ctypes.c_int, [_vp, _u64]),
-    ("pfac_server_stats", ctypes.c_int, [_vp, _p(_u64), _p(_u64), _p(_u64)]),
+    ("pfac_server_stats", ctypes.c_int, [_vp, _p(_u64), _p(_u64), _p(_u64), _p(_u64)]),
     ("pfac_server_free", None, [_vp]),
 ]
 
@@ -354,6 +356,15 @@ def pfac_autotune(trie: Trie, ws: Workspace, text_dev, n: int, stream=None) -> d
     return {name: getattr(t, name) for name, _ in t._fields_}
 
 
+def pfac_autotune_batch(trie: Trie, ws: Workspace, texts_dev, offsets_dev, n_texts: int,
+                        total_bytes: int, stream=None) -> dict:
+    t = pfac_tuning()
+    check("pfac_autotune_batch", load().pfac_autotune_batch(
+        trie.handle, ws.handle, _dptr(texts_dev), _dptr(offsets_dev), n_texts, total_bytes,
+        _stream_ptr(stream), ctypes.byref(t)))
+    return {name: getattr(t, name) for name, _ in t._fields_}
+
+
 class Server:
     """``pfac_server_*``: continuous-batching scans into a caller-owned device arena."""
 
@@ -366,6 +377,9 @@ class Server:
             ctypes.byref(h)))
         self.handle = h.value
         self._keep = {}
+        # the worker thread uses these until close(): keep them alive
+        self._trie, self._arena = trie, arena_dev
+        self._streams = (compute_stream, copy_stream)
 
     def submit(self, text_host: np.ndarray) -> int:
         """Queue a scan of a host uint8 array (kept alive until waited for)."""
@@ -404,15 +418,18 @@ class Server:
         self._keep.pop(request_id, None)
 
     def stats(self) -> dict:
-        r, b, y = _u64(0), _u64(0), _u64(0)
-        check("pfac_server_stats", load().pfac_server_stats(self.handle, ctypes.byref(r),
-                                                            ctypes.byref(b), ctypes.byref(y)))
-        return {"requests": r.value, "batches": b.value, "bytes": y.value}
+        r, b, y, d = _u64(0), _u64(0), _u64(0), _u64(0)
+        check("pfac_server_stats", load().pfac_server_stats(
+            self.handle, ctypes.byref(r), ctypes.byref(b), ctypes.byref(y), ctypes.byref(d)))
+        return {"requests": r.value, "batches": b.value, "bytes": y.value,
+                "device_bytes": d.value}
 
     def close(self):
         if getattr(self, "handle", None):
             load().pfac_server_free(self.handle)
             self.handle = None
+        self._keep = {}
+        self._trie = self._arena = self._streams = None
 
     def __del__(self):
         try:

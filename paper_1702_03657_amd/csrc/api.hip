@@ -82,6 +82,8 @@ struct pfac_trie {
     mutable uint64_t dag_nodes = kNoSize, dag_edges = 0;
     // captured graphs and servers that read the current device image
     mutable std::atomic<int> pins{0};
+    // servers, whose worker reads the whole tuning at every launch
+    mutable std::atomic<int> tuning_pins{0};
 };
 
 struct pfac_workspace {
@@ -492,8 +494,14 @@ static bool valid_tuning(const pfac_tuning *p) {
            !(p->dag && (p->top_nodes || p->trunc_depth));
 }
 
+static bool same_tuning(const pfac_tuning &a, const pfac_tuning &b) {
+    return std::memcmp(&a, &b, sizeof(pfac_tuning)) == 0;
+}
+
 extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
     if (!t || !tn || !valid_tuning(tn)) return PFAC_EINVAL;
+    // a server's worker thread reads the tuning at every launch
+    if (t->tuning_pins.load() > 0 && !same_tuning(*tn, t->tuning)) return PFAC_EBUSY;
     const bool repack = tn->index_bits != t->tuning.index_bits || tn->fold_bits != t->tuning.fold_bits ||
                         tn->trunc_depth != t->tuning.trunc_depth || tn->dag != t->tuning.dag;
     // captured graphs and servers read the device image they started with
@@ -823,8 +831,18 @@ extern "C" int pfac_scan_batch_plain(const pfac_trie *t, pfac_workspace *w,
 }
 
 namespace pfac {
-// Servers keep the image of their trie while they run (declared in server.hip).
-void trie_pin(const pfac_trie *t, int delta) { t->pins += delta; }
+// Servers keep the image and the tuning of their trie while they run
+// (declared in server.hip).
+void trie_pin(const pfac_trie *t, int delta) {
+    t->pins += delta;
+    t->tuning_pins += delta;
+}
+uint64_t workspace_device_bytes(const pfac_workspace *w) {
+    if (!w) return 0;
+    return w->stage.bytes + w->unit_count.bytes + w->unit_off.bytes + w->blocksum.bytes +
+           w->tile_first.bytes + w->inline_stage.bytes + w->misc.bytes + w->cand.bytes +
+           w->cand_count.bytes;
+}
 }  // namespace pfac
 
 // ------------------------------------------------------------------- graphs
@@ -908,13 +926,30 @@ static uint32_t size_bucket(uint64_t n) {
     return b;
 }
 
-extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev, uint64_t n,
-                             void *stream, pfac_tuning *best) {
-    if (!t || !w || (!text_dev && n) || !best) return PFAC_EINVAL;
+// One scan of the text (or batch) being tuned for: writes up to `cap`
+// matches to out and the count to *dcount, asynchronously on `stream`.
+typedef int (*tune_scan_fn)(const void *ctx, const pfac_trie *t, pfac_workspace *w,
+                            pfac_match *out, uint64_t cap, uint64_t *dcount, void *stream);
+
+static int tune_scan_sync(const void *ctx, tune_scan_fn scan, const pfac_trie *t, pfac_workspace *w,
+                          pfac_match *out, uint64_t cap, uint64_t *n_host, void *stream) {
+    uint64_t *dcount = w->tmp_count();
+    int rc = scan(ctx, t, w, out, cap, dcount, stream);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(n_host, dcount, 8, hipMemcpyDeviceToHost, (hipStream_t)stream));
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    return *n_host > cap ? PFAC_ETRUNC : PFAC_OK;
+}
+
+// Time every candidate tuning on one input, keep the fastest whose match
+// list equals the starting tuning's, cache it under `key`.
+static int autotune_common(pfac_trie *t, pfac_workspace *w, const void *ctx, tune_scan_fn scan,
+                           uint32_t key, void *stream, pfac_tuning *best) {
     if (t->host_only) return PFAC_ENODEV;
+    // a server reads this trie's tuning at every launch
+    if (t->tuning_pins.load() > 0) return PFAC_EBUSY;
     std::lock_guard<std::mutex> lock(t->mu);
-    const uint32_t bucket = size_bucket(n);
-    auto it = t->tuned.find(bucket);
+    auto it = t->tuned.find(key);
     if (it != t->tuned.end()) {
         *best = it->second;
         return pfac_trie_set_tuning(t, best);
@@ -925,24 +960,43 @@ extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *tex
 
     // reference list with the starting parameters
     uint64_t ref_n = 0;
-    int rc = pfac_scan_sync(t, w, text_dev, n, nullptr, 0, &ref_n, nullptr, stream);
+    int rc = tune_scan_sync(ctx, scan, t, w, nullptr, 0, &ref_n, stream);
     if (rc != PFAC_OK && rc != PFAC_ETRUNC) return rc;
     const uint64_t cap = ref_n;
     pfac_match *dref = nullptr, *dcand = nullptr;
-    if (cap) {
-        HIP_TRY(hipMalloc(&dref, cap * sizeof(pfac_match)));
-        if (hipMalloc(&dcand, cap * sizeof(pfac_match)) != hipSuccess) {
-            (void)hipFree(dref);
-            return PFAC_ENOMEM;
-        }
-    }
-    std::vector<pfac_match> href(cap), hcand(cap);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
     auto cleanup = [&] {
         if (dref) (void)hipFree(dref);
         if (dcand) (void)hipFree(dcand);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
     };
+    if (cap) {
+        hipError_t e = hipMalloc(&dref, cap * sizeof(pfac_match));
+        if (e == hipSuccess) e = hipMalloc(&dcand, cap * sizeof(pfac_match));
+        if (e != hipSuccess) {
+            cleanup();
+            return hip_fail(e);
+        }
+    }
+    {
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e != hipSuccess) {
+            cleanup();
+            return hip_fail(e);
+        }
+    }
+    std::vector<pfac_match> href, hcand;
+    try {
+        href.resize(cap);
+        hcand.resize(cap);
+    } catch (const std::bad_alloc &) {
+        cleanup();
+        return PFAC_ENOMEM;
+    }
     uint64_t got = 0;
-    rc = pfac_scan_sync(t, w, text_dev, n, dref, cap, &got, nullptr, stream);
+    rc = tune_scan_sync(ctx, scan, t, w, dref, cap, &got, stream);
     if (rc == PFAC_OK && cap)
         if (hipMemcpy(href.data(), dref, cap * sizeof(pfac_match), hipMemcpyDeviceToHost) != hipSuccess)
             rc = PFAC_EDEVICE;
@@ -951,9 +1005,6 @@ extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *tex
         return rc;
     }
 
-    hipEvent_t e0, e1;
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
     std::vector<pfac_tuning> cands;
     for (uint32_t bits : {12u, 16u, 18u}) {
         for (uint32_t fold : {8u, 16u, 0u})
@@ -978,15 +1029,15 @@ extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *tex
     for (const pfac_tuning &c : cands) {
         if (pfac_trie_set_tuning(t, &c) != PFAC_OK) continue;
         // index widths that give the same depth K and symbol width repeat a point
-        const uint64_t key = ((uint64_t)c.kernel << 60) | ((uint64_t)c.bytes_per_lane << 48) |
-                             ((uint64_t)t->img.K << 40) | ((uint64_t)t->img.b << 32) |
-                             ((uint64_t)t->img.fold_bits << 24) | ((uint64_t)c.waves_per_wg << 16) |
-                             ((uint64_t)c.chunks_per_unit << 8) | ((uint64_t)c.child_check << 4) |
-                             c.wg_per_cu;
-        if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
-        seen.push_back(key);
+        const uint64_t k = ((uint64_t)c.kernel << 60) | ((uint64_t)c.bytes_per_lane << 48) |
+                           ((uint64_t)t->img.K << 40) | ((uint64_t)t->img.b << 32) |
+                           ((uint64_t)t->img.fold_bits << 24) | ((uint64_t)c.waves_per_wg << 16) |
+                           ((uint64_t)c.chunks_per_unit << 8) | ((uint64_t)c.child_check << 4) |
+                           c.wg_per_cu;
+        if (std::find(seen.begin(), seen.end(), k) != seen.end()) continue;
+        seen.push_back(k);
         uint64_t cn = 0;
-        if (pfac_scan_sync(t, w, text_dev, n, dcand, cap, &cn, nullptr, stream) != PFAC_OK) continue;
+        if (tune_scan_sync(ctx, scan, t, w, dcand, cap, &cn, stream) != PFAC_OK) continue;
         if (cn != ref_n) continue;
         if (cap && (hipMemcpy(hcand.data(), dcand, cap * sizeof(pfac_match), hipMemcpyDeviceToHost) != hipSuccess ||
                     std::memcmp(hcand.data(), href.data(), cap * sizeof(pfac_match)) != 0))
@@ -994,7 +1045,7 @@ extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *tex
         std::vector<float> ms;
         for (int rep = 0; rep < 5; rep++) {
             (void)hipEventRecord(e0, s);
-            if (pfac_scan(t, w, text_dev, n, dcand, cap, dcount, nullptr, stream) != PFAC_OK) break;
+            if (scan(ctx, t, w, dcand, cap, dcount, stream) != PFAC_OK) break;
             (void)hipEventRecord(e1, s);
             (void)hipEventSynchronize(e1);
             float m = 0;
@@ -1008,10 +1059,52 @@ extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *tex
             best_t = c;
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     cleanup();
-    t->tuned[bucket] = best_t;
+    t->tuned[key] = best_t;
     *best = best_t;
     return pfac_trie_set_tuning(t, &best_t);
+}
+
+struct TuneText {
+    const uint8_t *text;
+    uint64_t n;
+};
+
+static int tune_scan_text(const void *ctx, const pfac_trie *t, pfac_workspace *w, pfac_match *out,
+                          uint64_t cap, uint64_t *dcount, void *stream) {
+    const TuneText *x = (const TuneText *)ctx;
+    return pfac_scan(t, w, x->text, x->n, out, cap, dcount, nullptr, stream);
+}
+
+struct TuneBatch {
+    const uint8_t *texts;
+    const uint64_t *offsets;
+    uint32_t n_texts;
+    uint64_t total;
+};
+
+static int tune_scan_batch(const void *ctx, const pfac_trie *t, pfac_workspace *w, pfac_match *out,
+                           uint64_t cap, uint64_t *dcount, void *stream) {
+    const TuneBatch *x = (const TuneBatch *)ctx;
+    return pfac_scan_batch(t, w, x->texts, x->offsets, x->n_texts, x->total, out, cap, dcount, stream);
+}
+
+extern "C" int pfac_autotune(pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev, uint64_t n,
+                             void *stream, pfac_tuning *best) {
+    if (!t || !w || (!text_dev && n) || !best) return PFAC_EINVAL;
+    const TuneText x{text_dev, n};
+    return autotune_common(t, w, &x, tune_scan_text, size_bucket(n), stream, best);
+}
+
+extern "C" int pfac_autotune_batch(pfac_trie *t, pfac_workspace *w, const uint8_t *texts_dev,
+                                   const uint64_t *offsets_dev, uint32_t n_texts,
+                                   uint64_t total_bytes, void *stream, pfac_tuning *best) {
+    if (!t || !w || !offsets_dev || (!texts_dev && total_bytes) || !best ||
+        (n_texts == 0 && total_bytes != 0))
+        return PFAC_EINVAL;
+    const TuneBatch x{texts_dev, offsets_dev, n_texts, total_bytes};
+    // batches are cached apart from single texts, by total size and mean text size
+    const uint32_t key = (1u << 16) | (size_bucket(n_texts ? total_bytes / n_texts : 0) << 8) |
+                         size_bucket(total_bytes);
+    return autotune_common(t, w, &x, tune_scan_batch, key, stream, best);
 }

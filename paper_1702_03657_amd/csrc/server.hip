@@ -27,8 +27,11 @@
 #include "text_ring.hpp"
 
 namespace pfac {
-// +1 / -1: a server runs on the trie's current device image (defined with the trie)
+// +1 / -1: a server runs on the trie's current device image and tuning
+// (defined with the trie)
 void trie_pin(const pfac_trie *t, int delta);
+// device bytes a workspace holds
+uint64_t workspace_device_bytes(const pfac_workspace *w);
 }  // namespace pfac
 
 namespace {
@@ -272,6 +275,14 @@ struct pfac_server {
                     if (!b.empty()) {
                         int rc = launch(S, b);
                         if (rc != PFAC_OK) {
+                            // part of the batch may have been queued: let the
+                            // compute stream and the batch's copies finish
+                            // before its requests end and their ring bytes
+                            // (and host texts) are given back
+                            (void)hipStreamSynchronize(cs);
+                            for (Req *r : b)
+                                if (r->copied) (void)hipEventSynchronize(r->copied);
+                            (void)hipGetLastError();
                             for (Req *r : b) {
                                 r->rc = rc;
                                 r->st = St::Done;
@@ -470,13 +481,18 @@ extern "C" int pfac_server_cancel(pfac_server *s, uint64_t request_id) {
 }
 
 extern "C" int pfac_server_stats(const pfac_server *s, uint64_t *requests, uint64_t *batches,
-                                 uint64_t *bytes) {
+                                 uint64_t *bytes, uint64_t *device_bytes) {
     if (!s) return PFAC_EINVAL;
     pfac_server *m = const_cast<pfac_server *>(s);
     std::lock_guard<std::mutex> lock(m->mu);
     if (requests) *requests = s->stat_req;
     if (batches) *batches = s->stat_batches;
     if (bytes) *bytes = s->stat_bytes;
+    if (device_bytes) {
+        uint64_t d = 0;
+        for (const Slot &S : s->slot) d += pfac::workspace_device_bytes(S.ws);
+        *device_bytes = d;
+    }
     return PFAC_OK;
 }
 

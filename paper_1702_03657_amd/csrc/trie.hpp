@@ -131,9 +131,10 @@ struct DeviceImageHost {
     std::vector<uint16_t> qfp;
 };
 
-constexpr uint32_t kQ16Mul = 0x9E3779u;     // 24-bit odd multiplier
-
-constexpr uint32_t kPfx4Mul = 0x9E3779B1u;
+// Multiplicative (Fibonacci) hashing, Knuth TAOCP vol. 3, 6.4: odd
+// multipliers near 2^w / golden ratio, the hash taken from the top bits.
+constexpr uint32_t kQ16Mul = 0x9E3779u;     // 24-bit multiplier (one 24 x 24-bit multiply)
+constexpr uint32_t kPfx4Mul = 0x9E3779B1u;  // 32-bit multiplier
 
 // Derives the device image from the CRS trie for a level index of at most
 // `index_bits` bits and a prefix filter of `fold_bits` (0, 8 or 16) bits per

@@ -5,8 +5,11 @@
 // node x symbol sparse matrix (step VI) and compresses that matrix with
 // compressed row storage: row_ptr per node, the symbol (edge label) as the
 // column index and the child node as the value.  Steps III-V (truncation and
-// suffix / end-node merging) are not applied: they lose pattern identities,
-// and every (position, pattern id) match must be reported.
+// suffix / end-node merging) are built only in exact forms, as optional
+// device images: a truncated image keeps the pattern tails below the cut for
+// verification (pack_image, tails), and the merged DAG keeps the pattern
+// identities as ranks carried on its edges (build_dag).  The default image is
+// the whole CRS trie, since every (position, pattern id) match is reported.
 #include <algorithm>
 #include <cstring>
 #include <numeric>

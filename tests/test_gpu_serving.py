@@ -296,3 +296,59 @@ def test_server_pins_the_trie_image():
     trie.set_tuning(index_bits=8 if bits != 8 else 16)
     got, _ = gpu_scan(trie, t, counts=False)
     assert_same(got, oracle.brute(t, pats))
+
+
+def test_server_fixes_the_whole_tuning():
+    """The server's worker reads the trie's tuning at every launch: while it
+    runs, any tuning change (a kernel switch needs no new image) and the
+    autotuners are refused with PFAC_EBUSY, an unchanged tuning is accepted,
+    and requests keep their results."""
+    import torch
+    pats = [b"abcd", b"bcde", b"zzzz"]
+    trie = pf.Trie(pats)
+    srv, _buf = _server(trie, 1 << 16, (1 << 16) + (1 << 20), 4)
+    t = np.frombuffer(b"xxabcdezzzzz" * 500, dtype=np.uint8).copy()
+    rid = srv.submit(t)
+    tn = trie.tuning()
+    for change in (dict(kernel=0 if tn["kernel"] else 2), dict(chunks_per_unit=4),
+                   dict(waves_per_wg=8 if tn["waves_per_wg"] != 8 else 16)):
+        with pytest.raises(pf.PfacError) as e:
+            trie.set_tuning(**change)
+        assert e.value.code == pf.PFAC_EBUSY, change
+    trie.set_tuning(**tn)  # the same tuning: nothing changes, accepted
+    dev = torch.from_numpy(t).cuda()
+    with pytest.raises(pf.PfacError) as e:
+        pf.pfac_autotune(trie, pf.Workspace(), dev, t.size)
+    assert e.value.code == pf.PFAC_EBUSY
+    got, _ = srv.wait(rid, capacity=1 << 14)
+    assert_same(got, oracle.brute(t, pats))
+    assert trie.tuning() == tn
+    srv.close()
+    trie.set_tuning(kernel=0)
+    got, _ = gpu_scan(trie, t, counts=False)
+    assert_same(got, oracle.brute(t, pats))
+
+
+def test_server_keeps_its_trie_and_arena_alive():
+    """A server built from temporaries (trie, arena, streams) holds them
+    until it is closed: garbage collection in between frees none of them."""
+    import gc
+
+    import torch
+    pats = [b"abcd", b"cdef", b"efgh"]
+    t = np.frombuffer(b"abcdefgh" * 4096, dtype=np.uint8).copy()
+    srv = pf.Server(pf.Trie(pats), torch.empty((1 << 16) + (1 << 20), dtype=torch.uint8, device="cuda"),
+                    1 << 16, 4, torch.cuda.Stream(), torch.cuda.Stream())
+    gc.collect()
+    torch.cuda.empty_cache()
+    # other allocations now, which would reuse a freed arena
+    junk = torch.full((4 << 20,), 0x61, dtype=torch.uint8, device="cuda")
+    ids = [srv.submit(t) for _ in range(6)]
+    want = oracle.brute(t, pats)
+    for rid in ids:
+        got, _ = srv.wait(rid, capacity=1 << 16)
+        assert_same(got, want)
+    st = srv.stats()
+    assert st["device_bytes"] > 0 and st["requests"] == 6
+    srv.close()
+    del junk

@@ -275,6 +275,55 @@ def test_canonical_trie_invariants():
     assert fp["dense"] == 256 * 4 * N and fp["bitmap36"] == (256 // 8 + 4) * N
 
 
+def _footprint_sets():
+    dna = workloads.make_patterns(workloads.rng_for(300), 400, 20, 32, "acgt").as_list()
+    uni = workloads.make_patterns(workloads.rng_for(301), 300, 4, 16, "uniform").as_list()
+    return {
+        "empty": [],
+        "duplicates": [b"abc", b"abc", b"abc", b"x"],
+        "nested prefixes": [b"a", b"ab", b"abc", b"abcd", b"b", b"bc"],
+        "c1-like": uni,
+        "c3-like": dna,
+    }
+
+
+@pytest.mark.parametrize("name", list(_footprint_sets()))
+def test_footprint_is_the_size_of_the_structures(name):
+    """Design and Implementation (CRS paragraph; Results, 36-byte node):
+    each footprint figure equals the byte size of that structure, built out
+    of the trie and checked to encode it, not a restated formula."""
+    pats = _footprint_sets()[name]
+    t = oracle.canonical_trie(pats)
+    N, k = len(t["row_ptr"]) - 1, len(pats)
+    fp = oracle.footprint(N, k)
+    stored = ("row_ptr", "labels", "child", "term_ptr", "term_ids")
+    assert fp["crs_bytes"] == sum(t[a].nbytes for a in stored)
+    assert fp["crs_elements"] == t["row_ptr"].size + t["labels"].size + t["child"].size
+    rp = t["row_ptr"].astype(np.int64)
+    parent = np.repeat(np.arange(N), np.diff(rp))
+    # the uncompressed node x symbol table (step VI): one int32 per symbol
+    dense = np.full((N, 256), -1, dtype=np.int32)
+    dense[parent, t["labels"]] = t["child"]
+    assert fp["dense"] == dense.nbytes
+    assert np.count_nonzero(dense >= 0) == t["labels"].size
+    # bitmapped nodes: a 256-bit child bitmap and the first child's index;
+    # every child is the first child plus the set bits below its label
+    node_t = np.dtype([("bitmap", "<u4", (8,)), ("first", "<u4")])
+    nodes = np.zeros(N, dtype=node_t)
+    lab = t["labels"].astype(np.int64)
+    np.bitwise_or.at(nodes["bitmap"], (parent, lab >> 5),
+                     (np.uint32(1) << (lab & 31).astype(np.uint32)))
+    has = np.diff(rp) > 0
+    nodes["first"][has] = t["child"][rp[:-1][has]]
+    assert fp["bitmap36"] == nodes.nbytes
+    for e in range(t["labels"].size):
+        v, c = parent[e], int(lab[e])
+        words = nodes["bitmap"][v]
+        below = sum(bin(int(words[i])).count("1") for i in range(c >> 5))
+        below += bin(int(words[c >> 5]) & ((1 << (c & 31)) - 1)).count("1")
+        assert nodes["first"][v] + below == t["child"][e]
+
+
 def test_patternset_roundtrip():
     pats = [b"abc", b"\x00", b"zz" * 10]
     ps = PatternSet.from_list(pats)
