@@ -293,8 +293,8 @@ int pfac_scan_batch_plain(const pfac_trie *t, pfac_workspace *w, const uint8_t *
  * instantiate it.  Replays read the texts, offsets and outputs at the same
  * device addresses, so the caller may refill them between replays as long
  * as n_texts and total_bytes stay the same.  The graph allocates and owns
- * its own scratch, so `w` is not used (it may be NULL) and stays free for
- * other scans.  While the graph exists the trie's device image is pinned:
+ * its own scratch, so `w` (which may be NULL) stays free for other scans; only
+ * its timing events, if set, are taken over (see pfac_graph_set_timing).  While the graph exists the trie's device image is pinned:
  * a pfac_trie_set_tuning that would rebuild it (index_bits, fold_bits,
  * trunc_depth or dag changed, as the autotuner may do) fails with
  * PFAC_EBUSY, and the trie must outlive the graph.  Replays of one graph
@@ -305,6 +305,17 @@ int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w, const uint8_t
                             pfac_match *out_dev, uint64_t capacity, uint64_t *n_matches_dev,
                             void *stream, pfac_graph **out);
 int pfac_graph_launch(pfac_graph *g, void *stream);
+
+/*
+ * Kernel timing inside replays: when `w` had timing events set
+ * (pfac_workspace_set_timing) at pfac_graph_create_batch, the graph records
+ * them right before and right after its main scan kernel at every replay.
+ * This call makes later replays record these two events (hipEvent_t)
+ * instead, so each replay can be timed with events of its own.  PFAC_EINVAL
+ * for NULL arguments or a graph captured without timing events (or without
+ * a scan kernel: an empty batch).
+ */
+int pfac_graph_set_timing(pfac_graph *g, void *start_event, void *stop_event);
 void pfac_graph_free(pfac_graph *g);
 
 /*

@@ -104,6 +104,7 @@ SIGNATURES = [
     ("pfac_graph_create_batch", ctypes.c_int,
      [_vp, _vp, _vp, _vp, _u32, _u64, _vp, _u64, _vp, _vp, _p(_vp)]),
     ("pfac_graph_launch", ctypes.c_int, [_vp, _vp]),
+    ("pfac_graph_set_timing", ctypes.c_int, [_vp, _vp, _vp]),
     ("pfac_graph_free", None, [_vp]),
     ("pfac_autotune", ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _p(pfac_tuning)]),
     ("pfac_autotune_batch", ctypes.c_int,
@@ -336,6 +337,12 @@ class Graph:
 
     def launch(self, stream=None):
         check("pfac_graph_launch", load().pfac_graph_launch(self.handle, _stream_ptr(stream)))
+
+    def set_timing(self, start_event, stop_event):
+        """Later replays record these events around the main scan kernel (the
+        graph must have been captured from a workspace with timing events)."""
+        check("pfac_graph_set_timing", load().pfac_graph_set_timing(
+            self.handle, int(start_event.cuda_event), int(stop_event.cuda_event)))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -101,6 +101,9 @@ struct pfac_graph {
     hipGraphExec_t exec = nullptr;
     pfac_workspace *ws = nullptr;     // its own scratch, captured with it
     const pfac_trie *t = nullptr;     // pinned: its image may not be replaced
+    // event-record nodes around the main scan kernel (captured when the
+    // workspace passed at creation had timing events), else NULL
+    hipGraphNode_t n_start = nullptr, n_stop = nullptr;
 };
 
 extern "C" int pfac_last_hip_error(void) { return g_last_hip; }
@@ -568,21 +571,40 @@ extern "C" void pfac_workspace_free(pfac_workspace *w) {
     delete w;
 }
 
-// n_tiles: units (or 1 KiB chunks of the wave kernels, at least as many);
-// split: also the candidate lists of the split wave kernels.
-static int ws_reserve(pfac_workspace *w, uint64_t n_tiles, uint64_t capacity, bool split) {
-    uint64_t n_sums = std::max<uint64_t>(1, (n_tiles + (1u << kSumShift) - 1) >> kSumShift);
-    HIP_TRY(w->unit_count.reserve(std::max<uint64_t>(n_tiles, 1) * 4));
-    HIP_TRY(w->unit_off.reserve(std::max<uint64_t>(n_tiles, 1) * 8));
-    HIP_TRY(w->tile_first.reserve(std::max<uint64_t>(n_tiles, 1) * 4));
-    HIP_TRY(w->blocksum.reserve(n_sums * 8));
-    HIP_TRY(w->stage.reserve(std::max<uint64_t>(capacity, 1) * sizeof(pfac_match)));
+// Scratch sizes of a scan over n_tiles units (or 1 KiB chunks of the wave
+// kernels, at least as many) with room for `capacity` staged matches; split:
+// also the candidate lists of the split wave kernels.
+struct WsSizes {
+    uint64_t unit_count, unit_off, tile_first, blocksum, stage, inline_stage, cand, cand_count;
+};
+
+static WsSizes ws_sizes(uint64_t n_tiles, uint64_t capacity, bool split) {
+    const uint64_t n_sums = std::max<uint64_t>(1, (n_tiles + (1u << kSumShift) - 1) >> kSumShift);
+    WsSizes z{};
+    z.unit_count = std::max<uint64_t>(n_tiles, 1) * 4;
+    z.unit_off = std::max<uint64_t>(n_tiles, 1) * 8;
+    z.tile_first = std::max<uint64_t>(n_tiles, 1) * 4;
+    z.blocksum = n_sums * 8;
+    z.stage = std::max<uint64_t>(capacity, 1) * sizeof(pfac_match);
     // wave kernels: max(kInlineCap, kInlinePerChunk * G) slots per unit of G
     // chunks, at most kInlineCap per chunk
-    HIP_TRY(w->inline_stage.reserve((n_tiles + 64) * kInlineCap * sizeof(pfac_match)));
+    z.inline_stage = (n_tiles + 64) * kInlineCap * sizeof(pfac_match);
+    z.cand = split ? (n_tiles + 64) * kCandPerChunk * 16 : 0;
+    z.cand_count = split ? std::max<uint64_t>(n_tiles, 1) * 4 : 0;
+    return z;
+}
+
+static int ws_reserve(pfac_workspace *w, uint64_t n_tiles, uint64_t capacity, bool split) {
+    const WsSizes z = ws_sizes(n_tiles, capacity, split);
+    HIP_TRY(w->unit_count.reserve(z.unit_count));
+    HIP_TRY(w->unit_off.reserve(z.unit_off));
+    HIP_TRY(w->tile_first.reserve(z.tile_first));
+    HIP_TRY(w->blocksum.reserve(z.blocksum));
+    HIP_TRY(w->stage.reserve(z.stage));
+    HIP_TRY(w->inline_stage.reserve(z.inline_stage));
     if (split) {
-        HIP_TRY(w->cand.reserve((n_tiles + 64) * kCandPerChunk * 16));
-        HIP_TRY(w->cand_count.reserve(std::max<uint64_t>(n_tiles, 1) * 4));
+        HIP_TRY(w->cand.reserve(z.cand));
+        HIP_TRY(w->cand_count.reserve(z.cand_count));
     }
     return PFAC_OK;
 }
@@ -656,22 +678,45 @@ static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out) {
 
 static bool uses_split(const pfac_trie *t) { return t->tuning.kernel == 2 && use_wave_kernel(t, nullptr); }
 
+// How a scan of `total` bytes at `text` is cut with the trie's tuning:
+// output units (tiles, or units of G chunks), batch-plan units (1 KiB chunks
+// of the wave kernels, else tiles), and which kernels run.
+struct ScanShape {
+    bool wave_kernel, split;
+    uint32_t waves, tile, plan_unit;
+    uint64_t shift, n_tiles, n_plan;
+    uint64_t ws_units() const { return std::max(n_tiles, n_plan); }
+};
+
+static ScanShape scan_shape(const pfac_trie *t, const void *text, uint64_t total) {
+    ScanShape h{};
+    h.waves = t->tuning.waves_per_wg;
+    h.wave_kernel = use_wave_kernel(t, &h.waves);
+    h.split = h.wave_kernel && t->tuning.kernel == 2;
+    h.tile = h.wave_kernel ? kWaveChunk * t->tuning.chunks_per_unit : kWG * t->tuning.bytes_per_lane;
+    h.shift = (uintptr_t)text & 15;
+    h.n_tiles = tiles_for(total, h.shift, h.tile);
+    if (t->crs.k == 0) h.n_tiles = 0;  // nothing can match
+    h.plan_unit = h.wave_kernel ? kWaveChunk : h.tile;
+    h.n_plan = h.n_tiles ? tiles_for(total, h.shift, h.plan_unit) : 0;
+    return h;
+}
+
 static int enqueue_scan(const Launch &L, bool reserve) {
     const pfac_trie *t = L.t;
-    uint32_t waves = t->tuning.waves_per_wg;
-    const bool wave_kernel = use_wave_kernel(t, &waves);
-    const bool split = wave_kernel && t->tuning.kernel == 2;
+    const ScanShape h = scan_shape(t, L.text, L.total);
+    uint32_t waves = h.waves;
+    const bool wave_kernel = h.wave_kernel;
+    const bool split = h.split;
     const uint32_t bpl = t->tuning.bytes_per_lane;
-    const uint32_t tile = wave_kernel ? kWaveChunk * t->tuning.chunks_per_unit : kWG * bpl;
     const uintptr_t addr = (uintptr_t)L.text;
-    const uint64_t shift = addr & 15;
-    uint64_t n_tiles = tiles_for(L.total, shift, tile);
-    if (t->crs.k == 0) n_tiles = 0;  // nothing can match
+    const uint64_t shift = h.shift;
+    const uint64_t n_tiles = h.n_tiles;
     // the batch plan is per 1 KiB chunk for the wave kernel, per tile otherwise
-    const uint32_t plan_unit = wave_kernel ? kWaveChunk : tile;
-    const uint64_t n_plan = n_tiles ? tiles_for(L.total, shift, plan_unit) : 0;
+    const uint32_t plan_unit = h.plan_unit;
+    const uint64_t n_plan = h.n_plan;
     if (reserve) {
-        int rc = ws_reserve(L.w, std::max(n_tiles, n_plan), L.capacity, split);
+        int rc = ws_reserve(L.w, h.ws_units(), L.capacity, split);
         if (rc != PFAC_OK) return rc;
     }
     pfac_workspace *w = L.w;
@@ -730,12 +775,17 @@ static int enqueue_scan(const Launch &L, bool reserve) {
         if (per_cu == 0 || per_cu > occ) per_cu = occ;
         const uint64_t resident = (uint64_t)std::max(1, t->n_cu) * (uint64_t)per_cu;
         const uint32_t grid = (uint32_t)std::min<uint64_t>(want, resident);
-        if (w->ev_start) HIP_TRY(hipEventRecord(w->ev_start, L.s));
+        // under stream capture the timing events become event-record nodes
+        // of the graph (recorded again at every replay)
+        hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+        if (w->ev_start) HIP_TRY(hipStreamIsCapturing(L.s, &cap));
+        const unsigned ev_flags = cap == hipStreamCaptureStatusActive ? hipEventRecordExternal : 0u;
+        if (w->ev_start) HIP_TRY(hipEventRecordWithFlags(w->ev_start, L.s, ev_flags));
         if (wave_kernel)
             HIP_TRY(launch_scan_waves(a, waves, grid, L.s));
         else
             HIP_TRY(launch_scan(a, bpl, grid, L.s));
-        if (w->ev_stop) HIP_TRY(hipEventRecord(w->ev_stop, L.s));
+        if (w->ev_stop) HIP_TRY(hipEventRecordWithFlags(w->ev_stop, L.s, ev_flags));
         if (split) HIP_TRY(launch_walk_units(a, L.s));
     }
     FinishArgs f{};
@@ -847,6 +897,25 @@ uint64_t workspace_device_bytes(const pfac_workspace *w) {
 
 // ------------------------------------------------------------------- graphs
 
+// The event-record nodes of the timing events in a captured graph.
+static int find_timing_nodes(pfac_graph *g) {
+    size_t n = 0;
+    HIP_TRY(hipGraphGetNodes(g->graph, nullptr, &n));
+    std::vector<hipGraphNode_t> nodes(n);
+    if (n) HIP_TRY(hipGraphGetNodes(g->graph, nodes.data(), &n));
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        HIP_TRY(hipGraphNodeGetType(nd, &ty));
+        if (ty != hipGraphNodeTypeEventRecord) continue;
+        hipEvent_t ev = nullptr;
+        HIP_TRY(hipGraphEventRecordNodeGetEvent(nd, &ev));
+        if (ev == g->ws->ev_start) g->n_start = nd;
+        if (ev == g->ws->ev_stop) g->n_stop = nd;
+    }
+    // an empty batch launches no scan kernel, so it has no timing nodes
+    return PFAC_OK;
+}
+
 extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
                                        const uint8_t *texts_dev, const uint64_t *offsets_dev,
                                        uint32_t n_texts, uint64_t total_bytes,
@@ -854,7 +923,8 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
                                        uint64_t *n_matches_dev, void *stream, pfac_graph **out) {
     if (!out) return PFAC_EINVAL;
     *out = nullptr;
-    (void)w;  // the graph gets scratch of its own: `w` stays free for other scans
+    // the graph gets scratch of its own: `w` stays free for other scans and
+    // lends the graph only its timing events
     pfac_graph *g = new (std::nothrow) pfac_graph();
     if (!g) return PFAC_ENOMEM;
     int rc = pfac_workspace_create(&g->ws);
@@ -880,6 +950,11 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
         }
         s = own;
     }
+    // the caller's timing events, if set, are captured around the main kernel
+    if (w) {
+        g->ws->ev_start = w->ev_start;
+        g->ws->ev_stop = w->ev_stop;
+    }
     hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         Launch L{t, g->ws, texts_dev, total_bytes, offsets_dev, n_texts, 0, out_dev, capacity,
@@ -887,6 +962,7 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
         rc = enqueue_scan(L, false);
         hipError_t e2 = hipStreamEndCapture(s, &g->graph);
         if (rc == PFAC_OK && e2 != hipSuccess) rc = hip_fail(e2);
+        if (rc == PFAC_OK && g->ws->ev_start) rc = find_timing_nodes(g);
         if (rc == PFAC_OK) {
             e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
             if (e != hipSuccess) rc = hip_fail(e);
@@ -900,6 +976,14 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
         return rc;
     }
     *out = g;
+    return PFAC_OK;
+}
+
+extern "C" int pfac_graph_set_timing(pfac_graph *g, void *start_event, void *stop_event) {
+    if (!g || !g->exec || !start_event || !stop_event) return PFAC_EINVAL;
+    if (!g->n_start || !g->n_stop) return PFAC_EINVAL;  // captured without timing events
+    HIP_TRY(hipGraphExecEventRecordNodeSetEvent(g->exec, g->n_start, (hipEvent_t)start_event));
+    HIP_TRY(hipGraphExecEventRecordNodeSetEvent(g->exec, g->n_stop, (hipEvent_t)stop_event));
     return PFAC_OK;
 }
 

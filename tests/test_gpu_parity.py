@@ -503,3 +503,53 @@ def test_graph_owns_its_scratch_and_pins_the_image():
     trie.set_tuning(index_bits=8 if tn["index_bits"] != 8 else 16)  # free to rebuild now
     got, _ = gpu_scan(trie, small[:40_000], counts=False)
     assert_same(got, oracle.bucketed(small[:40_000], pats, threads=8))
+
+
+def test_graph_records_timing_events_in_every_replay():
+    """A graph captured from a workspace with timing events records them
+    around its main scan kernel at every replay; pfac_graph_set_timing moves
+    later replays to other events; the results stay the oracle's."""
+    import torch
+    rng = np.random.default_rng(93)
+    pats = workloads.make_patterns(rng, 800, 6, 30, "uniform").as_list()
+    text = rng.integers(0, 256, 3_000_000, dtype=np.uint8)
+    for at in rng.integers(0, text.size - 40, 2000):
+        p = pats[int(rng.integers(0, len(pats)))]
+        text[at:at + len(p)] = np.frombuffer(p, dtype=np.uint8)
+    offs = np.array([0, 1000, 1_000_000, 1_000_000, text.size], dtype=np.uint64)
+    want = oracle.bucketed(text, pats, offsets=offs, threads=8)
+    trie = pf.Trie(pats)
+    ws = pf.Workspace()
+    dev = torch.from_numpy(text).cuda()
+    offs_dev = torch.from_numpy(offs.view(np.int64)).cuda()
+    cap = want.n + 64
+    out = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    s = torch.cuda.Stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    for e in ev:
+        e.record(s)
+    ws.set_timing(ev[0], ev[1])
+    g = pf.Graph(trie, ws, dev, offs_dev, 4, text.size, out, cap, cnt, s)
+    ws.set_timing(None, None)
+    step = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    step[0].record(s)
+    for i in range(3):
+        g.set_timing(ev[2 * i], ev[2 * i + 1])
+        g.launch(s)
+        step[i + 1].record(s)
+    s.synchronize()
+    for i in range(3):
+        k = ev[2 * i].elapsed_time(ev[2 * i + 1])
+        whole = step[i].elapsed_time(step[i + 1])
+        say(f"replay {i}: kernel {k:.4f} ms of {whole:.4f} ms")
+        assert 0 < k <= whole
+    assert int(cnt.item()) == want.n
+    assert_same(pf.matches_to_numpy(out, want.n), want, with_text=True)
+    g.close()
+    # a graph captured without timing events has no nodes to move
+    g2 = pf.Graph(trie, ws, dev, offs_dev, 4, text.size, out, cap, cnt, s)
+    with pytest.raises(pf.PfacError) as e:
+        g2.set_timing(ev[0], ev[1])
+    assert e.value.code == pf.PFAC_EINVAL
+    g2.close()
