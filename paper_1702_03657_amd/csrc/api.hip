@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -20,6 +22,23 @@
 using namespace pfac;
 
 static thread_local int g_last_hip = 0;
+static int hip_fail(hipError_t e);
+
+// PFAC_TRACE_ERRORS=1 in the environment: every failing HIP call is named
+// on stderr (diagnostics only; the return codes do not change).
+static bool trace_errors() {
+    static const bool on = [] {
+        const char *v = std::getenv("PFAC_TRACE_ERRORS");
+        return v && v[0] && v[0] != '0';
+    }();
+    return on;
+}
+
+static int hip_fail_at(hipError_t e, const char *what, int line) {
+    if (trace_errors())
+        std::fprintf(stderr, "pfac: %s failed (line %d): %s\n", what, line, hipGetErrorString(e));
+    return hip_fail(e);
+}
 
 static int hip_fail(hipError_t e) {
     g_last_hip = (int)e;
@@ -30,10 +49,10 @@ static int hip_fail(hipError_t e) {
     return e == hipErrorOutOfMemory ? PFAC_ENOMEM : PFAC_EDEVICE;
 }
 
-#define HIP_TRY(expr)                                  \
-    do {                                               \
-        hipError_t e_ = (expr);                        \
-        if (e_ != hipSuccess) return hip_fail(e_);     \
+#define HIP_TRY(expr)                                                \
+    do {                                                             \
+        hipError_t e_ = (expr);                                      \
+        if (e_ != hipSuccess) return hip_fail_at(e_, #expr, __LINE__); \
     } while (0)
 
 struct DeviceBuf {
@@ -89,6 +108,7 @@ struct pfac_trie {
 struct pfac_workspace {
     DeviceBuf stage, unit_count, unit_off, blocksum, tile_first, inline_stage, misc;
     DeviceBuf cand, cand_count;  // split wave kernels: walk candidates per unit
+    DeviceBuf chunk_info;        // wave kernels, batches: text boundaries per 1 KiB chunk
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // optional kernel timing
     // misc: [0] stage cursor, [1] running total, [2] per-launch count
     unsigned long long *cursor() { return (unsigned long long *)misc.p; }
@@ -564,6 +584,7 @@ extern "C" void pfac_workspace_free(pfac_workspace *w) {
     w->unit_off.release();
     w->blocksum.release();
     w->tile_first.release();
+    w->chunk_info.release();
     w->inline_stage.release();
     w->cand.release();
     w->cand_count.release();
@@ -575,7 +596,8 @@ extern "C" void pfac_workspace_free(pfac_workspace *w) {
 // kernels, at least as many) with room for `capacity` staged matches; split:
 // also the candidate lists of the split wave kernels.
 struct WsSizes {
-    uint64_t unit_count, unit_off, tile_first, blocksum, stage, inline_stage, cand, cand_count;
+    uint64_t unit_count, unit_off, tile_first, chunk_info, blocksum, stage, inline_stage, cand,
+        cand_count;
 };
 
 static WsSizes ws_sizes(uint64_t n_tiles, uint64_t capacity, bool split) {
@@ -584,6 +606,7 @@ static WsSizes ws_sizes(uint64_t n_tiles, uint64_t capacity, bool split) {
     z.unit_count = std::max<uint64_t>(n_tiles, 1) * 4;
     z.unit_off = std::max<uint64_t>(n_tiles, 1) * 8;
     z.tile_first = std::max<uint64_t>(n_tiles, 1) * 4;
+    z.chunk_info = std::max<uint64_t>(n_tiles, 1) * 8;
     z.blocksum = n_sums * 8;
     z.stage = std::max<uint64_t>(capacity, 1) * sizeof(pfac_match);
     // wave kernels: max(kInlineCap, kInlinePerChunk * G) slots per unit of G
@@ -599,6 +622,7 @@ static int ws_reserve(pfac_workspace *w, uint64_t n_tiles, uint64_t capacity, bo
     HIP_TRY(w->unit_count.reserve(z.unit_count));
     HIP_TRY(w->unit_off.reserve(z.unit_off));
     HIP_TRY(w->tile_first.reserve(z.tile_first));
+    HIP_TRY(w->chunk_info.reserve(z.chunk_info));
     HIP_TRY(w->blocksum.reserve(z.blocksum));
     HIP_TRY(w->stage.reserve(z.stage));
     HIP_TRY(w->inline_stage.reserve(z.inline_stage));
@@ -731,6 +755,7 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     a.n_texts = L.n_texts;
     a.text_id0 = L.text_id0;
     a.tile_first_text = L.offsets ? (const uint32_t *)w->tile_first.p : nullptr;
+    a.chunk_info = L.offsets && wave_kernel ? (const uint2 *)w->chunk_info.p : nullptr;
     a.n_plan = n_plan;
     a.plan_shift = (uint32_t)__builtin_ctz(plan_unit);
     a.n_tiles = n_tiles;
@@ -757,7 +782,7 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     if (n_tiles) {
         if (L.offsets)
             HIP_TRY(launch_plan(L.offsets, L.n_texts, shift, n_plan, plan_unit,
-                                (uint32_t *)w->tile_first.p, L.s));
+                                (uint32_t *)w->tile_first.p, (uint2 *)a.chunk_info, L.s));
         int per_cu = (int)t->tuning.wg_per_cu;
         int occ;
         uint64_t want;
@@ -890,7 +915,7 @@ void trie_pin(const pfac_trie *t, int delta) {
 uint64_t workspace_device_bytes(const pfac_workspace *w) {
     if (!w) return 0;
     return w->stage.bytes + w->unit_count.bytes + w->unit_off.bytes + w->blocksum.bytes +
-           w->tile_first.bytes + w->inline_stage.bytes + w->misc.bytes + w->cand.bytes +
+           w->tile_first.bytes + w->chunk_info.bytes + w->inline_stage.bytes + w->misc.bytes + w->cand.bytes +
            w->cand_count.bytes;
 }
 }  // namespace pfac
@@ -950,25 +975,37 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
         }
         s = own;
     }
-    // the caller's timing events, if set, are captured around the main kernel
-    if (w) {
-        g->ws->ev_start = w->ev_start;
-        g->ws->ev_stop = w->ev_stop;
-    }
-    hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        Launch L{t, g->ws, texts_dev, total_bytes, offsets_dev, n_texts, 0, out_dev, capacity,
-                 n_matches_dev, nullptr, nullptr, s};
-        rc = enqueue_scan(L, false);
-        hipError_t e2 = hipStreamEndCapture(s, &g->graph);
-        if (rc == PFAC_OK && e2 != hipSuccess) rc = hip_fail(e2);
-        if (rc == PFAC_OK && g->ws->ev_start) rc = find_timing_nodes(g);
-        if (rc == PFAC_OK) {
-            e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
-            if (e != hipSuccess) rc = hip_fail(e);
+    // the caller's timing events, if set, are captured around the main
+    // kernel; if the runtime refuses them the graph is captured again
+    // without them (pfac_graph_set_timing then returns PFAC_EINVAL)
+    for (int with_events = (w && w->ev_start) ? 1 : 0; with_events >= 0; with_events--) {
+        g->ws->ev_start = with_events ? w->ev_start : nullptr;
+        g->ws->ev_stop = with_events ? w->ev_stop : nullptr;
+        g->n_start = g->n_stop = nullptr;
+        hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            Launch L{t, g->ws, texts_dev, total_bytes, offsets_dev, n_texts, 0, out_dev, capacity,
+                     n_matches_dev, nullptr, nullptr, s};
+            rc = enqueue_scan(L, false);
+            hipGraph_t graph = nullptr;
+            hipError_t e2 = hipStreamEndCapture(s, &graph);
+            g->graph = graph;
+            if (rc == PFAC_OK && e2 != hipSuccess) rc = hip_fail_at(e2, "hipStreamEndCapture", __LINE__);
+            if (rc == PFAC_OK && g->ws->ev_start) rc = find_timing_nodes(g);
+            if (rc == PFAC_OK) {
+                e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+                if (e != hipSuccess) rc = hip_fail_at(e, "hipGraphInstantiate", __LINE__);
+            }
+        } else {
+            rc = hip_fail_at(e, "hipStreamBeginCapture", __LINE__);
         }
-    } else {
-        rc = hip_fail(e);
+        if (rc == PFAC_OK || !with_events) break;
+        // drop the failed attempt and capture once more without events
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        g->exec = nullptr;
+        g->graph = nullptr;
+        (void)hipGetLastError();
     }
     if (own) (void)hipStreamDestroy(own);
     if (rc != PFAC_OK) {

@@ -429,9 +429,18 @@ __global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v) {
 }
 
 // tile_first_text[t] = last text i whose start (in frame coordinates) is at or
-// before the first byte of tile t.
+// before the first byte of tile t.  With chunk_info (1 KiB plan units of the
+// wave kernels) also the text boundaries of each chunk, packed as
+//   x: bits 0..16  distance from the chunk start to the first boundary at or
+//                  past its end (capped at 0x1ffff, the cap when none),
+//      bits 17..19 boundaries inside the chunk, 0..4 (7: more than four),
+//      bits 20..29 the first one (chunk position);
+//   y: the second, third and fourth, 10 bits each (0 when absent),
+// in ascending order, so that the filter kernel finds the distance from any
+// start position to the end of its text without searching the offsets.
 __global__ void plan_kernel(const uint64_t *offsets, uint32_t n_texts, uint64_t shift,
-                            uint64_t n_tiles, uint32_t tile, uint32_t *tile_first_text) {
+                            uint64_t n_tiles, uint32_t tile, uint32_t *tile_first_text,
+                            uint2 *chunk_info) {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += stride) {
         const uint64_t g = t * tile;
@@ -441,6 +450,27 @@ __global__ void plan_kernel(const uint64_t *offsets, uint32_t n_texts, uint64_t 
             if (offsets[mid] + shift <= g) lo = mid; else hi = mid;
         }
         tile_first_text[t] = lo;
+        if (chunk_info) {
+            // boundaries offsets[lo .. n_texts] + shift: the first is at or
+            // before g, so only it can equal g; the rest lie after g
+            uint32_t cnt = 0, w[4] = {0, 0, 0, 0};
+            uint64_t next = ~0ull;
+            for (uint32_t i = lo; i <= n_texts; i++) {
+                const uint64_t b = offsets[i] + shift;
+                if (b < g) continue;
+                if (b >= g + tile) {
+                    next = b;
+                    break;
+                }
+                if (cnt == 4) {
+                    cnt = 7;
+                    break;
+                }
+                w[cnt++] = (uint32_t)(b - g);
+            }
+            const uint32_t nrel = next - g > 0x1ffffull ? 0x1ffffu : (uint32_t)(next - g);
+            chunk_info[t] = make_uint2(nrel | (cnt << 17) | (w[0] << 20), w[1] | (w[2] << 10) | (w[3] << 20));
+        }
     }
 }
 
@@ -555,12 +585,13 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
 
 hipError_t launch_plan(const uint64_t *offsets, uint32_t n_texts, uint64_t shift,
                        uint64_t n_tiles, uint32_t tile, uint32_t *tile_first_text,
-                       hipStream_t s) {
+                       uint2 *chunk_info, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
+    if (chunk_info && tile != kWaveChunk) return hipErrorInvalidValue;
     uint64_t g = (n_tiles + 255) / 256;
     const uint32_t grid = (uint32_t)(g < 65536 ? g : 65536);
     hipLaunchKernelGGL(plan_kernel, dim3(grid), dim3(256), 0, s, offsets, n_texts, shift,
-                       n_tiles, tile, tile_first_text);
+                       n_tiles, tile, tile_first_text, chunk_info);
     return hipGetLastError();
 }
 

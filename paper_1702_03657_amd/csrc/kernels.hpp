@@ -56,6 +56,7 @@ struct ScanArgs {
     uint64_t total;                   // bytes of all texts
     const uint64_t *offsets;          // n_texts + 1 text starts, or NULL for one text
     const uint32_t *tile_first_text;  // per plan unit: text holding its first byte (batch only)
+    const uint2 *chunk_info;          // wave kernels, batch only: text boundaries per 1 KiB chunk
     uint64_t n_plan;                  // plan units of 1 << plan_shift bytes
     uint32_t plan_shift, pad3;
     uint64_t n_tiles;
@@ -117,7 +118,7 @@ hipError_t launch_reset(unsigned long long *stage_cursor, unsigned long long *bl
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_plan(const uint64_t *offsets, uint32_t n_texts, uint64_t shift,
                        uint64_t n_tiles, uint32_t tile, uint32_t *tile_first_text,
-                       hipStream_t s);
+                       uint2 *chunk_info, hipStream_t s);
 hipError_t launch_scan(const ScanArgs &a, uint32_t bpl, uint32_t grid, hipStream_t s);
 hipError_t launch_finish(const FinishArgs &f, hipStream_t s);
 hipError_t launch_add_running(unsigned long long *running, const uint64_t *n, hipStream_t s);

@@ -66,6 +66,8 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x)
     return x;
 }
 
+__device__ __forceinline__ uint64_t umin64(uint64_t x, uint64_t y) { return x < y ? x : y; }
+
 __device__ __forceinline__ uint32_t mbcnt(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
@@ -380,12 +382,6 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     const bool krec = a.krec_words != 0;
     const bool pfx4 = a.pfx4_words != 0;
 
-    auto load_vec = [&](uint64_t g) -> uint4 {
-        uint4 v = make_uint4(0, 0, 0, 0);
-        // an aligned 16-byte block holding a text byte lies in a mapped page
-        if (g + 16 > lo_valid && g < hi_valid) v = *(const uint4 *)(a.base + g);
-        return v;
-    };
     // chunks of a unit that hold text
     auto unit_chunks = [&](uint64_t u) -> uint32_t {
         const uint64_t lo = u * G * kChunk;
@@ -393,53 +389,59 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         return (uint32_t)min((uint64_t)G, (left + kChunk - 1) / kChunk);
     };
 
-    uint64_t u = (uint64_t)blockIdx.x * waves + wave;
-    // The wave's chunks in order (units u, u + stride, ...; chunks 0..nch-1
-    // of each), loaded two ahead of the one being filtered.  The 16 bytes
-    // after a chunk are the next chunk's first vector (lane 0), except after
-    // the last chunk of a unit, where lane 0 loads them with the chunk.
-    uint64_t pu = u;
-    uint32_t pg = 0;
-    struct Vec2 {
-        uint4 v, h;
+    // The wave's chunks in order: units u0, u0 + stride, ...; chunks 0 .. n-1
+    // of each.
+    struct Cur {
+        uint64_t u;
+        uint32_t g, n;
     };
-    // A unit of a single text that starts inside it and ends at least
-    // 0x20000 bytes before its end: no chunk of it needs a boundary test and
-    // every limit is the 16-bit maximum.
-    auto interior = [&](uint64_t uu) -> bool {
-        const uint64_t lo = uu * G * kChunk;
-        return a.offsets == nullptr && lo >= lo_valid && lo + (uint64_t)G * kChunk + 0x20000 <= hi_valid;
-    };
-    uint32_t pn = pu < n_units ? unit_chunks(pu) : 0u;  // chunks of unit pu
-    bool p_in = pu < n_units && interior(pu);
-    auto prefetch = [&]() -> Vec2 {
-        Vec2 r;
-        r.v = make_uint4(0, 0, 0, 0);
-        r.h = r.v;
-        if (pu < n_units) {
-            const uint64_t lo = (pu * G + pg) * kChunk;
-            // every 16-byte block of an inner chunk holds text: no lane checks
-            if (p_in || (lo + 16 > lo_valid && lo + kChunk - 16 < hi_valid))
-                r.v = *(const uint4 *)(a.base + lo + 16 * lane);
-            else
-                r.v = load_vec(lo + 16ull * lane);
-            if (pg + 1 >= pn && lane == 0) r.h = load_vec(lo + kChunk);
-            if (++pg >= pn) {
-                pg = 0;
-                pu += stride;
-                pn = pu < n_units ? unit_chunks(pu) : 0u;
-                p_in = pu < n_units && interior(pu);
-            }
+    auto start_at = [&](uint64_t uu) -> Cur { return Cur{uu, 0u, uu < n_units ? unit_chunks(uu) : 0u}; };
+    auto advance = [&](Cur &c) {
+        if (++c.g >= c.n) {
+            c.u += stride;
+            c.g = 0;
+            c.n = c.u < n_units ? unit_chunks(c.u) : 0u;
         }
-        return r;
     };
-    Vec2 c0 = prefetch(), c1 = prefetch();
-    uint4 cur = c0.v, cur_h = c0.h, nxt = c1.v, nxt_h = c1.h;
-    for (; u < n_units; u += stride) {
+    // One chunk's loads: its 1 KiB (16 bytes a lane), the 16 bytes after it
+    // (the same block in every lane) and its boundary word.  They are issued
+    // unconditionally, at addresses clamped to the 16-byte blocks that hold
+    // text (all in mapped memory), so that the wait for a chunk's data counts
+    // only the loads issued after it and the next two chunks stay in flight
+    // while it is filtered.  Bytes outside the text are never reported:
+    // every start position is checked against the text range and every walk
+    // stops at the end of its text.
+    struct Slot {
+        uint4 v, h;
+        uint2 info;
+    };
+    const uint64_t blk_lo = lo_valid & ~15ull;
+    const uint64_t blk_hi = (hi_valid - 1) & ~15ull;
+    auto clampb = [&](uint64_t x) -> uint64_t { return x < blk_lo ? blk_lo : (x > blk_hi ? blk_hi : x); };
+    auto load_slot = [&](const Cur &c) -> Slot {
+        const uint64_t chunk = c.u * G + c.g;
+        const uint64_t lo = chunk * kChunk;
+        Slot sl;
+        sl.v = *(const uint4 *)(a.base + clampb(lo + 16ull * lane));
+        sl.h = *(const uint4 *)(a.base + clampb(lo + kChunk));
+        const uint2 *ip = a.chunk_info ? a.chunk_info + umin64(chunk, a.n_plan - 1)
+                                       : (const uint2 *)(a.base + blk_lo);
+        sl.info = *ip;
+        return sl;
+    };
+
+    uint32_t cn = 0, mn = 0;  // candidates, matches of the current unit (wave-uniform)
+    // Filter chunk cc with the data of slot sl, close its unit after its last
+    // chunk, and step cc to the wave's next chunk; false when none is left.
+    auto chunk = [&](const Slot &sl, Cur &cc) -> bool {
+        const uint64_t u = cc.u;
+        const uint32_t g = cc.g, nch = cc.n;
         const uint64_t unit_lo = u * G * kChunk;
-        const uint32_t nch = unit_chunks(u);
-        const bool u_in = interior(u);
-        uint32_t cn = 0, mn = 0;   // candidates, matches (wave-uniform)
+        const uint64_t chunk_lo = unit_lo + (uint64_t)g * kChunk;
+        if (g == 0) {
+            cn = 0;
+            mn = 0;
+        }
         uint4 *const wcg = SPLIT ? a.cand + u * a.cand_cap : nullptr;
         // queue a candidate (ballot mask mk over the wave); the split kernels
         // also pass on the 8 text bytes after the level index, B[pl+K ..
@@ -486,57 +488,180 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             cn = 0;
         };
 
-        for (uint32_t g = 0; g < nch; g++) {
-            const uint64_t chunk_lo = unit_lo + (uint64_t)g * kChunk;
-            // the chunk after next, in flight while this one is filtered
-            const Vec2 c2 = prefetch();
-            const uint4 nx2 = c2.v, nx2_h = c2.h;
+        *(uint4 *)(wtext + 16 * lane) = sl.v;
+        if (lane == 0) *(uint4 *)(wtext + kChunk) = sl.h;
+        wave_sync();
 
-            *(uint4 *)(wtext + 16 * lane) = cur;
-            if (lane == 0) {
-                const bool more = g + 1 < nch;  // the next chunk follows this one
-                *(uint4 *)(wtext + kChunk) = make_uint4(more ? nxt.x : cur_h.x, more ? nxt.y : cur_h.y,
-                                                        more ? nxt.z : cur_h.z, more ? nxt.w : cur_h.w);
+        // Text boundaries of the chunk: the distance from its start to the
+        // first boundary at or past its end, and up to four inside it in
+        // ascending order (from the batch plan, or from the text's two ends);
+        // more than four: the bit map in LDS.
+        // (read in every case: a load left unread would hold up the next
+        // load into its registers)
+        uint32_t bx = (uint32_t)__builtin_amdgcn_readfirstlane((int)sl.info.x);
+        uint32_t by = (uint32_t)__builtin_amdgcn_readfirstlane((int)sl.info.y);
+        if (!a.chunk_info) {
+            // the text's first byte and its end: ascending, at most one of
+            // each in the chunk
+            const bool lo_in = lo_valid >= chunk_lo && lo_valid < chunk_lo + kChunk;
+            const bool hi_in = hi_valid >= chunk_lo && hi_valid < chunk_lo + kChunk;
+            const uint32_t lo_rel = (uint32_t)(lo_valid - chunk_lo) & 0x3ffu;
+            const uint32_t hi_rel = (uint32_t)(hi_valid - chunk_lo) & 0x3ffu;
+            const uint64_t hi_dist = hi_valid - chunk_lo;
+            const uint32_t nrel0 = hi_in || hi_dist > 0x1ffffull ? 0x1ffffu : (uint32_t)hi_dist;
+            const uint32_t cnt = (uint32_t)lo_in + (uint32_t)hi_in;
+            bx = nrel0 | (cnt << 17) | ((lo_in ? lo_rel : hi_rel) << 20);
+            by = lo_in && hi_in ? hi_rel : 0u;
+        }
+        const uint32_t bcnt = (bx >> 17) & 7u;
+        const uint32_t nrel = bx & 0x1ffffu;
+        bool dirty = false;
+        unsigned long long next_bnd = 0;
+        if (bcnt > 4) chunk_bounds(a, chunk_lo / kChunk, chunk_lo, wbnd, dirty, next_bnd);
+        // distance from chunk position pl to the end of its text, at most 0xffff
+        auto lim_of = [&](uint32_t pl) -> uint32_t {
+            if (bcnt > 4) return limit_after(wbnd, dirty, chunk_lo, pl, next_bnd);
+            uint32_t nb = nrel;
+            if (bcnt) {
+                const uint32_t b0 = bx >> 20, b1 = by & 0x3ffu, b2 = (by >> 10) & 0x3ffu, b3 = by >> 20;
+                // the list is ascending and unused entries are 0: the least
+                // entry above pl is the first boundary after it
+                nb = b3 > pl ? b3 : nb;
+                nb = b2 > pl ? b2 : nb;
+                nb = b1 > pl ? b1 : nb;
+                nb = b0 > pl ? b0 : nb;
             }
-            bool dirty = false;
-            unsigned long long next_bnd = hi_valid;
-            if (!u_in) chunk_bounds(a, chunk_lo / kChunk, chunk_lo, wbnd, dirty, next_bnd);
+            return min(nb - pl, 0xffffu);
+        };
+        // valid chunk positions (inside the batch's or the text's range)
+        const uint32_t vlo = lo_valid > chunk_lo ? (uint32_t)umin64(lo_valid - chunk_lo, kWin) : 0u;
+        const uint32_t vhi = hi_valid > chunk_lo ? (uint32_t)umin64(hi_valid - chunk_lo, kWin) : 0u;
 
-            uint32_t w[8];
-            {
-                w[0] = cur.x; w[1] = cur.y; w[2] = cur.z; w[3] = cur.w;
-                const uint4 x = *(const uint4 *)(wtext + 16 * lane + 16);
-                w[4] = x.x; w[5] = x.y; w[6] = x.z; w[7] = x.w;
+        uint32_t w[8];
+        {
+            w[0] = sl.v.x; w[1] = sl.v.y; w[2] = sl.v.z; w[3] = sl.v.w;
+            const uint4 x = *(const uint4 *)(wtext + 16 * lane + 16);
+            w[4] = x.x; w[5] = x.y; w[6] = x.z; w[7] = x.w;
+        }
+
+        // ---- stage 2: the exact byte after the level index, the end of
+        // the text, and the depth-K node; survivors become candidates.
+        // decode(e) gives (window position, K-symbol code) of entry e.
+        auto stage2 = [&](uint32_t qn, auto decode) {
+            for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
+                if (!SPLIT && cn + 64 > ccap) flush();
+                const uint32_t e = r0 + lane;
+                bool pass2 = false;
+                uint32_t entry = 0, v = 0;
+                if (e < qn) {
+                    const uint2 pc = decode(e);
+                    const uint32_t pl = pc.x;
+                    const uint64_t p = chunk_lo + pl;
+                    const uint32_t lim = lim_of(pl);
+                    // the filter read K + 1 bytes: all must be in this text
+                    pass2 = p >= lo_valid && p < hi_valid && lim > K;
+                    if (pass2 && K) {
+                        const uint32_t code = pc.y;
+                        const uint32_t bits = s_bits[code >> 5];
+                        const uint32_t below = bits & ((1u << (code & 31)) - 1u);
+                        const uint32_t rank = s_rank[code >> 5] + (uint32_t)__builtin_popcount(below);
+                        v = im.lvl_start + rank;
+                        if (krec) {
+                            // up to three child labels, or 0xff.. for more
+                            const uint32_t rec = s_krec[rank];
+                            const uint32_t ncc = rec >> 24;
+                            if (ncc <= 3) {
+                                const uint32_t c = wtext[pl + K];
+                                const uint32_t x = rec ^ (c * 0x00010101u);
+                                const uint32_t mm = (x - 0x00010101u) & ~x & 0x00808080u;
+                                pass2 = mm != 0 && ((uint32_t)__builtin_ctz(mm) >> 3) < ncc;
+                            }
+                        }
+                    }
+                    entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
+                }
+                push(pass2, __ballot(pass2), entry, v, entry & (kChunk - 1));
             }
+            wave_sync();
+        };
 
-            // ---- stage 2: the exact byte after the level index, the end of
-            // the text, and the depth-K node; survivors become candidates.
-            // decode(e) gives (window position, K-symbol code) of entry e.
-            auto stage2 = [&](uint32_t qn, auto decode) {
+        if (MODE == 1 || MODE == 2) {
+            // ---- stage 1 over the lane's 16 positions into a hit mask:
+            // code = (B[j] << 8) | B[j+1] indexes the table, B[j+2]
+            // picks the folded child bit.  The table is the first LDS
+            // section and the kernel has no static LDS, so the code is
+            // the LDS address; all sixteen lookups are issued before any
+            // is used.
+            uint32_t ent[16];
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const uint32_t lo = w[j >> 2], hi = w[(j >> 2) + 1];
+                const uint32_t r = j & 3;
+                const uint32_t code = __builtin_amdgcn_perm(hi, lo, 0x0c0c0000u | (r << 8) | (r + 1));
+                ent[j] = MODE == 1 ? (uint32_t)lds_tab8()[code] : (uint32_t)lds_tab16()[code];
+            }
+            uint32_t hm = 0;
+#pragma unroll
+            for (int j = 0; j < 16; j++) {
+                const uint32_t nx = __builtin_amdgcn_ubfe(w[(j + 2) >> 2], 8 * ((j + 2) & 3),
+                                                          MODE == 1 ? 3 : 4);
+                hm |= __builtin_amdgcn_ubfe(ent[j], nx, 1) << j;
+            }
+            // compact the hits of the wave, at most kQ16 per round
+            uint16_t *wq16 = (uint16_t *)wq;
+            uint32_t tot;
+            const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
+            const int rounds = tot > kQ16 ? 2 : 1;
+            // valid positions and the distance to the next text boundary,
+            // relative to the chunk (wave-uniform)
+            for (int half = 0; half < rounds; half++) {
+                uint32_t mset = hm, o = off_all, qn = tot, jb = 0;
+                if (rounds == 2) {
+                    mset = half == 0 ? (hm & 0xffu) : (hm >> 8);
+                    jb = half == 0 ? 0u : 8u;
+                    o = wave_excl_scan((uint32_t)__builtin_popcount(mset), qn);
+                }
+                while (mset) {
+                    const uint32_t j = (uint32_t)__builtin_ctz(mset);
+                    wq16[o++] = (uint16_t)(16 * lane + jb + j);
+                    mset &= mset - 1;
+                }
+                wave_sync();
+                // ---- stage 2 (K = 2): the text's end, the exact third
+                // byte against the depth-2 node's child labels, the node
                 for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
                     if (!SPLIT && cn + 64 > ccap) flush();
                     const uint32_t e = r0 + lane;
                     bool pass2 = false;
                     uint32_t entry = 0, v = 0;
                     if (e < qn) {
-                        const uint2 pc = decode(e);
-                        const uint32_t pl = pc.x;
-                        const uint64_t p = chunk_lo + pl;
-                        const uint32_t lim = limit_after(wbnd, dirty, chunk_lo, pl, next_bnd);
-                        // the filter read K + 1 bytes: all must be in this text
-                        pass2 = p >= lo_valid && p < hi_valid && lim > K;
-                        if (pass2 && K) {
-                            const uint32_t code = pc.y;
+                        const uint32_t pl = wq16[e];
+                        const uint32_t a4 = pl & ~3u;
+                        const uint32_t d0 = *(const uint32_t *)(wtext + a4);
+                        const uint32_t d1 = *(const uint32_t *)(wtext + a4 + 4);
+                        const uint32_t by = __builtin_amdgcn_alignbyte(d1, d0, pl & 3u);  // B[pl..pl+3]
+                        const uint32_t lim = lim_of(pl);
+                        // with the prefix-4 filter every pattern is 4 bytes or longer
+                        pass2 = pl >= vlo && pl < vhi && lim > (pfx4 ? 3u : 2u);
+                        if (pass2 && pfx4) {
+                            // both bits of the first four bytes' hash must be set
+                            const uint64_t m = (uint64_t)by * im.pfx4_mul;
+                            const uint32_t sh = 32u - im.pfx4_log2;
+                            const uint32_t h1 = (uint32_t)m >> sh, h2 = (uint32_t)(m >> 32) >> sh;
+                            pass2 = ((s_pfx4[h1 >> 5] >> (h1 & 31)) & (s_pfx4[h2 >> 5] >> (h2 & 31)) & 1u) != 0;
+                        }
+                        if (pass2) {
+                            const uint32_t code = __builtin_amdgcn_perm(0u, by, 0x0c0c0001u);
                             const uint32_t bits = s_bits[code >> 5];
-                            const uint32_t below = bits & ((1u << (code & 31)) - 1u);
-                            const uint32_t rank = s_rank[code >> 5] + (uint32_t)__builtin_popcount(below);
+                            const uint32_t rank = s_rank[code >> 5] +
+                                (uint32_t)__builtin_popcount(bits & ((1u << (code & 31)) - 1u));
                             v = im.lvl_start + rank;
                             if (krec) {
-                                // up to three child labels, or 0xff.. for more
+                                // up to three child labels, or a count above 3
                                 const uint32_t rec = s_krec[rank];
                                 const uint32_t ncc = rec >> 24;
                                 if (ncc <= 3) {
-                                    const uint32_t c = wtext[pl + K];
+                                    const uint32_t c = (by >> 16) & 0xffu;
                                     const uint32_t x = rec ^ (c * 0x00010101u);
                                     const uint32_t mm = (x - 0x00010101u) & ~x & 0x00808080u;
                                     pass2 = mm != 0 && ((uint32_t)__builtin_ctz(mm) >> 3) < ncc;
@@ -548,292 +673,203 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                     push(pass2, __ballot(pass2), entry, v, entry & (kChunk - 1));
                 }
                 wave_sync();
+            }
+        } else if (MODE == 3) {
+            // ---- four-symbol alphabets.  Stage 1: the lane's 32 bytes
+            // as 2-bit symbols (symbol j at bits 2j of P), the 16-symbol
+            // key of position j = bits [2j, 2j + 32), one LDS word of the
+            // filter per position, two bits of it tested.
+            const uint32_t qa = im.qa, qb = im.qb;
+            // 2-bit symbols of the four bytes of x in one byte: a dot
+            // product of the per-byte symbols with weights 1, 4, 16, 64
+            auto pack4 = [&](uint32_t x) -> uint32_t {
+                const uint32_t t = ((x >> qa) ^ (x >> qb)) & 0x03030303u;
+                return __builtin_amdgcn_udot4(t, 0x40100401u, 0u, false);
             };
-
-            if (MODE == 1 || MODE == 2) {
-                // ---- stage 1 over the lane's 16 positions into a hit mask:
-                // code = (B[j] << 8) | B[j+1] indexes the table, B[j+2]
-                // picks the folded child bit.  The table is the first LDS
-                // section and the kernel has no static LDS, so the code is
-                // the LDS address; all sixteen lookups are issued before any
-                // is used.
-                uint32_t ent[16];
+            const uint32_t P0 = pack4(w[0]) | pack4(w[1]) << 8 | pack4(w[2]) << 16 | pack4(w[3]) << 24;
+            const uint32_t P1 = pack4(w[4]) | pack4(w[5]) << 8 | pack4(w[6]) << 16 | pack4(w[7]) << 24;
+            const uint32_t qsh = 32u - im.q16_lw;
+            uint32_t hh[16], ent[16];
 #pragma unroll
-                for (int j = 0; j < 16; j++) {
-                    const uint32_t lo = w[j >> 2], hi = w[(j >> 2) + 1];
-                    const uint32_t r = j & 3;
-                    const uint32_t code = __builtin_amdgcn_perm(hi, lo, 0x0c0c0000u | (r << 8) | (r + 1));
-                    ent[j] = MODE == 1 ? (uint32_t)lds_tab8()[code] : (uint32_t)lds_tab16()[code];
-                }
-                uint32_t hm = 0;
+            for (int j = 0; j < 16; j++) {
+                const uint32_t key = j == 0 ? P0 : __builtin_amdgcn_alignbit(P1, P0, 2 * j);
+                hh[j] = __umul24(key, im.q16_mul) + (key >> 8);  // 24 x 24-bit multiply
+                ent[j] = lds_tab32()[hh[j] >> qsh];
+            }
+            uint32_t hm = 0;
 #pragma unroll
-                for (int j = 0; j < 16; j++) {
-                    const uint32_t nx = __builtin_amdgcn_ubfe(w[(j + 2) >> 2], 8 * ((j + 2) & 3),
-                                                              MODE == 1 ? 3 : 4);
-                    hm |= __builtin_amdgcn_ubfe(ent[j], nx, 1) << j;
+            for (int j = 0; j < 16; j++)
+                hm |= ((ent[j] >> hh[j]) & (ent[j] >> (hh[j] >> 5)) & 1u) << j;
+            uint16_t *wq16 = (uint16_t *)wq;
+            uint32_t tot;
+            const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
+            const int rounds = tot > kQ16 ? 2 : 1;
+            for (int half = 0; half < rounds; half++) {
+                uint32_t mset = hm, o = off_all, qn = tot, jb = 0;
+                if (rounds == 2) {
+                    mset = half == 0 ? (hm & 0xffu) : (hm >> 8);
+                    jb = half == 0 ? 0u : 8u;
+                    o = wave_excl_scan((uint32_t)__builtin_popcount(mset), qn);
                 }
-                // compact the hits of the wave, at most kQ16 per round
-                uint16_t *wq16 = (uint16_t *)wq;
-                uint32_t tot;
-                const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
-                const int rounds = tot > kQ16 ? 2 : 1;
-                // valid positions and the distance to the next text boundary,
-                // relative to the chunk (wave-uniform)
-                uint32_t vlo = 0, vhi = kWin, nb_rel = 0x20000;
-                if (!u_in) {
-                    vlo = lo_valid > chunk_lo ? (uint32_t)min(lo_valid - chunk_lo, (uint64_t)kWin) : 0u;
-                    vhi = hi_valid > chunk_lo ? (uint32_t)min(hi_valid - chunk_lo, (uint64_t)kWin) : 0u;
-                    nb_rel = (uint32_t)min(next_bnd - chunk_lo, (unsigned long long)0x20000);
+                while (mset) {
+                    const uint32_t j = (uint32_t)__builtin_ctz(mset);
+                    wq16[o++] = (uint16_t)(16 * lane + jb + j);
+                    mset &= mset - 1;
                 }
-                for (int half = 0; half < rounds; half++) {
-                    uint32_t mset = hm, o = off_all, qn = tot, jb = 0;
-                    if (rounds == 2) {
-                        mset = half == 0 ? (hm & 0xffu) : (hm >> 8);
-                        jb = half == 0 ? 0u : 8u;
-                        o = wave_excl_scan((uint32_t)__builtin_popcount(mset), qn);
-                    }
-                    while (mset) {
-                        const uint32_t j = (uint32_t)__builtin_ctz(mset);
-                        wq16[o++] = (uint16_t)(16 * lane + jb + j);
-                        mset &= mset - 1;
-                    }
-                    wave_sync();
-                    // ---- stage 2 (K = 2): the text's end, the exact third
-                    // byte against the depth-2 node's child labels, the node
-                    for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
-                        if (!SPLIT && cn + 64 > ccap) flush();
-                        const uint32_t e = r0 + lane;
-                        bool pass2 = false;
-                        uint32_t entry = 0, v = 0;
-                        if (e < qn) {
-                            const uint32_t pl = wq16[e];
-                            const uint32_t a4 = pl & ~3u;
-                            const uint32_t d0 = *(const uint32_t *)(wtext + a4);
-                            const uint32_t d1 = *(const uint32_t *)(wtext + a4 + 4);
-                            const uint32_t by = __builtin_amdgcn_alignbyte(d1, d0, pl & 3u);  // B[pl..pl+3]
-                            const uint32_t lim = dirty ? limit_after(wbnd, dirty, chunk_lo, pl, next_bnd)
-                                                       : min(nb_rel - pl, 0xffffu);
-                            // with the prefix-4 filter every pattern is 4 bytes or longer
-                            pass2 = pl >= vlo && pl < vhi && lim > (pfx4 ? 3u : 2u);
-                            if (pass2 && pfx4) {
-                                // both bits of the first four bytes' hash must be set
-                                const uint64_t m = (uint64_t)by * im.pfx4_mul;
-                                const uint32_t sh = 32u - im.pfx4_log2;
-                                const uint32_t h1 = (uint32_t)m >> sh, h2 = (uint32_t)(m >> 32) >> sh;
-                                pass2 = ((s_pfx4[h1 >> 5] >> (h1 & 31)) & (s_pfx4[h2 >> 5] >> (h2 & 31)) & 1u) != 0;
+                wave_sync();
+                // ---- stage 2: the 16 bytes all in this text and all of
+                // the alphabet, the key's fingerprint in its buckets,
+                // then the depth-K node from the level index
+                for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
+                    const uint32_t e = r0 + lane;
+                    bool pass2 = false;
+                    uint32_t entry = 0, v = 0, pl = 0;
+                    if (e < qn) {
+                        pl = wq16[e];
+                        const uint32_t lim = lim_of(pl);
+                        pass2 = pl >= vlo && pl < vhi && lim >= 16u;
+                        entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
+                        uint32_t key = 0;
+                        if (pass2) {
+                            const uint32_t *t32 = (const uint32_t *)(wtext + (pl & ~3u));
+                            uint32_t d[5];
+#pragma unroll
+                            for (int k = 0; k < 5; k++) d[k] = t32[k];
+                            bool valid = true;
+#pragma unroll
+                            for (int k = 0; k < 4; k++) {
+                                const uint32_t x = __builtin_amdgcn_alignbyte(d[k + 1], d[k], pl & 3u);
+                                const uint32_t t = ((x >> qa) ^ (x >> qb)) & 0x03030303u;
+                                valid = valid && __builtin_amdgcn_perm(0u, im.qalph, t) == x;
+                                key |= __builtin_amdgcn_udot4(t, 0x40100401u, 0u, false) << (8 * k);
                             }
-                            if (pass2) {
-                                const uint32_t code = __builtin_amdgcn_perm(0u, by, 0x0c0c0001u);
-                                const uint32_t bits = s_bits[code >> 5];
-                                const uint32_t rank = s_rank[code >> 5] +
-                                    (uint32_t)__builtin_popcount(bits & ((1u << (code & 31)) - 1u));
-                                v = im.lvl_start + rank;
-                                if (krec) {
-                                    // up to three child labels, or a count above 3
-                                    const uint32_t rec = s_krec[rank];
-                                    const uint32_t ncc = rec >> 24;
-                                    if (ncc <= 3) {
-                                        const uint32_t c = (by >> 16) & 0xffu;
-                                        const uint32_t x = rec ^ (c * 0x00010101u);
-                                        const uint32_t mm = (x - 0x00010101u) & ~x & 0x00808080u;
-                                        pass2 = mm != 0 && ((uint32_t)__builtin_ctz(mm) >> 3) < ncc;
-                                    }
-                                }
-                            }
-                            entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
+                            pass2 = valid;
                         }
-                        push(pass2, __ballot(pass2), entry, v, entry & (kChunk - 1));
-                    }
-                    wave_sync();
-                }
-            } else if (MODE == 3) {
-                // ---- four-symbol alphabets.  Stage 1: the lane's 32 bytes
-                // as 2-bit symbols (symbol j at bits 2j of P), the 16-symbol
-                // key of position j = bits [2j, 2j + 32), one LDS word of the
-                // filter per position, two bits of it tested.
-                const uint32_t qa = im.qa, qb = im.qb;
-                // 2-bit symbols of the four bytes of x in one byte: a dot
-                // product of the per-byte symbols with weights 1, 4, 16, 64
-                auto pack4 = [&](uint32_t x) -> uint32_t {
-                    const uint32_t t = ((x >> qa) ^ (x >> qb)) & 0x03030303u;
-                    return __builtin_amdgcn_udot4(t, 0x40100401u, 0u, false);
-                };
-                const uint32_t P0 = pack4(w[0]) | pack4(w[1]) << 8 | pack4(w[2]) << 16 | pack4(w[3]) << 24;
-                const uint32_t P1 = pack4(w[4]) | pack4(w[5]) << 8 | pack4(w[6]) << 16 | pack4(w[7]) << 24;
-                const uint32_t qsh = 32u - im.q16_lw;
-                uint32_t hh[16], ent[16];
+                        if (pass2 && im.qfp_lb) {
+                            const uint32_t h2 = key * a.im.pfx4_mul;
+                            const uint32_t fp = (h2 & 0xffffu) | 1u;
+                            const uint32_t nb = 1u << im.qfp_lb;
+                            const uint32_t bk = h2 >> (32u - im.qfp_lb);
+                            const uint4 f[2] = {im.qfp[bk], im.qfp[(bk + 1) & (nb - 1)]};
+                            const uint32_t fp2 = fp * 0x00010001u;
+                            uint32_t hit = 0;
 #pragma unroll
-                for (int j = 0; j < 16; j++) {
-                    const uint32_t key = j == 0 ? P0 : __builtin_amdgcn_alignbit(P1, P0, 2 * j);
-                    hh[j] = __umul24(key, im.q16_mul) + (key >> 8);  // 24 x 24-bit multiply
-                    ent[j] = lds_tab32()[hh[j] >> qsh];
-                }
-                uint32_t hm = 0;
+                            for (int k = 0; k < 2; k++) {
+                                const uint32_t wv[4] = {f[k].x, f[k].y, f[k].z, f[k].w};
 #pragma unroll
-                for (int j = 0; j < 16; j++)
-                    hm |= ((ent[j] >> hh[j]) & (ent[j] >> (hh[j] >> 5)) & 1u) << j;
-                uint16_t *wq16 = (uint16_t *)wq;
-                uint32_t tot;
-                const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
-                const int rounds = tot > kQ16 ? 2 : 1;
-                uint32_t vlo = 0, vhi = kWin, nb_rel = 0x20000;
-                if (!u_in) {
-                    vlo = lo_valid > chunk_lo ? (uint32_t)min(lo_valid - chunk_lo, (uint64_t)kWin) : 0u;
-                    vhi = hi_valid > chunk_lo ? (uint32_t)min(hi_valid - chunk_lo, (uint64_t)kWin) : 0u;
-                    nb_rel = (uint32_t)min(next_bnd - chunk_lo, (unsigned long long)0x20000);
-                }
-                for (int half = 0; half < rounds; half++) {
-                    uint32_t mset = hm, o = off_all, qn = tot, jb = 0;
-                    if (rounds == 2) {
-                        mset = half == 0 ? (hm & 0xffu) : (hm >> 8);
-                        jb = half == 0 ? 0u : 8u;
-                        o = wave_excl_scan((uint32_t)__builtin_popcount(mset), qn);
-                    }
-                    while (mset) {
-                        const uint32_t j = (uint32_t)__builtin_ctz(mset);
-                        wq16[o++] = (uint16_t)(16 * lane + jb + j);
-                        mset &= mset - 1;
-                    }
-                    wave_sync();
-                    // ---- stage 2: the 16 bytes all in this text and all of
-                    // the alphabet, the key's fingerprint in its buckets,
-                    // then the depth-K node from the level index
-                    for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
-                        const uint32_t e = r0 + lane;
-                        bool pass2 = false;
-                        uint32_t entry = 0, v = 0, pl = 0;
-                        if (e < qn) {
-                            pl = wq16[e];
-                            const uint32_t lim = dirty ? limit_after(wbnd, dirty, chunk_lo, pl, next_bnd)
-                                                       : min(nb_rel - pl, 0xffffu);
-                            pass2 = pl >= vlo && pl < vhi && lim >= 16u;
-                            entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
-                            uint32_t key = 0;
-                            if (pass2) {
-                                const uint32_t *t32 = (const uint32_t *)(wtext + (pl & ~3u));
-                                uint32_t d[5];
-#pragma unroll
-                                for (int k = 0; k < 5; k++) d[k] = t32[k];
-                                bool valid = true;
-#pragma unroll
-                                for (int k = 0; k < 4; k++) {
-                                    const uint32_t x = __builtin_amdgcn_alignbyte(d[k + 1], d[k], pl & 3u);
-                                    const uint32_t t = ((x >> qa) ^ (x >> qb)) & 0x03030303u;
-                                    valid = valid && __builtin_amdgcn_perm(0u, im.qalph, t) == x;
-                                    key |= __builtin_amdgcn_udot4(t, 0x40100401u, 0u, false) << (8 * k);
+                                for (int q = 0; q < 4; q++) {
+                                    const uint32_t x = wv[q] ^ fp2;  // a zero half = equal fingerprint
+                                    hit |= (x - 0x00010001u) & ~x & 0x80008000u;
                                 }
-                                pass2 = valid;
                             }
-                            if (pass2 && im.qfp_lb) {
-                                const uint32_t h2 = key * a.im.pfx4_mul;
-                                const uint32_t fp = (h2 & 0xffffu) | 1u;
-                                const uint32_t nb = 1u << im.qfp_lb;
-                                const uint32_t bk = h2 >> (32u - im.qfp_lb);
-                                const uint4 f[2] = {im.qfp[bk], im.qfp[(bk + 1) & (nb - 1)]};
-                                const uint32_t fp2 = fp * 0x00010001u;
-                                uint32_t hit = 0;
-#pragma unroll
-                                for (int k = 0; k < 2; k++) {
-                                    const uint32_t wv[4] = {f[k].x, f[k].y, f[k].z, f[k].w};
-#pragma unroll
-                                    for (int q = 0; q < 4; q++) {
-                                        const uint32_t x = wv[q] ^ fp2;  // a zero half = equal fingerprint
-                                        hit |= (x - 0x00010001u) & ~x & 0x80008000u;
-                                    }
-                                }
-                                pass2 = hit != 0;
-                            }
-                            if (pass2) {
-                                // depth-K code, first symbol highest: the low
-                                // 2K bits of the key with the symbol order reversed
-                                const uint32_t r = __builtin_bitreverse32(key);
-                                uint32_t code = ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
-                                code >>= 32u - 2u * K;
-                                const uint2 lv = ((const uint2 *)im.lvl)[code >> 5];
-                                v = im.lvl_start + lv.y +
-                                    (uint32_t)__builtin_popcount(lv.x & ((1u << (code & 31)) - 1u));
-                                pass2 = (lv.x >> (code & 31)) & 1u;
-                            }
+                            pass2 = hit != 0;
                         }
-                        push(pass2, __ballot(pass2), entry, v, pl);
+                        if (pass2) {
+                            // depth-K code, first symbol highest: the low
+                            // 2K bits of the key with the symbol order reversed
+                            const uint32_t r = __builtin_bitreverse32(key);
+                            uint32_t code = ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
+                            code >>= 32u - 2u * K;
+                            const uint2 lv = ((const uint2 *)im.lvl)[code >> 5];
+                            v = im.lvl_start + lv.y +
+                                (uint32_t)__builtin_popcount(lv.x & ((1u << (code & 31)) - 1u));
+                            pass2 = (lv.x >> (code & 31)) & 1u;
+                        }
                     }
-                    wave_sync();
+                    push(pass2, __ballot(pass2), entry, v, pl);
                 }
-            } else {
-                // generic filter: rolling code over L = K + m symbols
-                const uint32_t b = im.b;
-                const uint32_t m = (K >= 1 && a.fold) ? im.fold_syms : 0u;
-                const uint32_t L = K >= 1 ? K + m : 1u;
-                const uint32_t full_mask = (b * L >= 32) ? 0xffffffffu : ((1u << (b * L)) - 1u);
-                const uint32_t fmask = (a.fold - 1u) & ((b * m >= 32) ? 0xffffffffu : ((1u << (b * m)) - 1u));
-                uint32_t full = 0, run = 0;
-                // the first L - 1 symbols of the lane window
+                wave_sync();
+            }
+        } else {
+            // generic filter: rolling code over L = K + m symbols
+            const uint32_t b = im.b;
+            const uint32_t m = (K >= 1 && a.fold) ? im.fold_syms : 0u;
+            const uint32_t L = K >= 1 ? K + m : 1u;
+            const uint32_t full_mask = (b * L >= 32) ? 0xffffffffu : ((1u << (b * L)) - 1u);
+            const uint32_t fmask = (a.fold - 1u) & ((b * m >= 32) ? 0xffffffffu : ((1u << (b * m)) - 1u));
+            uint32_t full = 0, run = 0;
+            // the first L - 1 symbols of the lane window
 #pragma unroll
-                for (int j = 0; j < 15; j++) {
-                    if ((uint32_t)j + 1 >= L) continue;
-                    const uint32_t byte = wbyte(w, j);
+            for (int j = 0; j < 15; j++) {
+                if ((uint32_t)j + 1 >= L) continue;
+                const uint32_t byte = wbyte(w, j);
+                uint32_t s = byte;
+                bool ok = true;
+                if (!im.identity) { s = s_sym[byte]; ok = s != 0xffu; }
+                run = ok ? run + 1 : 0u;
+                full = ((full << b) | (s & 0xffu)) & full_mask;
+            }
+#pragma unroll
+            for (int pass = 0; pass < 16 / (int)kPPL; pass++) {
+                uint32_t qn = 0;
+#pragma unroll
+                for (int jj = 0; jj < (int)kPPL; jj++) {
+                    const int j = pass * (int)kPPL + jj;
+                    // the symbol at window byte j + L - 1 completes position j
+                    const uint32_t byte = wtext[16 * lane + j + L - 1];
                     uint32_t s = byte;
                     bool ok = true;
                     if (!im.identity) { s = s_sym[byte]; ok = s != 0xffu; }
                     run = ok ? run + 1 : 0u;
                     full = ((full << b) | (s & 0xffu)) & full_mask;
-                }
-#pragma unroll
-                for (int pass = 0; pass < 16 / (int)kPPL; pass++) {
-                    uint32_t qn = 0;
-#pragma unroll
-                    for (int jj = 0; jj < (int)kPPL; jj++) {
-                        const int j = pass * (int)kPPL + jj;
-                        // the symbol at window byte j + L - 1 completes position j
-                        const uint32_t byte = wtext[16 * lane + j + L - 1];
-                        uint32_t s = byte;
-                        bool ok = true;
-                        if (!im.identity) { s = s_sym[byte]; ok = s != 0xffu; }
-                        run = ok ? run + 1 : 0u;
-                        full = ((full << b) | (s & 0xffu)) & full_mask;
-                        uint32_t hit = 0, code = 0;
-                        if (run >= L) {
-                            if (K == 0) {
-                                hit = (s_root[full >> 5] >> (full & 31)) & 1u;
-                            } else if (a.fold) {
-                                code = full >> (b * m);
-                                const uint32_t bit = full & fmask;
-                                hit = a.fold == 8 ? (s_ftab[code] >> bit) & 1u
-                                                  : (((const uint16_t *)s_ftab)[code] >> bit) & 1u;
-                            } else {
-                                code = full;
-                                hit = (s_bits[code >> 5] >> (code & 31)) & 1u;
-                            }
+                    uint32_t hit = 0, code = 0;
+                    if (run >= L) {
+                        if (K == 0) {
+                            hit = (s_root[full >> 5] >> (full & 31)) & 1u;
+                        } else if (a.fold) {
+                            code = full >> (b * m);
+                            const uint32_t bit = full & fmask;
+                            hit = a.fold == 8 ? (s_ftab[code] >> bit) & 1u
+                                              : (((const uint16_t *)s_ftab)[code] >> bit) & 1u;
+                        } else {
+                            code = full;
+                            hit = (s_bits[code >> 5] >> (code & 31)) & 1u;
                         }
-                        const unsigned long long mk = __ballot(hit != 0);
-                        if (hit) wq[qn + mbcnt(mk)] = ((16 * lane + j) << 20) | code;
-                        qn += (uint32_t)__popcll(mk);
                     }
-                    wave_sync();
-                    stage2(qn, [&](uint32_t e) {
-                        const uint32_t ent = wq[e];
-                        return make_uint2(ent >> 20, ent & 0xfffffu);
-                    });
+                    const unsigned long long mk = __ballot(hit != 0);
+                    if (hit) wq[qn + mbcnt(mk)] = ((16 * lane + j) << 20) | code;
+                    qn += (uint32_t)__popcll(mk);
                 }
+                wave_sync();
+                stage2(qn, [&](uint32_t e) {
+                    const uint32_t ent = wq[e];
+                    return make_uint2(ent >> 20, ent & 0xfffffu);
+                });
             }
-            cur = nxt;
-            cur_h = nxt_h;
-            nxt = nx2;
-            nxt_h = nx2_h;
         }
-        if (SPLIT) {
-            if (lane == 0) a.cand_count[u] = cn;
-            continue;
+        // the unit's last chunk: hand over or emit its results
+        if (g + 1 == nch) {
+            if (SPLIT) {
+                if (lane == 0) a.cand_count[u] = cn;
+            } else {
+                flush();
+                wave_sync();
+                // ---- this unit's matches, in (pos, id) order
+                if (mn <= mcap)
+                    emit_unit(a, u, unit_lo, wm, mn, (uint2 *)wq);
+                else
+                    unit_from_root(a, u, unit_lo, nch, wbnd);
+                wave_sync();
+            }
         }
-        flush();
-        wave_sync();
+        advance(cc);
+        return cc.u < n_units;
+    };
 
-        // ---- this unit's matches, in (pos, id) order
-        if (mn <= mcap)
-            emit_unit(a, u, unit_lo, wm, mn, (uint2 *)wq);
-        else
-            unit_from_root(a, u, unit_lo, nch, wbnd);
-        wave_sync();
+    // The next chunk's loads are issued as soon as the current chunk's data
+    // has arrived, so they are in flight while it is filtered.
+    Cur cc = start_at((uint64_t)blockIdx.x * waves + wave);
+    if (cc.u < n_units) {
+        Cur pc = cc;
+        Slot sl = load_slot(pc);
+        advance(pc);
+        bool more;
+        do {
+            const Slot cur = sl;
+            sl = load_slot(pc);
+            advance(pc);
+            more = chunk(cur, cc);
+        } while (more);
     }
 }
 
