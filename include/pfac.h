@@ -298,7 +298,9 @@ int pfac_scan_batch_plain(const pfac_trie *t, pfac_workspace *w, const uint8_t *
  * a pfac_trie_set_tuning that would rebuild it (index_bits, fold_bits,
  * trunc_depth or dag changed, as the autotuner may do) fails with
  * PFAC_EBUSY, and the trie must outlive the graph.  Replays of one graph
- * must not overlap each other.
+ * must not overlap each other.  The capture runs on a stream the library
+ * creates for it; `stream` is not used (replays take theirs in
+ * pfac_graph_launch).
  */
 int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w, const uint8_t *texts_dev,
                             const uint64_t *offsets_dev, uint32_t n_texts, uint64_t total_bytes,

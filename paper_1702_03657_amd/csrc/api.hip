@@ -110,6 +110,9 @@ struct pfac_workspace {
     DeviceBuf cand, cand_count;  // split wave kernels: walk candidates per unit
     DeviceBuf chunk_info;        // wave kernels, batches: text boundaries per 1 KiB chunk
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;  // optional kernel timing
+    // launch shape of the last main scan kernel (grid, block, dynamic LDS):
+    // graphs find its node by it
+    uint32_t main_grid = 0, main_block = 0, main_lds = 0;
     // misc: [0] stage cursor, [1] running total, [2] per-launch count
     unsigned long long *cursor() { return (unsigned long long *)misc.p; }
     unsigned long long *running() { return (unsigned long long *)misc.p + 1; }
@@ -124,6 +127,7 @@ struct pfac_graph {
     // event-record nodes around the main scan kernel (captured when the
     // workspace passed at creation had timing events), else NULL
     hipGraphNode_t n_start = nullptr, n_stop = nullptr;
+    hipEvent_t ev_own[2] = {nullptr, nullptr};  // recorded by those nodes at capture
 };
 
 extern "C" int pfac_last_hip_error(void) { return g_last_hip; }
@@ -774,6 +778,8 @@ static int enqueue_scan(const Launch &L, bool reserve) {
         a.cand_cap = a.group * kCandPerChunk;
     }
     if (a.lds_total > t->lds_limit) return PFAC_EINVAL;
+    // the wave kernels count 1 KiB chunks in 32 bits
+    if (wave_kernel && n_plan >= (1ull << 31)) return PFAC_EINVAL;
 
     a.n_sums = n_sums;
     // the split filter kernel clears the block sums and the cursor itself
@@ -806,6 +812,9 @@ static int enqueue_scan(const Launch &L, bool reserve) {
         if (w->ev_start) HIP_TRY(hipStreamIsCapturing(L.s, &cap));
         const unsigned ev_flags = cap == hipStreamCaptureStatusActive ? hipEventRecordExternal : 0u;
         if (w->ev_start) HIP_TRY(hipEventRecordWithFlags(w->ev_start, L.s, ev_flags));
+        w->main_grid = grid;
+        w->main_block = wave_kernel ? 64 * waves : kWG;
+        w->main_lds = a.lds_total;
         if (wave_kernel)
             HIP_TRY(launch_scan_waves(a, waves, grid, L.s));
         else
@@ -941,6 +950,49 @@ static int find_timing_nodes(pfac_graph *g) {
     return PFAC_OK;
 }
 
+// Event-record nodes added around the main scan kernel of a captured graph:
+// the kernel node is the one launched with the scan's grid, block and
+// dynamic LDS (no other kernel of a scan uses dynamic LDS); the start node
+// takes over its dependencies and the stop node its dependents.
+static int add_timing_nodes(pfac_graph *g) {
+    size_t n = 0;
+    HIP_TRY(hipGraphGetNodes(g->graph, nullptr, &n));
+    std::vector<hipGraphNode_t> nodes(n);
+    if (n) HIP_TRY(hipGraphGetNodes(g->graph, nodes.data(), &n));
+    hipGraphNode_t k = nullptr;
+    for (hipGraphNode_t nd : nodes) {
+        hipGraphNodeType ty;
+        HIP_TRY(hipGraphNodeGetType(nd, &ty));
+        if (ty != hipGraphNodeTypeKernel) continue;
+        hipKernelNodeParams kp{};
+        HIP_TRY(hipGraphKernelNodeGetParams(nd, &kp));
+        if (kp.sharedMemBytes == 0 || kp.sharedMemBytes != g->ws->main_lds ||
+            kp.blockDim.x != g->ws->main_block || kp.gridDim.x != g->ws->main_grid)
+            continue;
+        if (k) return PFAC_EINVAL;  // not unique
+        k = nd;
+    }
+    if (!k) return PFAC_OK;  // an empty batch launches no scan kernel
+    size_t ni = 0, no = 0;
+    HIP_TRY(hipGraphNodeGetDependencies(k, nullptr, &ni));
+    HIP_TRY(hipGraphNodeGetDependentNodes(k, nullptr, &no));
+    std::vector<hipGraphNode_t> in(ni), after(no);
+    if (ni) HIP_TRY(hipGraphNodeGetDependencies(k, in.data(), &ni));
+    if (no) HIP_TRY(hipGraphNodeGetDependentNodes(k, after.data(), &no));
+    hipGraphNode_t ns = nullptr, ne = nullptr;
+    HIP_TRY(hipGraphAddEventRecordNode(&ns, g->graph, ni ? in.data() : nullptr, ni, g->ev_own[0]));
+    for (size_t i = 0; i < ni; i++) HIP_TRY(hipGraphRemoveDependencies(g->graph, &in[i], &k, 1));
+    HIP_TRY(hipGraphAddDependencies(g->graph, &ns, &k, 1));
+    HIP_TRY(hipGraphAddEventRecordNode(&ne, g->graph, &k, 1, g->ev_own[1]));
+    for (size_t i = 0; i < no; i++) {
+        HIP_TRY(hipGraphRemoveDependencies(g->graph, &k, &after[i], 1));
+        HIP_TRY(hipGraphAddDependencies(g->graph, &ne, &after[i], 1));
+    }
+    g->n_start = ns;
+    g->n_stop = ne;
+    return PFAC_OK;
+}
+
 extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
                                        const uint8_t *texts_dev, const uint64_t *offsets_dev,
                                        uint32_t n_texts, uint64_t total_bytes,
@@ -965,23 +1017,37 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
     }
     g->t = t;
     t->pins++;
-    hipStream_t s = (hipStream_t)stream;
-    hipStream_t own = nullptr;
-    if (!s) {
-        hipError_t ec = hipStreamCreateWithFlags(&own, hipStreamNonBlocking);
-        if (ec != hipSuccess) {
-            pfac_graph_free(g);
-            return hip_fail(ec);
-        }
-        s = own;
+    (void)stream;  // the capture runs on a stream of the library's own
+    hipStream_t s = nullptr;
+    hipError_t ec = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (ec != hipSuccess) {
+        pfac_graph_free(g);
+        return hip_fail_at(ec, "hipStreamCreateWithFlags", __LINE__);
     }
-    // the caller's timing events, if set, are captured around the main
-    // kernel; if the runtime refuses them the graph is captured again
-    // without them (pfac_graph_set_timing then returns PFAC_EINVAL)
-    for (int with_events = (w && w->ev_start) ? 1 : 0; with_events >= 0; with_events--) {
-        g->ws->ev_start = with_events ? w->ev_start : nullptr;
-        g->ws->ev_stop = with_events ? w->ev_stop : nullptr;
+    // With the caller's timing events set, event-record nodes around the
+    // main kernel record two events of the graph's own (plain hipEventCreate
+    // events), pointed at the caller's events once the graph is
+    // instantiated.  The nodes are added to the captured graph (method 0)
+    // or, where the runtime refuses that, captured from event records
+    // (method 1); if both fail the graph is captured without them
+    // (pfac_graph_set_timing then returns PFAC_EINVAL).
+    const bool timed = w && w->ev_start && w->ev_stop;
+    for (int method = timed ? 0 : 2; method <= 2; method++) {
+        g->ws->ev_start = g->ws->ev_stop = nullptr;
         g->n_start = g->n_stop = nullptr;
+        rc = PFAC_OK;
+        if (method < 2) {
+            for (hipEvent_t &e : g->ev_own)
+                if (!e && hipEventCreate(&e) != hipSuccess) e = nullptr;
+            if (!g->ev_own[0] || !g->ev_own[1]) {
+                (void)hipGetLastError();
+                continue;
+            }
+            if (method == 1) {
+                g->ws->ev_start = g->ev_own[0];
+                g->ws->ev_stop = g->ev_own[1];
+            }
+        }
         hipError_t e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             Launch L{t, g->ws, texts_dev, total_bytes, offsets_dev, n_texts, 0, out_dev, capacity,
@@ -991,22 +1057,29 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
             hipError_t e2 = hipStreamEndCapture(s, &graph);
             g->graph = graph;
             if (rc == PFAC_OK && e2 != hipSuccess) rc = hip_fail_at(e2, "hipStreamEndCapture", __LINE__);
-            if (rc == PFAC_OK && g->ws->ev_start) rc = find_timing_nodes(g);
+            if (rc == PFAC_OK && method == 0) rc = add_timing_nodes(g);
+            if (rc == PFAC_OK && method == 1) rc = find_timing_nodes(g);
             if (rc == PFAC_OK) {
                 e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
                 if (e != hipSuccess) rc = hip_fail_at(e, "hipGraphInstantiate", __LINE__);
             }
+            // replays record the caller's events from the start
+            if (rc == PFAC_OK && g->n_start && g->n_stop)
+                rc = pfac_graph_set_timing(g, w->ev_start, w->ev_stop);
         } else {
             rc = hip_fail_at(e, "hipStreamBeginCapture", __LINE__);
         }
-        if (rc == PFAC_OK || !with_events) break;
-        // drop the failed attempt and capture once more without events
+        g->ws->ev_start = g->ws->ev_stop = nullptr;
+        if (rc == PFAC_OK || method == 2) break;
+        // drop the failed attempt and try the next method
         if (g->exec) (void)hipGraphExecDestroy(g->exec);
         if (g->graph) (void)hipGraphDestroy(g->graph);
         g->exec = nullptr;
         g->graph = nullptr;
+        g->n_start = g->n_stop = nullptr;
         (void)hipGetLastError();
     }
+    hipStream_t own = s;
     if (own) (void)hipStreamDestroy(own);
     if (rc != PFAC_OK) {
         pfac_graph_free(g);
@@ -1035,6 +1108,8 @@ extern "C" void pfac_graph_free(pfac_graph *g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     pfac_workspace_free(g->ws);
+    for (hipEvent_t e : g->ev_own)
+        if (e) (void)hipEventDestroy(e);
     if (g->t) g->t->pins--;
     delete g;
 }

@@ -334,8 +334,9 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     const uint32_t lane = tid & 63;
 
     uint8_t *s_ftab = lds + a.off_ftab;
-    uint32_t *s_bits = (uint32_t *)(lds + a.off_bits);
-    uint32_t *s_rank = (uint32_t *)(lds + a.off_rank);
+    // level index in LDS: per 32 codes the bit map and the first node
+    // (level start + rank) of the word
+    uint2 *s_lvl = (uint2 *)(lds + a.off_bits);
     uint32_t *s_root = (uint32_t *)(lds + a.off_root);
     uint32_t *s_krec = (uint32_t *)(lds + a.off_krec);
     uint32_t *s_pfx4 = (uint32_t *)(lds + a.off_pfx4);
@@ -356,8 +357,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     }
     for (uint32_t i = tid; i < a.lvl_lds; i += nthreads) {
         const uint2 e = ((const uint2 *)im.lvl)[i];
-        s_bits[i] = e.x;
-        s_rank[i] = e.y;
+        s_lvl[i] = make_uint2(e.x, e.y + im.lvl_start);
     }
     for (uint32_t i = tid; i < a.root_words; i += nthreads) s_root[i] = im.root_bits[i];
     for (uint32_t i = tid; i < a.krec_words; i += nthreads) s_krec[i] = im.krec[i];
@@ -382,35 +382,41 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     const bool krec = a.krec_words != 0;
     const bool pfx4 = a.pfx4_words != 0;
 
-    // chunks of a unit that hold text
-    auto unit_chunks = [&](uint64_t u) -> uint32_t {
-        const uint64_t lo = u * G * kChunk;
-        const uint64_t left = hi_valid > lo ? hi_valid - lo : 0;
-        return (uint32_t)min((uint64_t)G, (left + kChunk - 1) / kChunk);
-    };
+    // Chunk c covers frame bytes [c KiB, (c + 1) KiB); chunks 0 .. n_ch - 1
+    // hold text.  Chunk and unit indices are 32-bit (the host refuses texts
+    // of 2^31 chunks or more).
+    const uint32_t n_ch = (uint32_t)a.n_plan;
+    const uint32_t n_u = (uint32_t)n_units;
+    const uint32_t ustride = (uint32_t)stride;
+    // chunks 1 .. n_ch - 2: every 16-byte block of the chunk and the block
+    // after it hold text, and neither end of the text lies inside it
+    const uint32_t n_in = n_ch >= 2 ? n_ch - 2 : 0u;
+    auto interior = [&](uint32_t c) -> bool { return c - 1u < n_in; };
+    // chunks of unit u that hold text
+    auto unit_chunks = [&](uint32_t u) -> uint32_t { return min(G, n_ch - u * G); };
 
     // The wave's chunks in order: units u0, u0 + stride, ...; chunks 0 .. n-1
     // of each.
     struct Cur {
-        uint64_t u;
-        uint32_t g, n;
+        uint32_t u, g, n;
     };
-    auto start_at = [&](uint64_t uu) -> Cur { return Cur{uu, 0u, uu < n_units ? unit_chunks(uu) : 0u}; };
+    auto start_at = [&](uint32_t uu) -> Cur { return Cur{uu, 0u, uu < n_u ? unit_chunks(uu) : 0u}; };
     auto advance = [&](Cur &c) {
         if (++c.g >= c.n) {
-            c.u += stride;
+            c.u += ustride;
             c.g = 0;
-            c.n = c.u < n_units ? unit_chunks(c.u) : 0u;
+            c.n = c.u < n_u ? unit_chunks(c.u) : 0u;
         }
     };
-    // One chunk's loads: its 1 KiB (16 bytes a lane), the 16 bytes after it
-    // (the same block in every lane) and its boundary word.  They are issued
-    // unconditionally, at addresses clamped to the 16-byte blocks that hold
-    // text (all in mapped memory), so that the wait for a chunk's data counts
-    // only the loads issued after it and the next two chunks stay in flight
-    // while it is filtered.  Bytes outside the text are never reported:
-    // every start position is checked against the text range and every walk
-    // stops at the end of its text.
+    // One chunk's loads: its 1 KiB (16 bytes a lane), the next 16 bytes of
+    // each lane (lane 63: the 16 bytes after the chunk) and its boundary
+    // word.  They are issued
+    // unconditionally (at the text's first or last block for the chunks at
+    // its two ends and past the end of the wave's work), so that the wait for
+    // a chunk's data counts only the loads issued after it, and the next
+    // chunk's loads are in flight while it is filtered.  Bytes outside the
+    // text are never reported: every start position is checked against the
+    // text range and every walk stops at the end of its text.
     struct Slot {
         uint4 v, h;
         uint2 info;
@@ -418,14 +424,18 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     const uint64_t blk_lo = lo_valid & ~15ull;
     const uint64_t blk_hi = (hi_valid - 1) & ~15ull;
     auto clampb = [&](uint64_t x) -> uint64_t { return x < blk_lo ? blk_lo : (x > blk_hi ? blk_hi : x); };
-    auto load_slot = [&](const Cur &c) -> Slot {
-        const uint64_t chunk = c.u * G + c.g;
-        const uint64_t lo = chunk * kChunk;
+    auto load_slot = [&](const Cur &cr) -> Slot {
+        const uint32_t c = cr.u * G + cr.g;
+        const uint64_t lo = (uint64_t)c * kChunk;
         Slot sl;
-        sl.v = *(const uint4 *)(a.base + clampb(lo + 16ull * lane));
-        sl.h = *(const uint4 *)(a.base + clampb(lo + kChunk));
-        const uint2 *ip = a.chunk_info ? a.chunk_info + umin64(chunk, a.n_plan - 1)
-                                       : (const uint2 *)(a.base + blk_lo);
+        uint64_t av = lo + 16ull * lane, ah = av + 16;
+        if (!interior(c)) {
+            av = clampb(av);
+            ah = clampb(ah);
+        }
+        sl.v = *(const uint4 *)(a.base + av);
+        sl.h = *(const uint4 *)(a.base + ah);
+        const uint2 *ip = a.chunk_info ? a.chunk_info + min(c, n_ch - 1) : (const uint2 *)(a.base + blk_lo);
         sl.info = *ip;
         return sl;
     };
@@ -434,15 +444,16 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     // Filter chunk cc with the data of slot sl, close its unit after its last
     // chunk, and step cc to the wave's next chunk; false when none is left.
     auto chunk = [&](const Slot &sl, Cur &cc) -> bool {
-        const uint64_t u = cc.u;
-        const uint32_t g = cc.g, nch = cc.n;
-        const uint64_t unit_lo = u * G * kChunk;
-        const uint64_t chunk_lo = unit_lo + (uint64_t)g * kChunk;
+        const uint32_t u = cc.u, g = cc.g, nch = cc.n;
+        const uint32_t c = u * G + g;
+        const uint64_t unit_lo = (uint64_t)(u * G) * kChunk;
+        const uint64_t chunk_lo = (uint64_t)c * kChunk;
+        const bool inner = interior(c);
         if (g == 0) {
             cn = 0;
             mn = 0;
         }
-        uint4 *const wcg = SPLIT ? a.cand + u * a.cand_cap : nullptr;
+        uint4 *const wcg = SPLIT ? a.cand + (uint64_t)u * a.cand_cap : nullptr;
         // queue a candidate (ballot mask mk over the wave); the split kernels
         // also pass on the 8 text bytes after the level index, B[pl+K ..
         // pl+K+8), so that short walks read no text from global memory
@@ -489,7 +500,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         };
 
         *(uint4 *)(wtext + 16 * lane) = sl.v;
-        if (lane == 0) *(uint4 *)(wtext + kChunk) = sl.h;
+        if (lane == 63) *(uint4 *)(wtext + kChunk) = sl.h;
         wave_sync();
 
         // Text boundaries of the chunk: the distance from its start to the
@@ -500,7 +511,11 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         // load into its registers)
         uint32_t bx = (uint32_t)__builtin_amdgcn_readfirstlane((int)sl.info.x);
         uint32_t by = (uint32_t)__builtin_amdgcn_readfirstlane((int)sl.info.y);
-        if (!a.chunk_info) {
+        if (!a.chunk_info && inner) {
+            // no end of the text in the chunk; the next one is its end
+            bx = n_ch - c > 128u ? 0x1ffffu : min((uint32_t)hi_valid - (uint32_t)chunk_lo, 0x1ffffu);
+            by = 0;
+        } else if (!a.chunk_info) {
             // the text's first byte and its end: ascending, at most one of
             // each in the chunk
             const bool lo_in = lo_valid >= chunk_lo && lo_valid < chunk_lo + kChunk;
@@ -517,7 +532,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         const uint32_t nrel = bx & 0x1ffffu;
         bool dirty = false;
         unsigned long long next_bnd = 0;
-        if (bcnt > 4) chunk_bounds(a, chunk_lo / kChunk, chunk_lo, wbnd, dirty, next_bnd);
+        if (bcnt > 4) chunk_bounds(a, c, chunk_lo, wbnd, dirty, next_bnd);
         // distance from chunk position pl to the end of its text, at most 0xffff
         auto lim_of = [&](uint32_t pl) -> uint32_t {
             if (bcnt > 4) return limit_after(wbnd, dirty, chunk_lo, pl, next_bnd);
@@ -534,15 +549,14 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             return min(nb - pl, 0xffffu);
         };
         // valid chunk positions (inside the batch's or the text's range)
-        const uint32_t vlo = lo_valid > chunk_lo ? (uint32_t)umin64(lo_valid - chunk_lo, kWin) : 0u;
-        const uint32_t vhi = hi_valid > chunk_lo ? (uint32_t)umin64(hi_valid - chunk_lo, kWin) : 0u;
-
-        uint32_t w[8];
-        {
-            w[0] = sl.v.x; w[1] = sl.v.y; w[2] = sl.v.z; w[3] = sl.v.w;
-            const uint4 x = *(const uint4 *)(wtext + 16 * lane + 16);
-            w[4] = x.x; w[5] = x.y; w[6] = x.z; w[7] = x.w;
+        uint32_t vlo = 0, vhi = kWin;
+        if (!inner) {
+            vlo = lo_valid > chunk_lo ? (uint32_t)umin64(lo_valid - chunk_lo, kWin) : 0u;
+            vhi = hi_valid > chunk_lo ? (uint32_t)umin64(hi_valid - chunk_lo, kWin) : 0u;
         }
+
+        // the lane's 16 bytes and the 16 after them
+        const uint32_t w[8] = {sl.v.x, sl.v.y, sl.v.z, sl.v.w, sl.h.x, sl.h.y, sl.h.z, sl.h.w};
 
         // ---- stage 2: the exact byte after the level index, the end of
         // the text, and the depth-K node; survivors become candidates.
@@ -562,11 +576,10 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                     pass2 = p >= lo_valid && p < hi_valid && lim > K;
                     if (pass2 && K) {
                         const uint32_t code = pc.y;
-                        const uint32_t bits = s_bits[code >> 5];
-                        const uint32_t below = bits & ((1u << (code & 31)) - 1u);
-                        const uint32_t rank = s_rank[code >> 5] + (uint32_t)__builtin_popcount(below);
-                        v = im.lvl_start + rank;
+                        const uint2 lv = s_lvl[code >> 5];
+                        v = lv.y + (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(lv.x, 0, code & 31));
                         if (krec) {
+                            const uint32_t rank = v - im.lvl_start;
                             // up to three child labels, or 0xff.. for more
                             const uint32_t rec = s_krec[rank];
                             const uint32_t ncc = rec >> 24;
@@ -629,6 +642,11 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                 wave_sync();
                 // ---- stage 2 (K = 2): the text's end, the exact third
                 // byte against the depth-2 node's child labels, the node
+                // the filters read 4 bytes (prefix-4 filter: every pattern
+                // is that long) or 3 (child labels); in a chunk without
+                // boundaries the positions [vlo, top) have them in the text
+                const uint32_t need = pfx4 ? 4u : 3u;
+                const uint32_t top = min(vhi, nrel + 1u - need);
                 for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
                     if (!SPLIT && cn + 64 > ccap) flush();
                     const uint32_t e = r0 + lane;
@@ -639,10 +657,15 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                         const uint32_t a4 = pl & ~3u;
                         const uint32_t d0 = *(const uint32_t *)(wtext + a4);
                         const uint32_t d1 = *(const uint32_t *)(wtext + a4 + 4);
-                        const uint32_t by = __builtin_amdgcn_alignbyte(d1, d0, pl & 3u);  // B[pl..pl+3]
-                        const uint32_t lim = lim_of(pl);
-                        // with the prefix-4 filter every pattern is 4 bytes or longer
-                        pass2 = pl >= vlo && pl < vhi && lim > (pfx4 ? 3u : 2u);
+                        const uint32_t by = __builtin_amdgcn_alignbyte(d1, d0, pl);  // B[pl..pl+3]
+                        uint32_t lim;
+                        if (bcnt == 0) {
+                            lim = min(nrel - pl, 0xffffu);
+                            pass2 = pl - vlo < top - vlo;
+                        } else {
+                            lim = lim_of(pl);
+                            pass2 = pl >= vlo && pl < vhi && lim >= need;
+                        }
                         if (pass2 && pfx4) {
                             // both bits of the first four bytes' hash must be set
                             const uint64_t m = (uint64_t)by * im.pfx4_mul;
@@ -652,13 +675,11 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                         }
                         if (pass2) {
                             const uint32_t code = __builtin_amdgcn_perm(0u, by, 0x0c0c0001u);
-                            const uint32_t bits = s_bits[code >> 5];
-                            const uint32_t rank = s_rank[code >> 5] +
-                                (uint32_t)__builtin_popcount(bits & ((1u << (code & 31)) - 1u));
-                            v = im.lvl_start + rank;
+                            const uint2 lv = s_lvl[code >> 5];
+                            v = lv.y + (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(lv.x, 0, code & 31));
                             if (krec) {
                                 // up to three child labels, or a count above 3
-                                const uint32_t rec = s_krec[rank];
+                                const uint32_t rec = s_krec[v - im.lvl_start];
                                 const uint32_t ncc = rec >> 24;
                                 if (ncc <= 3) {
                                     const uint32_t c = (by >> 16) & 0xffu;
@@ -823,7 +844,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                                               : (((const uint16_t *)s_ftab)[code] >> bit) & 1u;
                         } else {
                             code = full;
-                            hit = (s_bits[code >> 5] >> (code & 31)) & 1u;
+                            hit = (s_lvl[code >> 5].x >> (code & 31)) & 1u;
                         }
                     }
                     const unsigned long long mk = __ballot(hit != 0);
@@ -853,13 +874,13 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             }
         }
         advance(cc);
-        return cc.u < n_units;
+        return cc.u < n_u;
     };
 
     // The next chunk's loads are issued as soon as the current chunk's data
     // has arrived, so they are in flight while it is filtered.
-    Cur cc = start_at((uint64_t)blockIdx.x * waves + wave);
-    if (cc.u < n_units) {
+    Cur cc = start_at(blockIdx.x * waves + wave);
+    if (cc.u < n_u) {
         Cur pc = cc;
         Slot sl = load_slot(pc);
         advance(pc);
@@ -1018,8 +1039,9 @@ void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit, bool split
     a.ftab_bytes = (a.ftab_bytes + 15u) & ~15u;
     a.off_ftab = take(a.ftab_bytes);
     a.lvl_lds = a.q16_words ? 0u : a.im.lvl_words;
-    a.off_bits = take(4 * a.lvl_lds);
-    a.off_rank = take(4 * a.lvl_lds);
+    // level index: (bit map, first node) per 32 codes
+    a.off_bits = take(8 * a.lvl_lds);
+    a.off_rank = a.off_bits;
     a.root_words = a.im.K == 0 ? std::max(1u, (1u << a.im.b) / 32) : 0u;
     a.off_root = take(4 * a.root_words);
     a.off_krec = take(4 * a.krec_words);
