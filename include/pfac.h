@@ -258,6 +258,26 @@ int pfac_scan(const pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev, ui
               pfac_match *out_dev, uint64_t capacity, uint64_t *n_matches_dev,
               uint32_t *counts_dev, void *stream);
 
+/*
+ * pfac_scan for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid the allocator.
+ * Same arguments, results and errors as pfac_scan without the workspace:
+ * its scratch (per-unit counts and offsets, walk candidates, match staging)
+ * lives in one 64 MiB array that the library holds in each device's memory
+ * from its load until the process ends, so no call allocates or frees
+ * anything.  The scratch a scan needs grows with n and capacity: about
+ * 700 bytes per KiB of text plus 16 bytes per unit of capacity (a 32 MiB
+ * text with capacity 2^20 fits); a call whose needs exceed 64 MiB returns
+ * PFAC_EINVAL before touching the device.  Every call on a device uses the
+ * same array: calls that may overlap on one device (different streams or
+ * threads) race and must be ordered by the caller; a call on one stream
+ * after another is safe.  The array keeps the previous call's contents;
+ * the scan clears what it needs cleared.
+ */
+int pfac_scan_noalloc(const pfac_trie *t, const uint8_t *text_dev, uint64_t n,
+                      pfac_match *out_dev, uint64_t capacity, uint64_t *n_matches_dev,
+                      uint32_t *counts_dev, void *stream);
+
 /* pfac_scan, then wait for `stream` and return the count in *n_matches_host;
  * returns PFAC_ETRUNC when it exceeds capacity. */
 int pfac_scan_sync(const pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev, uint64_t n,

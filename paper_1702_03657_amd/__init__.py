@@ -30,6 +30,7 @@ from ._pfac import (  # noqa: F401
     pfac_scan,
     pfac_scan_batch,
     pfac_scan_batch_plain,
+    pfac_scan_noalloc,
     pfac_scan_sync,
     scan_host,
     strerror,

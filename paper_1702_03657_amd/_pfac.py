@@ -99,6 +99,7 @@ SIGNATURES = [
     ("pfac_workspace_set_timing", ctypes.c_int, [_vp, _vp, _vp]),
     ("pfac_scan", ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u64, _vp, _vp, _vp]),
     ("pfac_scan_sync", ctypes.c_int, [_vp, _vp, _vp, _u64, _vp, _u64, _p(_u64), _vp, _vp]),
+    ("pfac_scan_noalloc", ctypes.c_int, [_vp, _vp, _u64, _vp, _u64, _vp, _vp, _vp]),
     ("pfac_scan_batch", ctypes.c_int, [_vp, _vp, _vp, _vp, _u32, _u64, _vp, _u64, _vp, _vp]),
     ("pfac_scan_batch_plain", ctypes.c_int, [_vp, _vp, _vp, _p(_u64), _u32, _vp, _u64, _vp, _vp]),
     ("pfac_graph_create_batch", ctypes.c_int,
@@ -290,6 +291,13 @@ def pfac_scan(trie: Trie, ws: Workspace, text_dev, n: int, out_dev, capacity: in
     return check("pfac_scan", load().pfac_scan(
         trie.handle, ws.handle, _dptr(text_dev), n, _dptr(out_dev), capacity,
         _dptr(n_matches_dev), _dptr(counts_dev), _stream_ptr(stream)))
+
+
+def pfac_scan_noalloc(trie: Trie, text_dev, n: int, out_dev, capacity: int, n_matches_dev,
+                      counts_dev=None, stream=None) -> int:
+    return check("pfac_scan_noalloc", load().pfac_scan_noalloc(
+        trie.handle, _dptr(text_dev), n, _dptr(out_dev), capacity, _dptr(n_matches_dev),
+        _dptr(counts_dev), _stream_ptr(stream)))
 
 
 def pfac_scan_sync(trie: Trie, ws: Workspace, text_dev, n: int, out_dev, capacity: int,

@@ -859,6 +859,76 @@ extern "C" int pfac_scan(const pfac_trie *t, pfac_workspace *w, const uint8_t *t
     return enqueue_scan(L, true);
 }
 
+// ------------------------------------------------- scan without allocation
+
+// Scratch of pfac_scan_noalloc: one array in every device's memory, taken
+// from the code object when the library is loaded on that device and held
+// until the process ends.  Host code reaches it only through the device
+// address that hipGetSymbolAddress returns on each device; the array's
+// name itself is a host-side stand-in.
+constexpr uint64_t kNoAllocScratch = 64ull << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratch];
+constexpr int kMaxDevices = 256;
+static std::mutex g_scratch_mu;
+static uint8_t *g_scratch_dev[kMaxDevices] = {};
+
+// The scratch's device address on the current device, looked up once per
+// device with that device current.
+static int noalloc_scratch(uint8_t **out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return PFAC_EINVAL;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_dev[dev] = (uint8_t *)p;
+    }
+    *out = g_scratch_dev[dev];
+    return PFAC_OK;
+}
+
+extern "C" int pfac_scan_noalloc(const pfac_trie *t, const uint8_t *text_dev, uint64_t n,
+                                 pfac_match *out_dev, uint64_t capacity, uint64_t *n_matches_dev,
+                                 uint32_t *counts_dev, void *stream) {
+    if (!t || !n_matches_dev) return PFAC_EINVAL;
+    if (t->host_only) return PFAC_ENODEV;
+    if (n > 0 && !text_dev) return PFAC_EINVAL;
+    if (capacity > 0 && !out_dev) return PFAC_EINVAL;
+    // the workspace pfac_scan would reserve, carved out of the scratch
+    const ScanShape h = scan_shape(t, text_dev, n);
+    if (h.ws_units() > (1ull << 40) || capacity > (1ull << 40)) return PFAC_EINVAL;
+    const WsSizes z = ws_sizes(h.ws_units(), capacity, h.split);
+    uint8_t *base = nullptr;
+    int rc = noalloc_scratch(&base);
+    if (rc != PFAC_OK) return rc;
+    pfac_workspace w{};
+    uint64_t off = 0;
+    auto take = [&](DeviceBuf &b, uint64_t bytes) {
+        b.p = base + off;
+        b.bytes = bytes;
+        off += (bytes + 255) & ~255ull;
+    };
+    take(w.misc, 256);
+    take(w.unit_count, z.unit_count);
+    take(w.unit_off, z.unit_off);
+    take(w.tile_first, z.tile_first);
+    take(w.chunk_info, z.chunk_info);
+    take(w.blocksum, z.blocksum);
+    take(w.stage, z.stage);
+    take(w.inline_stage, z.inline_stage);
+    if (h.split) {
+        take(w.cand, z.cand);
+        take(w.cand_count, z.cand_count);
+    }
+    if (off > kNoAllocScratch) return PFAC_EINVAL;  // text or capacity beyond the scratch
+    Launch L{t, &w, text_dev, n, nullptr, 1, 0, out_dev, capacity, n_matches_dev, counts_dev,
+             nullptr, (hipStream_t)stream};
+    // every buffer is in place: the scan allocates nothing (the DeviceBufs
+    // are not owned and are dropped without release)
+    return enqueue_scan(L, false);
+}
+
 extern "C" int pfac_scan_sync(const pfac_trie *t, pfac_workspace *w, const uint8_t *text_dev,
                               uint64_t n, pfac_match *out_dev, uint64_t capacity,
                               uint64_t *n_matches_host, uint32_t *counts_dev, void *stream) {
