@@ -847,6 +847,8 @@ def measure_single(pf, torch, name, args, dev_name, threads, steps, headline=Fal
     if args.tuning and headline:
         trie.set_tuning(**parse_tuning(args.tuning))
         tuning, tuned_now = trie.tuning(), False
+    elif args.default_tuning and headline:
+        tuning, tuned_now = trie.tuning(), False
     else:
         tuning, tuned_now = choose_tuning(pf, trie, ws, text, n, name, dev_name, args.retune)
     st = trie.stats()
@@ -930,6 +932,8 @@ def measure_batch(pf, torch, args, dev_name, threads):
 
     if args.tuning:
         trie.set_tuning(**parse_tuning(args.tuning))
+        tuning, tuned_now = trie.tuning(), False
+    elif args.default_tuning:
         tuning, tuned_now = trie.tuning(), False
     else:
         tuning, tuned_now = choose_tuning(pf, trie, ws, text, total, "c4", dev_name, args.retune,
@@ -1051,6 +1055,8 @@ def main():
     ap.add_argument("--tuning", default=None,
                     help="kernel,bytes_per_lane,index_bits,fold_bits,wg_per_cu,waves_per_wg,"
                          "chunks_per_unit,child_check[,top_nodes[,trunc_depth[,dag]]]")
+    ap.add_argument("--default-tuning", action="store_true",
+                    help="the trie's default launch (no autotuning) for the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true",

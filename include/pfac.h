@@ -118,16 +118,22 @@ typedef struct {
     uint32_t kernel;           /* 0 = tile kernel (workgroup tiles), 1 = fused wave kernel
                                   (filter, walks and emission in one kernel), 2 = split wave
                                   kernels (filter kernel writes walk candidates, a walk kernel
-                                  runs them; the default for byte alphabets with K = 2 and for
-                                  alphabets of at most four bytes, where it uses the 16-symbol
-                                  filter when every pattern has 16 bytes or more) */
+                                  runs them; for alphabets of at most four bytes it uses the
+                                  16-symbol filter when every pattern has 16 bytes or more),
+                                  3 = by launch size: 2 for launches (a text, or a whole
+                                  batch) of 8 MiB or more, else 0 with 4 bytes per lane
+                                  below 1 MiB and 8 from there (the default for byte
+                                  alphabets with K = 2 and for alphabets of at most four
+                                  bytes).  Statistics report the kernel of large launches */
     uint32_t bytes_per_lane;   /* tile kernel: start positions per lane per tile: 4, 8 or 16 */
     uint32_t index_bits;       /* level-index width in bits (1..18); depth K = bits / symbol_bits */
     uint32_t fold_bits;        /* wave kernel prefix filter: 0 (level bitmap), 8 or 16 bits per node */
     uint32_t wg_per_cu;        /* resident workgroups per compute unit (0 = occupancy max) */
     uint32_t waves_per_wg;     /* wave kernel: 4, 8, 12 or 16 waves per workgroup (fewer when
                                   the LDS tables leave no room) */
-    uint32_t chunks_per_unit;  /* wave kernel: 1 KiB chunks per output unit, 1..64 */
+    uint32_t chunks_per_unit;  /* wave kernel: 1 KiB chunks per output unit, 1..64; a launch
+                                  of fewer chunks than 2 units per resident wave of the grid
+                                  uses fewer (a batch of small texts fills the GPU) */
     uint32_t child_check;      /* wave kernel second stage: 0 = none, 1 = check the byte after
                                   the level index against the depth-K node's child labels in
                                   LDS when they fit, 2 = the prefix-4 filter (two hashed bits

@@ -315,9 +315,9 @@ static int build_common(const uint8_t *data, const uint64_t *offsets, uint32_t k
     // default launch: the split filter + walk kernels where the byte-symbol
     // two-level filter applies (few walk candidates); the fused wave kernel
     // otherwise (small alphabets and short patterns leave many candidates)
-    if (t->img.identity && t->img.K == 2) t->tuning.kernel = 2;
+    if (t->img.identity && t->img.K == 2) t->tuning.kernel = 3;
     if (t->img.pfx4_log2) t->tuning.child_check = 2;
-    if (t->img.q16_lw) t->tuning.kernel = 2;  // four-symbol alphabets: the 16-symbol filter
+    if (t->img.q16_lw) t->tuning.kernel = 3;  // four-symbol alphabets: the 16-symbol filter
     t->build_s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     set_halo(t);
     t->host_only = (flags & PFAC_BUILD_HOST_ONLY) != 0;
@@ -376,7 +376,40 @@ extern "C" int pfac_build(const uint8_t *const *patterns, const uint64_t *length
 // fewer waves per workgroup, then dropping the LDS child records, until its
 // tables and per-wave areas fit; the tile kernel otherwise.  *wave_out says
 // which one it is.
-static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr, bool *wave_out = nullptr) {
+// Kernel 3 (auto) picks by launch size.  On MI355X, one-text scans of 64 KiB
+// to 64 MiB with 100, 10,000 and 20,000 patterns put the split wave kernels
+// ahead of the tile kernel from 8 MiB on (their three launches and the
+// persistent grid do not pay off below); under that the one-launch tile
+// kernel is fastest with 4 bytes per lane below 1 MiB and 8 from there.
+constexpr uint64_t kAutoSplitBytes = 8ull << 20;
+constexpr uint64_t kAutoWideLanes = 1ull << 20;
+
+// The tuning a launch over `total` bytes runs with: kernel 3 resolved, and
+// for the wave kernels at most as many chunks per unit as give every
+// resident wave two units (output units are independent; a launch of few
+// chunks, such as a batch of small texts, needs small units to fill the
+// grid).
+static pfac_tuning launch_tuning(const pfac_trie *t, uint64_t total) {
+    pfac_tuning tn = t->tuning;
+    if (tn.kernel == 3) {
+        if (total >= kAutoSplitBytes) {
+            tn.kernel = 2;
+        } else {
+            tn.kernel = 0;
+            tn.bytes_per_lane = total < kAutoWideLanes ? 4 : 8;
+        }
+    }
+    if (tn.kernel == 1 || tn.kernel == 2) {
+        const uint64_t chunks = total / kWaveChunk + 1;
+        const uint64_t slots = 2ull * (uint64_t)std::max(t->n_cu, 1) * tn.waves_per_wg;
+        const uint64_t g = std::max<uint64_t>(1, chunks / slots);
+        if (g < tn.chunks_per_unit) tn.chunks_per_unit = (uint32_t)g;
+    }
+    return tn;
+}
+
+static ScanArgs layout_for(const pfac_trie *t, const pfac_tuning &tn, uint32_t *waves_out = nullptr,
+                           bool *wave_out = nullptr) {
     auto common = [&]() {
         ScanArgs a{};
         a.im = t->view;
@@ -390,23 +423,23 @@ static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr, bo
     };
     // tails and the merged DAG are walked by the tile kernel only, and the
     // wave kernels' walk limits are 16-bit
-    const bool wave_ok = (t->tuning.kernel == 1 || t->tuning.kernel == 2) && !t->img.trunc_depth &&
+    const bool wave_ok = (tn.kernel == 1 || tn.kernel == 2) && !t->img.trunc_depth &&
                          !t->img.dag && t->crs.max_len <= 0xffff;
     if (wave_ok) {
         ScanArgs a = common();
         a.fold = t->img.fold_bits;
-        a.group = t->tuning.chunks_per_unit;
+        a.group = tn.chunks_per_unit;
         // child_check 2: the prefix-4 filter where the image has one, else
         // the child records; dropped last when the layout does not fit
-        const bool pfx4 = t->tuning.child_check == 2 && t->img.pfx4_log2 != 0;
+        const bool pfx4 = tn.child_check == 2 && t->img.pfx4_log2 != 0;
         // the split kernel filters four-symbol alphabets with the 16-symbol
         // filter when the image has one
-        a.q16_words = (t->tuning.kernel == 2 && t->img.q16_lw) ? (1u << t->img.q16_lw) : 0u;
-        for (int with_rec = (t->tuning.child_check && t->img.K) ? 1 : 0; with_rec >= 0; with_rec--) {
+        a.q16_words = (tn.kernel == 2 && t->img.q16_lw) ? (1u << t->img.q16_lw) : 0u;
+        for (int with_rec = (tn.child_check && t->img.K) ? 1 : 0; with_rec >= 0; with_rec--) {
             a.krec_words = with_rec && !pfx4 ? (uint32_t)t->img.krec.size() : 0u;
             a.pfx4_words = with_rec && pfx4 ? (uint32_t)t->img.pfx4.size() : 0u;
-            for (uint32_t waves = t->tuning.waves_per_wg; waves >= 4; waves -= 4) {
-                wave_lds_layout(a, waves, t->lds_limit, t->tuning.kernel == 2);
+            for (uint32_t waves = tn.waves_per_wg; waves >= 4; waves -= 4) {
+                wave_lds_layout(a, waves, t->lds_limit, tn.kernel == 2);
                 if (a.lds_total <= t->lds_limit) {
                     if (waves_out) *waves_out = waves;
                     if (wave_out) *wave_out = true;
@@ -416,14 +449,19 @@ static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr, bo
         }
     }
     ScanArgs a = common();
-    a.top_words = t->tuning.top_nodes && t->img.K ? (uint32_t)t->img.top.size() : 0u;
-    lds_layout(a, t->tuning.bytes_per_lane);
-    if (waves_out) *waves_out = std::max(4u, t->tuning.waves_per_wg);
+    a.top_words = tn.top_nodes && t->img.K ? (uint32_t)t->img.top.size() : 0u;
+    lds_layout(a, tn.bytes_per_lane);
+    if (waves_out) *waves_out = std::max(4u, tn.waves_per_wg);
     if (wave_out) *wave_out = false;
     return a;
 }
 
-static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out);
+// the layout of large launches (statistics, checks)
+static ScanArgs layout_for(const pfac_trie *t, uint32_t *waves_out = nullptr, bool *wave_out = nullptr) {
+    return layout_for(t, launch_tuning(t, ~0ull), waves_out, wave_out);
+}
+
+static bool use_wave_kernel(const pfac_trie *t, const pfac_tuning &tn, uint32_t *waves_out);
 
 extern "C" int pfac_trie_stats(const pfac_trie *t, pfac_stats *o) {
     if (!t || !o) return PFAC_EINVAL;
@@ -445,8 +483,10 @@ extern "C" int pfac_trie_stats(const pfac_trie *t, pfac_stats *o) {
     o->symbol_bits = t->img.b;
     o->index_depth = t->img.K;
     o->lds_bytes = layout_for(t).lds_total;
-    uint32_t waves = t->tuning.waves_per_wg;
-    o->scan_kernel = use_wave_kernel(t, &waves) ? t->tuning.kernel : 0u;
+    // (kernel 3: the kernel of large launches)
+    const pfac_tuning large = launch_tuning(t, ~0ull);
+    uint32_t waves = large.waves_per_wg;
+    o->scan_kernel = use_wave_kernel(t, large, &waves) ? large.kernel : 0u;
     o->scan_waves = o->scan_kernel ? waves : kWG / 64;
     // the wave kernels' filter stages for this tuning
     o->stage1 = 0;
@@ -510,7 +550,7 @@ extern "C" int pfac_trie_get_tuning(const pfac_trie *t, pfac_tuning *out) {
 }
 
 static bool valid_tuning(const pfac_tuning *p) {
-    return p->kernel <= 2 &&
+    return p->kernel <= 3 &&
            (p->bytes_per_lane == 4 || p->bytes_per_lane == 8 || p->bytes_per_lane == 16) &&
            p->index_bits >= 1 && p->index_bits <= 18 &&
            (p->fold_bits == 0 || p->fold_bits == 8 || p->fold_bits == 16) && p->wg_per_cu <= 8 &&
@@ -545,7 +585,8 @@ extern "C" int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tn) {
     }
     const pfac_tuning old = t->tuning;
     t->tuning = *tn;
-    if (layout_for(t).lds_total > t->lds_limit) {
+    if (layout_for(t, launch_tuning(t, 0)).lds_total > t->lds_limit ||
+        layout_for(t, launch_tuning(t, ~0ull)).lds_total > t->lds_limit) {
         // the kernel this tuning selects does not fit in LDS (e.g. bitmapped
         // top nodes or a level index too large): the previous tuning and
         // image stay
@@ -677,9 +718,8 @@ static uint64_t tiles_for(uint64_t total, uint64_t shift, uint32_t tile) {
 }
 
 
-static uint32_t unit_bytes(const pfac_trie *t) {
-    return use_wave_kernel(t, nullptr) ? kWaveChunk * t->tuning.chunks_per_unit
-                                       : kWG * t->tuning.bytes_per_lane;
+static uint32_t unit_bytes(const pfac_trie *t, const pfac_tuning &tn) {
+    return use_wave_kernel(t, tn, nullptr) ? kWaveChunk * tn.chunks_per_unit : kWG * tn.bytes_per_lane;
 }
 
 // Opt a kernel into more than 64 KiB of dynamic LDS (once per size).
@@ -698,13 +738,15 @@ static hipError_t prep_wave(int mode, uint32_t bytes) { return prepare_wave_kern
 
 // Wave kernel when asked for, applicable and its LDS layout fits; the tile
 // kernel otherwise.
-static bool use_wave_kernel(const pfac_trie *t, uint32_t *waves_out) {
+static bool use_wave_kernel(const pfac_trie *t, const pfac_tuning &tn, uint32_t *waves_out) {
     bool wave = false;
-    (void)layout_for(t, waves_out, &wave);
+    (void)layout_for(t, tn, waves_out, &wave);
     return wave;
 }
 
-static bool uses_split(const pfac_trie *t) { return t->tuning.kernel == 2 && use_wave_kernel(t, nullptr); }
+static bool uses_split(const pfac_trie *t, const pfac_tuning &tn) {
+    return tn.kernel == 2 && use_wave_kernel(t, tn, nullptr);
+}
 
 // How a scan of `total` bytes at `text` is cut with the trie's tuning:
 // output units (tiles, or units of G chunks), batch-plan units (1 KiB chunks
@@ -716,12 +758,12 @@ struct ScanShape {
     uint64_t ws_units() const { return std::max(n_tiles, n_plan); }
 };
 
-static ScanShape scan_shape(const pfac_trie *t, const void *text, uint64_t total) {
+static ScanShape scan_shape(const pfac_trie *t, const pfac_tuning &tn, const void *text, uint64_t total) {
     ScanShape h{};
-    h.waves = t->tuning.waves_per_wg;
-    h.wave_kernel = use_wave_kernel(t, &h.waves);
-    h.split = h.wave_kernel && t->tuning.kernel == 2;
-    h.tile = h.wave_kernel ? kWaveChunk * t->tuning.chunks_per_unit : kWG * t->tuning.bytes_per_lane;
+    h.waves = tn.waves_per_wg;
+    h.wave_kernel = use_wave_kernel(t, tn, &h.waves);
+    h.split = h.wave_kernel && tn.kernel == 2;
+    h.tile = h.wave_kernel ? kWaveChunk * tn.chunks_per_unit : kWG * tn.bytes_per_lane;
     h.shift = (uintptr_t)text & 15;
     h.n_tiles = tiles_for(total, h.shift, h.tile);
     if (t->crs.k == 0) h.n_tiles = 0;  // nothing can match
@@ -732,11 +774,12 @@ static ScanShape scan_shape(const pfac_trie *t, const void *text, uint64_t total
 
 static int enqueue_scan(const Launch &L, bool reserve) {
     const pfac_trie *t = L.t;
-    const ScanShape h = scan_shape(t, L.text, L.total);
+    const pfac_tuning tn = launch_tuning(t, L.total);
+    const ScanShape h = scan_shape(t, tn, L.text, L.total);
     uint32_t waves = h.waves;
     const bool wave_kernel = h.wave_kernel;
     const bool split = h.split;
-    const uint32_t bpl = t->tuning.bytes_per_lane;
+    const uint32_t bpl = tn.bytes_per_lane;
     const uintptr_t addr = (uintptr_t)L.text;
     const uint64_t shift = h.shift;
     const uint64_t n_tiles = h.n_tiles;
@@ -750,7 +793,7 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     pfac_workspace *w = L.w;
     const uint32_t n_sums = (uint32_t)std::max<uint64_t>(1, (n_tiles + (1u << kSumShift) - 1) >> kSumShift);
 
-    ScanArgs a = layout_for(t, &waves);
+    ScanArgs a = layout_for(t, tn, &waves);
     a.im = t->view;
     a.base = (const uint8_t *)(addr - shift);
     a.shift = shift;
@@ -771,7 +814,7 @@ static int enqueue_scan(const Launch &L, bool reserve) {
     a.blocksum = (unsigned long long *)w->blocksum.p;
     a.counts = L.counts;
     a.inline_stage = (pfac_match *)w->inline_stage.p;
-    a.inline_cap = wave_kernel ? std::max(kInlineCap, kInlinePerChunk * t->tuning.chunks_per_unit) : 0;
+    a.inline_cap = wave_kernel ? std::max(kInlineCap, kInlinePerChunk * tn.chunks_per_unit) : 0;
     if (split) {
         a.cand = (uint4 *)w->cand.p;
         a.cand_count = (uint32_t *)w->cand_count.p;
@@ -789,7 +832,7 @@ static int enqueue_scan(const Launch &L, bool reserve) {
         if (L.offsets)
             HIP_TRY(launch_plan(L.offsets, L.n_texts, shift, n_plan, plan_unit,
                                 (uint32_t *)w->tile_first.p, (uint2 *)a.chunk_info, L.s));
-        int per_cu = (int)t->tuning.wg_per_cu;
+        int per_cu = (int)tn.wg_per_cu;
         int occ;
         uint64_t want;
         if (wave_kernel) {
@@ -896,7 +939,7 @@ extern "C" int pfac_scan_noalloc(const pfac_trie *t, const uint8_t *text_dev, ui
     if (n > 0 && !text_dev) return PFAC_EINVAL;
     if (capacity > 0 && !out_dev) return PFAC_EINVAL;
     // the workspace pfac_scan would reserve, carved out of the scratch
-    const ScanShape h = scan_shape(t, text_dev, n);
+    const ScanShape h = scan_shape(t, launch_tuning(t, n), text_dev, n);
     if (h.ws_units() > (1ull << 40) || capacity > (1ull << 40)) return PFAC_EINVAL;
     const WsSizes z = ws_sizes(h.ws_units(), capacity, h.split);
     uint8_t *base = nullptr;
@@ -963,12 +1006,15 @@ extern "C" int pfac_scan_batch_plain(const pfac_trie *t, pfac_workspace *w,
     if (!offsets_host) return PFAC_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     uint64_t max_tiles = 0;
+    bool split = false;
     for (uint32_t i = 0; i < n_texts; i++) {
         if (offsets_host[i + 1] < offsets_host[i]) return PFAC_EINVAL;
-        max_tiles = std::max(max_tiles, tiles_for(offsets_host[i + 1] - offsets_host[i], 15,
-                                                  std::min(unit_bytes(t), kWaveChunk)));
+        const uint64_t n = offsets_host[i + 1] - offsets_host[i];
+        const pfac_tuning tn = launch_tuning(t, n);
+        max_tiles = std::max(max_tiles, tiles_for(n, 15, std::min(unit_bytes(t, tn), kWaveChunk)));
+        split = split || uses_split(t, tn);
     }
-    rc = ws_reserve(w, max_tiles, capacity, uses_split(t));
+    rc = ws_reserve(w, max_tiles, capacity, split);
     if (rc) return rc;
     HIP_TRY(launch_fill_u32((uint32_t *)w->running(), 2, 0, s));
     for (uint32_t i = 0; i < n_texts; i++) {
@@ -1079,8 +1125,12 @@ extern "C" int pfac_graph_create_batch(const pfac_trie *t, pfac_workspace *w,
         rc = check_scan_args(t, g->ws, texts_dev, total_bytes, out_dev, capacity, n_matches_dev);
     if (rc == PFAC_OK && !offsets_dev) rc = PFAC_EINVAL;
     if (rc == PFAC_OK)
-        rc = ws_reserve(g->ws, tiles_for(total_bytes, 15, std::min(unit_bytes(t), kWaveChunk)), capacity,
-                        uses_split(t));
+    {
+        const pfac_tuning tn = launch_tuning(t, total_bytes);
+        if (rc == PFAC_OK)
+            rc = ws_reserve(g->ws, tiles_for(total_bytes, 15, std::min(unit_bytes(t, tn), kWaveChunk)),
+                            capacity, uses_split(t, tn));
+    }
     if (rc != PFAC_OK) {
         pfac_graph_free(g);
         return rc;

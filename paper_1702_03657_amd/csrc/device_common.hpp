@@ -282,15 +282,27 @@ __device__ __forceinline__ uint2 hit_list(const ImageView &im, uint2 h) {
     return h;
 }
 
+// The text of a whole output unit of a batch, when one text holds it: its
+// index and frame start.
+struct UnitText {
+    bool known = false;
+    uint32_t tid = 0;
+    uint64_t start = 0;
+};
+
 // Write the matches of one start position (frame position `frame_pos`, the
 // pattern list `ids` = (offset, count)) to dst[idx ..], dropping records at
 // or beyond `cap`; also its per-position count when requested.
 __device__ __forceinline__ void emit(const ScanArgs &a, uint64_t frame_pos, uint2 ids,
-                                     pfac_match *dst, uint64_t idx, uint64_t cap) {
+                                     pfac_match *dst, uint64_t idx, uint64_t cap,
+                                     const UnitText &ut = UnitText{}) {
     const ImageView &im = a.im;
     uint32_t tid = 0;
     uint64_t start = a.shift;
-    if (a.offsets) {
+    if (a.offsets && ut.known) {
+        tid = ut.tid;
+        start = ut.start;
+    } else if (a.offsets) {
         // the batch plan bounds the search: the texts holding the first
         // bytes of this plan unit and of the next one
         const uint64_t c = frame_pos >> a.plan_shift;

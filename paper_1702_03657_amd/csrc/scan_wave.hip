@@ -218,7 +218,8 @@ __device__ __forceinline__ uint32_t limit_after(const uint32_t *bnd, bool dirty,
 // stored list length << 16, list offset).  At most inline_cap records go to
 // the unit's inline slots; more reserve staging space with one atomic.
 __device__ __forceinline__ void emit_unit(const ScanArgs &a, uint64_t u, uint64_t unit_lo,
-                                          const uint2 *wm, uint32_t mn, uint2 *sorted) {
+                                          const uint2 *wm, uint32_t mn, uint2 *sorted,
+                                          const UnitText &ut = UnitText{}) {
     const ImageView &im = a.im;
     const uint32_t lane = lane_id();
     if (mn == 0) {
@@ -268,7 +269,7 @@ __device__ __forceinline__ void emit_unit(const ScanArgs &a, uint64_t u, uint64_
         if (i < mn) ids = hit_list(im, make_uint2(sorted[i].y, sorted[i].x >> 16));
         uint32_t t;
         const uint32_t before = wave_excl_scan(ids.y, t);
-        if (i < mn) emit(a, unit_lo + (sorted[i].x & 0xffffu), ids, dst, base + before, cap);
+        if (i < mn) emit(a, unit_lo + (sorted[i].x & 0xffffu), ids, dst, base + before, cap, ut);
         base += t;
     }
 }
@@ -340,6 +341,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     uint32_t *s_root = (uint32_t *)(lds + a.off_root);
     uint32_t *s_krec = (uint32_t *)(lds + a.off_krec);
     uint32_t *s_pfx4 = (uint32_t *)(lds + a.off_pfx4);
+    const uint8_t *pfx4_base = lds + a.off_pfx4;
     uint8_t *s_sym = lds + a.off_sym;
 
     // the split path needs no reset kernel: the walk kernel, the first to
@@ -577,7 +579,8 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                     if (pass2 && K) {
                         const uint32_t code = pc.y;
                         const uint2 lv = s_lvl[code >> 5];
-                        v = lv.y + (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(lv.x, 0, code & 31));
+                        // (the field width is taken from the code's low five bits)
+                        v = lv.y + (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(lv.x, 0, code));
                         if (krec) {
                             const uint32_t rank = v - im.lvl_start;
                             // up to three child labels, or 0xff.. for more
@@ -671,12 +674,14 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                             const uint64_t m = (uint64_t)by * im.pfx4_mul;
                             const uint32_t sh = 32u - im.pfx4_log2;
                             const uint32_t h1 = (uint32_t)m >> sh, h2 = (uint32_t)(m >> 32) >> sh;
-                            pass2 = ((s_pfx4[h1 >> 5] >> (h1 & 31)) & (s_pfx4[h2 >> 5] >> (h2 & 31)) & 1u) != 0;
+                            const uint32_t w1 = *(const uint32_t *)(pfx4_base + ((h1 >> 5) << 2));
+                            const uint32_t w2 = *(const uint32_t *)(pfx4_base + ((h2 >> 5) << 2));
+                            pass2 = ((w1 >> (h1 & 31)) & (w2 >> (h2 & 31)) & 1u) != 0;
                         }
                         if (pass2) {
                             const uint32_t code = __builtin_amdgcn_perm(0u, by, 0x0c0c0001u);
                             const uint2 lv = s_lvl[code >> 5];
-                            v = lv.y + (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(lv.x, 0, code & 31));
+                            v = lv.y + (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(lv.x, 0, code));
                             if (krec) {
                                 // up to three child labels, or a count above 3
                                 const uint32_t rec = s_krec[v - im.lvl_start];
@@ -918,6 +923,21 @@ __global__ __launch_bounds__(64 * kWalkWaves, 8) void walk_units(const ScanArgs 
     const uint32_t nch = (uint32_t)min((uint64_t)a.group, (left + kChunk - 1) / kChunk);
     uint2 *wm = s_match[wave];
     const uint32_t cn = a.cand_count[u];
+    // a batch unit inside one text (the texts holding its first chunk and
+    // the chunk after it are the same): its matches need no search for their
+    // text; the loads overlap the walks
+    UnitText ut;
+    if (a.offsets) {
+        const uint64_t c0 = u * a.group, c1 = c0 + nch;
+        if (c1 < a.n_plan) {
+            const uint32_t t0 = a.tile_first_text[c0];
+            if (t0 == a.tile_first_text[c1]) {
+                ut.known = true;
+                ut.tid = t0;
+                ut.start = a.offsets[t0] + a.shift;
+            }
+        }
+    }
     if (cn <= a.cand_cap) {
         const uint4 *cl = a.cand + u * a.cand_cap;
         const uint32_t K = im.K;
@@ -1016,7 +1036,7 @@ __global__ __launch_bounds__(64 * kWalkWaves, 8) void walk_units(const ScanArgs 
         }
         wave_sync();
         if (mn <= kWalkMcap) {
-            emit_unit(a, u, unit_lo, wm, mn, s_sorted[wave]);
+            emit_unit(a, u, unit_lo, wm, mn, s_sorted[wave], ut);
             return;
         }
     }
