@@ -248,6 +248,8 @@ static int upload_image(pfac_trie *t) {
     v.pfx4 = (const uint32_t *)(b + o_pfx4);
     v.pfx4_log2 = I.pfx4_log2;
     v.pfx4_mul = kPfx4Mul;
+    v.pfx4_m1 = kPfx4M1;
+    v.pfx4_m2 = kPfx4M2;
     v.q16 = (const uint32_t *)(b + o_q16);
     v.qfp = (const uint4 *)(b + o_qfp);
     v.q16_lw = I.q16_lw;

@@ -43,7 +43,8 @@ struct ImageView {
     uint32_t dag;
     uint32_t K, b, identity, lvl_words;
     uint32_t lvl_start, max_len, n_nodes, fold_syms;
-    uint32_t pfx4_log2, pfx4_mul;     // prefix-4 filter: 2^pfx4_log2 bits, hash multiplier
+    uint32_t pfx4_log2, pfx4_mul;     // prefix-4 filter: 2^pfx4_log2 bits; 32-bit hash multiplier
+    uint32_t pfx4_m1, pfx4_m2;        // the prefix-4 filter's 24-bit hash multipliers
     uint32_t q16_lw, qfp_lb;          // four-symbol filter sizes (0 = none)
     uint32_t qa, qb, qalph, q16_mul;  // its symbol map, alphabet bytes and hash multiplier
     uint32_t top_nodes, top_rw;       // bitmapped top nodes: count, words per node

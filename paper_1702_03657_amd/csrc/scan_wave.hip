@@ -32,6 +32,8 @@
 // root, 64 positions at a time, in position order.
 #include <hip/hip_runtime.h>
 
+#include <utility>
+
 #include "device_common.hpp"
 
 namespace pfac {
@@ -67,6 +69,24 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x)
 }
 
 __device__ __forceinline__ uint64_t umin64(uint64_t x, uint64_t y) { return x < y ? x : y; }
+
+// (x << J) | y in one instruction (the compiler would build a tree of
+// separate shifts and three-input ORs)
+template <int J>
+__device__ __forceinline__ uint32_t lshl_or(uint32_t x, uint32_t y) {
+    uint32_t r;
+    asm("v_lshl_or_b32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "i"(J), "v"(y));
+    return r;
+}
+
+// sum of bit[j] << j over j = 0 .. sizeof...(J) (each bit[j] is 0 or 1);
+// J runs over 0 .. n - 1 for bits 1 .. n
+template <int... J>
+__device__ __forceinline__ uint32_t gather_bits(const uint32_t *bit, std::integer_sequence<int, J...>) {
+    uint32_t hm = bit[0];
+    ((hm = lshl_or<J + 1>(bit[J + 1], hm)), ...);
+    return hm;
+}
 
 __device__ __forceinline__ uint32_t mbcnt(unsigned long long m) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -425,18 +445,24 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     };
     const uint64_t blk_lo = lo_valid & ~15ull;
     const uint64_t blk_hi = (hi_valid - 1) & ~15ull;
-    auto clampb = [&](uint64_t x) -> uint64_t { return x < blk_lo ? blk_lo : (x > blk_hi ? blk_hi : x); };
+    const uint32_t lane16 = 16u * lane;
     auto load_slot = [&](const Cur &cr) -> Slot {
         const uint32_t c = cr.u * G + cr.g;
         const uint64_t lo = (uint64_t)c * kChunk;
         Slot sl;
-        uint64_t av = lo + 16ull * lane, ah = av + 16;
+        // a wave-uniform base and 32-bit lane offsets; at the ends the
+        // offsets are clamped to [blk_lo, blk_hi] - base
+        uint64_t sb = lo;
+        uint32_t ov = lane16, oh = lane16 + 16u;
         if (!interior(c)) {
-            av = clampb(av);
-            ah = clampb(ah);
+            sb = lo < blk_hi ? lo : blk_hi;
+            const uint32_t lo_off = blk_lo > sb ? (uint32_t)(blk_lo - sb) : 0u;
+            const uint32_t hi_off = (uint32_t)umin64(blk_hi - sb, 0x7fffffffull);
+            ov = min(max(ov, lo_off), hi_off);
+            oh = min(max(oh, lo_off), hi_off);
         }
-        sl.v = *(const uint4 *)(a.base + av);
-        sl.h = *(const uint4 *)(a.base + ah);
+        sl.v = *(const uint4 *)(a.base + sb + ov);
+        sl.h = *(const uint4 *)(a.base + sb + oh);
         const uint2 *ip = a.chunk_info ? a.chunk_info + min(c, n_ch - 1) : (const uint2 *)(a.base + blk_lo);
         sl.info = *ip;
         return sl;
@@ -444,8 +470,10 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
 
     uint32_t cn = 0, mn = 0;  // candidates, matches of the current unit (wave-uniform)
     // Filter chunk cc with the data of slot sl, close its unit after its last
-    // chunk, and step cc to the wave's next chunk; false when none is left.
-    auto chunk = [&](const Slot &sl, Cur &cc) -> bool {
+    // chunk, and step cc to the wave's next chunk (nothing past the wave's
+    // last chunk).
+    auto chunk = [&](const Slot &sl, Cur &cc) {
+        if (cc.u >= n_u) return;
         const uint32_t u = cc.u, g = cc.g, nch = cc.n;
         const uint32_t c = u * G + g;
         const uint64_t unit_lo = (uint64_t)(u * G) * kChunk;
@@ -611,18 +639,19 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             uint32_t ent[16];
 #pragma unroll
             for (int j = 0; j < 16; j++) {
-                const uint32_t lo = w[j >> 2], hi = w[(j >> 2) + 1];
                 const uint32_t r = j & 3;
-                const uint32_t code = __builtin_amdgcn_perm(hi, lo, 0x0c0c0000u | (r << 8) | (r + 1));
+                const uint32_t code =
+                    __builtin_amdgcn_perm(w[(j >> 2) + 1], w[j >> 2], 0x0c0c0000u | (r << 8) | (r + 1));
                 ent[j] = MODE == 1 ? (uint32_t)lds_tab8()[code] : (uint32_t)lds_tab16()[code];
             }
-            uint32_t hm = 0;
+            uint32_t bit[16];
 #pragma unroll
             for (int j = 0; j < 16; j++) {
                 const uint32_t nx = __builtin_amdgcn_ubfe(w[(j + 2) >> 2], 8 * ((j + 2) & 3),
                                                           MODE == 1 ? 3 : 4);
-                hm |= __builtin_amdgcn_ubfe(ent[j], nx, 1) << j;
+                bit[j] = __builtin_amdgcn_ubfe(ent[j], nx, 1);
             }
+            const uint32_t hm = gather_bits(bit, std::make_integer_sequence<int, 15>{});
             // compact the hits of the wave, at most kQ16 per round
             uint16_t *wq16 = (uint16_t *)wq;
             uint32_t tot;
@@ -670,13 +699,14 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                             pass2 = pl >= vlo && pl < vhi && lim >= need;
                         }
                         if (pass2 && pfx4) {
-                            // both bits of the first four bytes' hash must be set
-                            const uint64_t m = (uint64_t)by * im.pfx4_mul;
+                            // both bits of the first four bytes' hash must be
+                            // set, in the word that h1 names
+                            const uint32_t t8 = by >> 8;
+                            const uint32_t h1 = __umul24(by, im.pfx4_m1) + t8;
+                            const uint32_t h2 = __umul24(t8, im.pfx4_m2) + by;
                             const uint32_t sh = 32u - im.pfx4_log2;
-                            const uint32_t h1 = (uint32_t)m >> sh, h2 = (uint32_t)(m >> 32) >> sh;
-                            const uint32_t w1 = *(const uint32_t *)(pfx4_base + ((h1 >> 5) << 2));
-                            const uint32_t w2 = *(const uint32_t *)(pfx4_base + ((h2 >> 5) << 2));
-                            pass2 = ((w1 >> (h1 & 31)) & (w2 >> (h2 & 31)) & 1u) != 0;
+                            const uint32_t wd = *(const uint32_t *)(pfx4_base + ((h1 >> (sh + 5u)) << 2));
+                            pass2 = ((wd >> ((h1 >> sh) & 31u)) & (wd >> (h2 >> 27)) & 1u) != 0;
                         }
                         if (pass2) {
                             const uint32_t code = __builtin_amdgcn_perm(0u, by, 0x0c0c0001u);
@@ -879,23 +909,35 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             }
         }
         advance(cc);
-        return cc.u < n_u;
     };
 
-    // The next chunk's loads are issued as soon as the current chunk's data
-    // has arrived, so they are in flight while it is filtered.
-    Cur cc = start_at(blockIdx.x * waves + wave);
-    if (cc.u < n_u) {
-        Cur pc = cc;
-        Slot sl = load_slot(pc);
+    // Three chunks in flight: the loads of the chunk two ahead are issued
+    // before a chunk is filtered.  The loop runs over whole groups of three
+    // with its one exit at the bottom (slot variables keep their registers
+    // and every wait counts only the loads issued after its own); the
+    // chunks past the wave's last are loaded at the text's last block and
+    // skipped.
+    const uint32_t u0 = blockIdx.x * waves + wave;
+    uint32_t n_wave = 0;  // chunks of this wave
+    if (u0 < n_u) {
+        const uint32_t nu = (n_u - u0 + ustride - 1) / ustride;
+        n_wave = (nu - 1) * G + unit_chunks(u0 + (nu - 1) * ustride);
+    }
+    Cur cc = start_at(u0), pc = cc;
+    Slot sa = load_slot(pc);
+    advance(pc);
+    Slot sb = load_slot(pc);
+    advance(pc);
+    for (uint32_t grp = 0; grp < (n_wave + 2) / 3; grp++) {
+        const Slot sc = load_slot(pc);
         advance(pc);
-        bool more;
-        do {
-            const Slot cur = sl;
-            sl = load_slot(pc);
-            advance(pc);
-            more = chunk(cur, cc);
-        } while (more);
+        chunk(sa, cc);
+        sa = load_slot(pc);
+        advance(pc);
+        chunk(sb, cc);
+        sb = load_slot(pc);
+        advance(pc);
+        chunk(sc, cc);
     }
 }
 

@@ -108,10 +108,12 @@ struct DeviceImageHost {
     // hold up to three labels, byte 3 the count (0xff when there are more).
     std::vector<uint32_t> krec;
     // Prefix-4 filter (byte alphabets, every pattern of 4 bytes or more): a
-    // bitmap of 2^pfx4_log2 bits in which each pattern's first four bytes
-    // x = B0 | B1 << 8 | B2 << 16 | B3 << 24 set the two bits named by the
-    // top pfx4_log2 bits of the low and of the high word of x * kPfx4Mul.  A
-    // start position with either bit clear matches no pattern.
+    // blocked Bloom filter of 2^(pfx4_log2 - 5) words.  Each pattern's first
+    // four bytes x = B0 | B1 << 8 | B2 << 16 | B3 << 24 give
+    // h1 = (x mod 2^24) * kPfx4M1 + (x >> 8) and h2 = (x >> 8) * kPfx4M2 + x
+    // (mod 2^32, two 24 x 24-bit multiplies); word h1 >> (37 - pfx4_log2)
+    // has bits (h1 >> (32 - pfx4_log2)) & 31 and h2 >> 27 set.  A start
+    // position with either bit clear matches no pattern.
     uint32_t pfx4_log2 = 0;            // 0 = no filter
     std::vector<uint32_t> pfx4;
     // Four-symbol filter (alphabets of at most four bytes whose sorted bytes
@@ -135,6 +137,8 @@ struct DeviceImageHost {
 // multipliers near 2^w / golden ratio, the hash taken from the top bits.
 constexpr uint32_t kQ16Mul = 0x9E3779u;     // 24-bit multiplier (one 24 x 24-bit multiply)
 constexpr uint32_t kPfx4Mul = 0x9E3779B1u;  // 32-bit multiplier
+constexpr uint32_t kPfx4M1 = 0x9E3779u;     // 24-bit multipliers of the prefix-4 filter
+constexpr uint32_t kPfx4M2 = 0x7F4A7Du;
 
 // Derives the device image from the CRS trie for a level index of at most
 // `index_bits` bits and a prefix filter of `fold_bits` (0, 8 or 16) bits per

@@ -344,10 +344,9 @@ static void pack_core(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
             const uint8_t *p = T.pat_data.data() + T.pat_off[T.rep[v]];
             const uint32_t x = (uint32_t)p[0] | (uint32_t)p[1] << 8 | (uint32_t)p[2] << 16 |
                                (uint32_t)p[3] << 24;
-            const uint64_t m = (uint64_t)x * kPfx4Mul;
-            const uint32_t h1 = (uint32_t)m >> (32 - lg), h2 = (uint32_t)(m >> 32) >> (32 - lg);
-            I.pfx4[h1 >> 5] |= 1u << (h1 & 31);
-            I.pfx4[h2 >> 5] |= 1u << (h2 & 31);
+            const uint32_t h1 = (x & 0xffffffu) * kPfx4M1 + (x >> 8);
+            const uint32_t h2 = (x >> 8) * kPfx4M2 + x;
+            I.pfx4[h1 >> (37 - lg)] |= (1u << ((h1 >> (32 - lg)) & 31)) | (1u << (h2 >> 27));
         }
     }
 
