@@ -70,6 +70,16 @@ __device__ __forceinline__ unsigned long long wave_min_u64(unsigned long long x)
 
 __device__ __forceinline__ uint64_t umin64(uint64_t x, uint64_t y) { return x < y ? x : y; }
 
+// The lane index, tied to a value that changes from chunk to chunk: a
+// comparison of it inside the chunk loop stays there (one compare) instead
+// of being hoisted into a lane mask that occupies two scalar registers for
+// the whole kernel.
+__device__ __forceinline__ uint32_t lane_at(uint32_t salt) {
+    uint32_t l;
+    asm("; lane %1" : "=v"(l) : "s"(salt), "0"(threadIdx.x & 63u));
+    return l;
+}
+
 // (x << J) | y in one instruction (the compiler would build a tree of
 // separate shifts and three-input ORs)
 template <int J>
@@ -186,7 +196,7 @@ __device__ __forceinline__ uint2 walk_g(const ImageView &im, const uint8_t *base
 __device__ __forceinline__ void chunk_bounds(const ScanArgs &a, uint64_t chunk, uint64_t lo,
                                              uint32_t *bnd, bool &dirty,
                                              unsigned long long &next_bnd) {
-    const uint32_t lane = lane_id();
+    const uint32_t lane = lane_at((uint32_t)chunk);
     const uint64_t lo_valid = a.shift, hi_valid = a.shift + a.total;
     const uint64_t end = lo + kWin;
     constexpr uint32_t nbw = kWin / 32 + 2;
@@ -343,7 +353,9 @@ __device__ __forceinline__ void unit_from_root(const ScanArgs &a, uint64_t u, ui
 // SPLIT: stop after stage 2 and write each unit's walk candidates to global
 // memory for walk_units (the walks then run at the occupancy of a kernel
 // without the LDS tables); otherwise walk and emit here.
-template <int MODE, bool SPLIT>
+// P4 (modes 1 and 2, split): stage 2 checks the prefix-4 filter, which the
+// launch guarantees, and has no child-record path.
+template <int MODE, bool SPLIT, bool P4 = false>
 __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     const ImageView &im = a.im;
@@ -401,8 +413,8 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     const uint64_t stride = (uint64_t)gridDim.x * waves;
     const uint32_t K = im.K;
     const uint32_t ccap = a.ccap, mcap = a.mcap;
-    const bool krec = a.krec_words != 0;
-    const bool pfx4 = a.pfx4_words != 0;
+    const bool krec = !P4 && a.krec_words != 0;
+    const bool pfx4 = P4 || a.pfx4_words != 0;
 
     // Chunk c covers frame bytes [c KiB, (c + 1) KiB); chunks 0 .. n_ch - 1
     // hold text.  Chunk and unit indices are 32-bit (the host refuses texts
@@ -530,7 +542,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         };
 
         *(uint4 *)(wtext + 16 * lane) = sl.v;
-        if (lane == 63) *(uint4 *)(wtext + kChunk) = sl.h;
+        if (lane_at(c) == 63) *(uint4 *)(wtext + kChunk) = sl.h;
         wave_sync();
 
         // Text boundaries of the chunk: the distance from its start to the
@@ -896,7 +908,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         // the unit's last chunk: hand over or emit its results
         if (g + 1 == nch) {
             if (SPLIT) {
-                if (lane == 0) a.cand_count[u] = cn;
+                if (lane_at(u) == 0) a.cand_count[u] = cn;
             } else {
                 flush();
                 wave_sync();
@@ -950,7 +962,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
 // candidates or matches overflowed is redone from the root.
 constexpr uint32_t kWalkMcap = 128;
 
-__global__ __launch_bounds__(64 * kWalkWaves, 8) void walk_units(const ScanArgs a) {
+__global__ __launch_bounds__(64 * kWalkWaves, 4) void walk_units(const ScanArgs a) {
     __shared__ __align__(16) uint2 s_match[kWalkWaves][kWalkMcap];
     __shared__ __align__(16) uint2 s_sorted[kWalkWaves][kWalkMcap];
     __shared__ uint32_t s_bnd[kWalkWaves][kWin / 32 + 2];
@@ -1123,13 +1135,15 @@ void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit, bool split
 }
 
 // 0..2: fused kernels; 3..5: the split filter kernels of modes 0..2; 6: the
-// split filter kernel of mode 3 (four-symbol alphabets)
+// split filter kernel of mode 3 (four-symbol alphabets); 7, 8: the split
+// filter kernels of modes 1 and 2 with the prefix-4 filter
 int wave_mode(const ScanArgs &a) {
     const int split = a.cand != nullptr ? 3 : 0;
     if (a.off_ftab != 0) return split;  // modes 1..3 need the table at LDS address 0
     if (split && a.q16_words) return 6;
-    if (a.im.identity && a.im.K == 2 && a.fold == 8 && a.im.fold_syms == 1) return 1 + split;
-    if (a.im.identity && a.im.K == 2 && a.fold == 16 && a.im.fold_syms == 1) return 2 + split;
+    const bool p4 = split && a.pfx4_words != 0;
+    if (a.im.identity && a.im.K == 2 && a.fold == 8 && a.im.fold_syms == 1) return p4 ? 7 : 1 + split;
+    if (a.im.identity && a.im.K == 2 && a.fold == 16 && a.im.fold_syms == 1) return p4 ? 8 : 2 + split;
     return split;
 }
 
@@ -1138,9 +1152,12 @@ static const void *wave_fn(bool split) {
     return split ? (const void *)scan_waves<MODE, true> : (const void *)scan_waves<MODE, false>;
 }
 
-// modes 3..5 are the split variants of modes 0..2, 6 of mode 3
+// modes 3..5 are the split variants of modes 0..2, 6 of mode 3, 7 and 8 of
+// modes 1 and 2 with the prefix-4 filter
 static const void *wave_fn_for(int mode) {
     if (mode == 6) return (const void *)scan_waves<3, true>;
+    if (mode == 7) return (const void *)scan_waves<1, true, true>;
+    if (mode == 8) return (const void *)scan_waves<2, true, true>;
     const bool split = mode >= 3;
     switch (mode % 3) {
         case 1: return wave_fn<1>(split);
@@ -1170,6 +1187,8 @@ hipError_t launch_scan_waves(const ScanArgs &a, uint32_t waves, uint32_t grid, h
         case 4: hipLaunchKernelGGL((scan_waves<1, true>), dim3(grid), block, a.lds_total, s, a); break;
         case 5: hipLaunchKernelGGL((scan_waves<2, true>), dim3(grid), block, a.lds_total, s, a); break;
         case 6: hipLaunchKernelGGL((scan_waves<3, true>), dim3(grid), block, a.lds_total, s, a); break;
+        case 7: hipLaunchKernelGGL((scan_waves<1, true, true>), dim3(grid), block, a.lds_total, s, a); break;
+        case 8: hipLaunchKernelGGL((scan_waves<2, true, true>), dim3(grid), block, a.lds_total, s, a); break;
         default: hipLaunchKernelGGL((scan_waves<0, false>), dim3(grid), block, a.lds_total, s, a); break;
     }
     return hipGetLastError();
