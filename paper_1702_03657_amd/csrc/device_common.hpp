@@ -12,6 +12,7 @@ constexpr uint32_t kNoneD = 0xffffffffu;
 constexpr uint32_t kTermFlagD = 1u << 16;
 constexpr uint32_t kSkipFlagD = 1u << 17;
 constexpr uint32_t kSkipShiftD = 18;
+constexpr uint32_t kLeafEndD = 1u << 15;
 constexpr uint32_t kCountShiftD = 18;
 constexpr uint32_t kCountEscD = (1u << 14) - 1;
 
@@ -174,7 +175,13 @@ __device__ __forceinline__ uint2 walk(const ImageView &im, const uint8_t *gbase,
             // they lie in the window and no text boundary falls inside them
             const uint32_t len = r.z >> kSkipShiftD;
             if (q + len <= T.win && (!T.dirty || range_clear(T.bnd, q + (d == 0), q + len))) {
-                if (!chain_equal(T.text, q, im.chain, r.x, len)) break;
+                const bool leaf = (r.z & kLeafEndD) != 0;
+                if (!chain_equal(T.text, q, im.chain, leaf ? r.x & 0xffffffu : r.x, len)) break;
+                if (leaf) {
+                    // the run ends at a leaf: its pattern list is in the record
+                    hit = make_uint2(r.w, r.x >> 24);
+                    break;
+                }
                 v = r.w;
                 d += len;
                 continue;

@@ -158,7 +158,13 @@ __device__ __forceinline__ uint2 walk_g(const ImageView &im, const uint8_t *base
             const uint32_t len = r.z >> kSkipShiftD;
             if (d + len > lim) break;
             if (p + d + len + 36 <= hi_valid) {
-                if (!chain_equal_g(base, p + d, im.chain, r.x, len)) break;
+                const bool leaf = (r.z & kLeafEndD) != 0;
+                if (!chain_equal_g(base, p + d, im.chain, leaf ? r.x & 0xffffffu : r.x, len)) break;
+                if (leaf) {
+                    // the run ends at a leaf: its pattern list is in the record
+                    hit = make_uint2(r.w, r.x >> 24);
+                    break;
+                }
                 v = r.w;
                 d += len;
                 continue;
@@ -1034,11 +1040,16 @@ __global__ __launch_bounds__(64 * kWalkWaves, 4) void walk_units(const ScanArgs 
                     if (d + len > lim) {
                         done = true;
                     } else if (p + d + len + 36 <= hi_valid) {
-                        if (chain_equal_g(a.base, p + d, im.chain, r.x, len)) {
+                        const bool leaf = (r.z & kLeafEndD) != 0;
+                        if (!chain_equal_g(a.base, p + d, im.chain, leaf ? r.x & 0xffffffu : r.x, len)) {
+                            done = true;
+                        } else if (leaf) {
+                            // the run ends at a leaf: its pattern list is in the record
+                            hit = make_uint2(r.w, r.x >> 24);
+                            done = true;
+                        } else {
                             v = r.w;
                             d += len;
-                        } else {
-                            done = true;
                         }
                     } else if (cb == im.label[r.y - 1]) {
                         v = r.y;

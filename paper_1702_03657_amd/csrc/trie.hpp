@@ -12,6 +12,7 @@ constexpr uint32_t kTermFlag = 1u << 16;   // node record .z: terminal node
 constexpr uint32_t kNcMask = 0xffffu;      // node record .z: number of children
 constexpr uint32_t kSkipFlag = 1u << 17;   // node record .z: compressed single-child run
 constexpr uint32_t kSkipShift = 18;        // node record .z: run length above this bit
+constexpr uint32_t kLeafEnd = 1u << 15;    // skip node .z: the run ends at a leaf
 constexpr uint32_t kSkipMax = (1u << 14) - 1;
 constexpr uint32_t kCountShift = 18;       // terminal record .z: pattern-list length above this bit
 constexpr uint32_t kCountEsc = (1u << 14) - 1;  // length stored before the list
@@ -48,7 +49,10 @@ struct DeviceImageHost {
     // z = nc | kTermFlag | list length << kCountShift, w = offset of the
     // node's pattern list in pout_ids (terminal nodes).  Skip nodes use
     // x = chain offset, z = 1 | kSkipFlag | run length << kSkipShift,
-    // w = node reached after the run.
+    // w = node reached after the run; when that node is a leaf whose list
+    // length is below 255 and the chain offset below 2^24, z also has
+    // kLeafEnd, x bits 24..31 hold the leaf's list length and w its list
+    // offset.
     std::vector<uint32_t> node;        // 4 * N
     std::vector<uint8_t> label;        // N - 1 (a copy of the CRS labels, padded)
     std::vector<uint8_t> chain;        // labels of single-child runs (skip nodes)

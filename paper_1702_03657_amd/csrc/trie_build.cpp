@@ -208,6 +208,24 @@ static void pack_core(const CrsTrie &T, uint32_t index_bits, uint32_t fold_bits,
     I.pout_ptr.assign(1, 0);
     if (I.pout_ids.empty()) I.pout_ids.push_back(0);
 
+    // A run that ends at a leaf: its skip nodes carry the leaf's pattern list
+    // instead of the leaf's id (x bits 24..31 its length, w its offset, z
+    // kLeafEnd), so a walk that matches the run ends without reading the
+    // leaf's record.
+    if (!D) {
+        for (uint32_t v = 0; v < N; v++) {
+            uint32_t *rec = &I.node[4ull * v];
+            if (!(rec[2] & kSkipFlag)) continue;
+            const uint32_t *end = &I.node[4ull * rec[3]];
+            const uint32_t n = end[2] >> kCountShift;
+            if ((end[2] & kNcMask) != 0 || !(end[2] & kTermFlag) || n >= 255 || rec[0] >= (1u << 24))
+                continue;
+            rec[0] |= n << 24;
+            rec[2] |= kLeafEnd;
+            rec[3] = end[3];
+        }
+    }
+
     // Truncation (Design and Implementation, step III) kept exact: only the
     // nodes of depths 0..D stay; a depth-D node with children becomes a tail
     // node whose record lists every terminal node below it (its pattern's
