@@ -27,8 +27,11 @@ JSON line:
   a time at 0.5 / 0.8 / 0.95 of the measured capacity, every request's list
   compared with the other path's and the oracle's.
 
-``--workload c1|c2|c3`` makes one text the headline instead;
-``--no-extras`` / ``--no-serving`` / ``--no-cpu-baseline`` leave parts out.
+Every scan runs with the library's default launch (kernel 3: the launch
+shape by size); ``--autotune`` autotunes instead (cached per workload and
+device), ``--tuning`` sets one.  ``--workload c1|c2|c3`` makes one text the
+headline instead; ``--no-extras`` / ``--no-serving`` / ``--no-cpu-baseline``
+leave parts out.
 
 ``--placement c1,c2,...`` prints instead one line with the trie-placement
 ablation: the tile kernel with 0, 1, 2, ... trie levels resolved in LDS by
@@ -847,10 +850,10 @@ def measure_single(pf, torch, name, args, dev_name, threads, steps, headline=Fal
     if args.tuning and headline:
         trie.set_tuning(**parse_tuning(args.tuning))
         tuning, tuned_now = trie.tuning(), False
-    elif args.default_tuning and headline:
-        tuning, tuned_now = trie.tuning(), False
-    else:
+    elif args.autotune:
         tuning, tuned_now = choose_tuning(pf, trie, ws, text, n, name, dev_name, args.retune)
+    else:
+        tuning, tuned_now = trie.tuning(), False
     st = trie.stats()
 
     stream = torch.cuda.current_stream()
@@ -933,11 +936,11 @@ def measure_batch(pf, torch, args, dev_name, threads):
     if args.tuning:
         trie.set_tuning(**parse_tuning(args.tuning))
         tuning, tuned_now = trie.tuning(), False
-    elif args.default_tuning:
-        tuning, tuned_now = trie.tuning(), False
-    else:
+    elif args.autotune:
         tuning, tuned_now = choose_tuning(pf, trie, ws, text, total, "c4", dev_name, args.retune,
                                           offsets=offs, n_texts=n_texts)
+    else:
+        tuning, tuned_now = trie.tuning(), False
     st = trie.stats()
     stream = torch.cuda.Stream()
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -1051,12 +1054,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="c4", choices=sorted(WORKLOADS) + ["c4"],
                     help="c4 (default): the batched graph launch; c1-c3: one text")
-    ap.add_argument("--retune", action="store_true", help="ignore the cached autotune choice")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the launches (cached per workload and device) instead of "
+                         "the library's default launch")
+    ap.add_argument("--retune", action="store_true", help="with --autotune: ignore the cached choice")
     ap.add_argument("--tuning", default=None,
                     help="kernel,bytes_per_lane,index_bits,fold_bits,wg_per_cu,waves_per_wg,"
                          "chunks_per_unit,child_check[,top_nodes[,trunc_depth[,dag]]]")
-    ap.add_argument("--default-tuning", action="store_true",
-                    help="the trie's default launch (no autotuning) for the headline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-extras", action="store_true",

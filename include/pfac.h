@@ -120,9 +120,10 @@ typedef struct {
                                   kernels (filter kernel writes walk candidates, a walk kernel
                                   runs them; for alphabets of at most four bytes it uses the
                                   16-symbol filter when every pattern has 16 bytes or more),
-                                  3 = by launch size: 2 for launches (a text, or a whole
-                                  batch) of 8 MiB or more, else 0 with 4 bytes per lane
-                                  below 1 MiB and 8 from there (the default for byte
+                                  3 = by launch size: 2 with 64 chunks per unit for
+                                  launches (a text, or a whole batch) of 8 MiB or more,
+                                  else 0 with 4 bytes per lane below 1 MiB and 8 from
+                                  there (the default for byte
                                   alphabets with K = 2 and for alphabets of at most four
                                   bytes).  Statistics report the kernel of large launches */
     uint32_t bytes_per_lane;   /* tile kernel: start positions per lane per tile: 4, 8 or 16 */
