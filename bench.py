@@ -751,8 +751,9 @@ def valu_issue(counts, n_cu, kernel_ms):
 
 
 def kernel_of(stats):
-    """(name, split) of the main scan kernel the trie's tuning launches."""
-    k = int(stats["scan_kernel"])
+    """(name, split) of the main scan kernel of a launch; `stats` carries
+    "launch_kernel", the kernel a launch of the measured size runs."""
+    k = int(stats["launch_kernel"])
     return ("scan_waves" if k in (1, 2) else "scan_tiles"), k == 2
 
 
@@ -855,6 +856,7 @@ def measure_single(pf, torch, name, args, dev_name, threads, steps, headline=Fal
     else:
         tuning, tuned_now = trie.tuning(), False
     st = trie.stats()
+    st["launch_kernel"] = trie.launch_kernel(n)[0]
 
     stream = torch.cuda.current_stream()
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
@@ -942,6 +944,7 @@ def measure_batch(pf, torch, args, dev_name, threads):
     else:
         tuning, tuned_now = trie.tuning(), False
     st = trie.stats()
+    st["launch_kernel"] = trie.launch_kernel(total)[0]
     stream = torch.cuda.Stream()
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
     with torch.cuda.stream(stream):

@@ -224,6 +224,14 @@ void pfac_trie_free(pfac_trie *t);
 int pfac_trie_get_tuning(const pfac_trie *t, pfac_tuning *out);
 int pfac_trie_set_tuning(pfac_trie *t, const pfac_tuning *tuning);
 
+/* The kernels a launch over `total_bytes` bytes (one text, or a whole
+ * batch) runs with the current tuning, with kernel 3 resolved by that size:
+ * *kernel = 0 (tile kernel), 1 (fused wave kernel) or 2 (split filter +
+ * walk kernels); *tuning (may be NULL) = the tuning that launch uses.
+ * Host only.  Errors: PFAC_EINVAL (NULL trie or kernel). */
+int pfac_trie_launch_kernel(const pfac_trie *t, uint64_t total_bytes, uint32_t *kernel,
+                            pfac_tuning *tuning);
+
 /* -------------------------------------------------------------- workspace */
 
 /* Device scratch for scans: match staging, per-tile counts, plan tables.

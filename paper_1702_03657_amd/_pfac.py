@@ -92,6 +92,7 @@ SIGNATURES = [
     ("pfac_trie_export", ctypes.c_int, [_vp, _vp, _vp, _vp, _vp, _vp]),
     ("pfac_trie_free", None, [_vp]),
     ("pfac_trie_get_tuning", ctypes.c_int, [_vp, _p(pfac_tuning)]),
+    ("pfac_trie_launch_kernel", ctypes.c_int, [_vp, ctypes.c_uint64, _p(ctypes.c_uint32), _p(pfac_tuning)]),
     ("pfac_trie_set_tuning", ctypes.c_int, [_vp, _p(pfac_tuning)]),
     ("pfac_workspace_create", ctypes.c_int, [_p(_vp)]),
     ("pfac_workspace_free", None, [_vp]),
@@ -242,6 +243,15 @@ class Trie:
         t = pfac_tuning()
         check("pfac_trie_get_tuning", load().pfac_trie_get_tuning(self.handle, ctypes.byref(t)))
         return {n: getattr(t, n) for n, _ in t._fields_}
+
+    def launch_kernel(self, total_bytes: int):
+        """(kernel, tuning) of a launch over total_bytes: 0 = tile kernel,
+        1 = fused wave kernel, 2 = split filter + walk kernels."""
+        k = ctypes.c_uint32()
+        t = pfac_tuning()
+        check("pfac_trie_launch_kernel", load().pfac_trie_launch_kernel(
+            self.handle, int(total_bytes), ctypes.byref(k), ctypes.byref(t)))
+        return int(k.value), {n: getattr(t, n) for n, _ in t._fields_}
 
     def set_tuning(self, **fields):
         """Change the named fields of the launch tuning (pfac_tuning); the

@@ -556,6 +556,16 @@ extern "C" int pfac_trie_get_tuning(const pfac_trie *t, pfac_tuning *out) {
     return PFAC_OK;
 }
 
+extern "C" int pfac_trie_launch_kernel(const pfac_trie *t, uint64_t total_bytes, uint32_t *kernel,
+                                       pfac_tuning *tuning) {
+    if (!t || !kernel) return PFAC_EINVAL;
+    const pfac_tuning tn = launch_tuning(t, total_bytes);
+    uint32_t waves = tn.waves_per_wg;
+    *kernel = use_wave_kernel(t, tn, &waves) ? tn.kernel : 0u;
+    if (tuning) *tuning = tn;
+    return PFAC_OK;
+}
+
 static bool valid_tuning(const pfac_tuning *p) {
     return p->kernel <= 3 &&
            (p->bytes_per_lane == 4 || p->bytes_per_lane == 8 || p->bytes_per_lane == 16) &&

@@ -2,6 +2,7 @@
 oracle's trie definition), footprint arithmetic, C-ABI argument checks and
 that every symbol of include/pfac.h is exported.  No GPU call is made."""
 
+import ctypes
 import os
 import re
 import subprocess
@@ -155,6 +156,31 @@ def test_default_launch_and_filters(lib):
     assert s["stage2"] != 2
 
 
+def test_launch_kernel_by_size(lib):
+    """Kernel 3 (the default) resolves by launch size: the tile kernel with 4
+    bytes per lane below 1 MiB and 8 below 8 MiB, then the split kernels with
+    64-chunk units (fewer when the launch has under two units per resident
+    wave of the device's CUs); an explicit kernel is kept at every size."""
+    t = pf.Trie(workloads.c2_signature_set(n_text=64, k=2000).patterns, host_only=True)
+    assert t.tuning()["kernel"] == 3
+    k, tn = t.launch_kernel(64 << 10)
+    assert (k, tn["kernel"], tn["bytes_per_lane"]) == (0, 0, 4)
+    k, tn = t.launch_kernel((8 << 20) - 1)
+    assert (k, tn["kernel"], tn["bytes_per_lane"]) == (0, 0, 8)
+    k, tn = t.launch_kernel(8 << 20)
+    assert (k, tn["kernel"]) == (2, 2) and 1 <= tn["chunks_per_unit"] <= 64  # by the CU count
+    k, tn = t.launch_kernel(4 << 30)
+    assert (k, tn["kernel"], tn["chunks_per_unit"]) == (2, 2, 64)
+    assert t.stats()["scan_kernel"] == 2               # statistics: large launches
+    t.set_tuning(kernel=1)
+    assert [t.launch_kernel(n)[0] for n in (1 << 10, 1 << 30)] == [1, 1]
+    t.set_tuning(kernel=0)
+    assert [t.launch_kernel(n)[0] for n in (1 << 10, 1 << 30)] == [0, 0]
+    k = ctypes.c_uint32()
+    assert lib.pfac_trie_launch_kernel(None, 1, ctypes.byref(k), None) == pf.PFAC_EINVAL
+    assert lib.pfac_trie_launch_kernel(t.handle, 1, None, None) == pf.PFAC_EINVAL
+
+
 def test_placement_depths_reach_the_requested_level_index():
     """The placement ablation's tunings resolve exactly the requested number
     of trie levels in LDS (0: none), for a byte alphabet and for DNA."""
@@ -300,6 +326,8 @@ def test_host_allocation_failure_reports_enomem():
     script = r'''
 import resource, sys
 sys.path.insert(0, sys.argv[1])
+import ctypes
+
 import numpy as np
 import paper_1702_03657_amd as pf
 from synth import workloads
