@@ -428,6 +428,25 @@ __global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v) {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
 }
 
+// Largest i in [lo, hi) whose text starts at or before frame position G
+// (wave-uniform), or lo when there is none: each round the wave's 64 lanes
+// probe 64 evenly spaced starts (a 64-ary search, three rounds for 65,600
+// texts).
+__device__ __forceinline__ uint32_t wave_last_start(const uint64_t *offsets, uint64_t shift,
+                                                    uint32_t lo, uint32_t hi, uint64_t G,
+                                                    uint32_t lane) {
+    while (hi - lo > 1) {
+        const uint32_t step = (hi - lo + 63) / 64;
+        const uint32_t i = lo + lane * step;
+        const bool ok = i < hi && offsets[i] + shift <= G;
+        const uint32_t c = (uint32_t)__popcll(__ballot(ok));  // starts are ascending: lanes 0 .. c-1
+        if (c == 0) break;
+        lo += (c - 1) * step;
+        hi = min(hi, lo + step);
+    }
+    return lo;
+}
+
 // tile_first_text[t] = last text i whose start (in frame coordinates) is at or
 // before the first byte of tile t.  With chunk_info (1 KiB plan units of the
 // wave kernels) also the text boundaries of each chunk, packed as
@@ -438,38 +457,78 @@ __global__ void fill_u32_kernel(uint32_t *p, uint64_t n, uint32_t v) {
 //   y: the second, third and fourth, 10 bits each (0 when absent),
 // in ascending order, so that the filter kernel finds the distance from any
 // start position to the end of its text without searching the offsets.
+// One wave per 64 consecutive tiles: two wave searches bound the texts of
+// its tiles, whose starts the lanes then hold one each; every lane finds its
+// tile's text among them (or, past 64 texts, in global memory).
 __global__ void plan_kernel(const uint64_t *offsets, uint32_t n_texts, uint64_t shift,
                             uint64_t n_tiles, uint32_t tile, uint32_t *tile_first_text,
                             uint2 *chunk_info) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += stride) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t n_groups = (n_tiles + 63) / 64;
+    const uint64_t wpb = blockDim.x / 64;
+    const uint64_t waves = (uint64_t)gridDim.x * wpb;
+    for (uint64_t w = (uint64_t)blockIdx.x * wpb + (threadIdx.x >> 6); w < n_groups; w += waves) {
+        const uint64_t t0 = w * 64, t = t0 + lane;
+        const uint64_t tl = min(t0 + 63, n_tiles - 1);
         const uint64_t g = t * tile;
-        uint32_t lo = 0, hi = n_texts;
-        while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (offsets[mid] + shift <= g) lo = mid; else hi = mid;
+        const uint32_t lo_w = wave_last_start(offsets, shift, 0, n_texts, t0 * tile, lane);
+        const uint32_t hi_w = wave_last_start(offsets, shift, lo_w, n_texts, tl * tile, lane);
+        // starts of texts lo_w .. lo_w + 63, one per lane (~0 past the end)
+        const uint32_t wi = lo_w + lane;
+        const unsigned long long wv = wi <= n_texts ? offsets[wi] + shift : ~0ull;
+        // start of text i >= lo_w; every lane calls it at the same time
+        auto start_of = [&](uint32_t i) -> uint64_t {
+            const uint32_t r = i - lo_w;
+            const uint64_t v = __shfl(wv, (int)(r & 63u), 64);
+            if (r < 64) return v;
+            return i <= n_texts ? offsets[i] + shift : ~0ull;
+        };
+        uint32_t lo;
+        if (hi_w - lo_w < 64) {
+            // largest r < span with start_of(lo_w + r) <= g (r = 0 when none)
+            const uint32_t span = hi_w - lo_w + 1;
+            uint32_t r = 0;
+            for (uint32_t step = 32; step > 0; step >>= 1) {
+                const uint32_t c = r + step;
+                const uint64_t v = __shfl(wv, (int)(c & 63u), 64);
+                if (c < span && v <= g) r = c;
+            }
+            lo = lo_w + r;
+        } else {
+            lo = lo_w;
+            uint32_t hi = hi_w + 1;
+            while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (offsets[mid] + shift <= g) lo = mid; else hi = mid;
+            }
         }
-        tile_first_text[t] = lo;
+        if (t < n_tiles) tile_first_text[t] = lo;
         if (chunk_info) {
-            // boundaries offsets[lo .. n_texts] + shift: the first is at or
-            // before g, so only it can equal g; the rest lie after g
-            uint32_t cnt = 0, w[4] = {0, 0, 0, 0};
+            // boundaries start_of(lo), start_of(lo + 1), ...: the first is at
+            // or before g, so only it can equal g; the rest lie after g.  Six
+            // are enough: one before g, four inside, then the next one past
+            // the chunk or a fifth inside it.
+            uint32_t cnt = 0, w0 = 0, w1 = 0, w2 = 0, w3 = 0;
             uint64_t next = ~0ull;
-            for (uint32_t i = lo; i <= n_texts; i++) {
-                const uint64_t b = offsets[i] + shift;
-                if (b < g) continue;
+            bool done = false;
+            for (uint32_t k = 0; k < 6; k++) {
+                const uint64_t b = start_of(lo + k);
+                if (done || b < g) continue;
                 if (b >= g + tile) {
                     next = b;
-                    break;
-                }
-                if (cnt == 4) {
+                    done = true;
+                } else if (cnt == 4) {
                     cnt = 7;
-                    break;
+                    done = true;
+                } else {
+                    const uint32_t rel = (uint32_t)(b - g);
+                    if (cnt == 0) w0 = rel; else if (cnt == 1) w1 = rel; else if (cnt == 2) w2 = rel; else w3 = rel;
+                    cnt++;
                 }
-                w[cnt++] = (uint32_t)(b - g);
             }
             const uint32_t nrel = next - g > 0x1ffffull ? 0x1ffffu : (uint32_t)(next - g);
-            chunk_info[t] = make_uint2(nrel | (cnt << 17) | (w[0] << 20), w[1] | (w[2] << 10) | (w[3] << 20));
+            if (t < n_tiles)
+                chunk_info[t] = make_uint2(nrel | (cnt << 17) | (w0 << 20), w1 | (w2 << 10) | (w3 << 20));
         }
     }
 }
@@ -588,6 +647,7 @@ hipError_t launch_plan(const uint64_t *offsets, uint32_t n_texts, uint64_t shift
                        uint2 *chunk_info, hipStream_t s) {
     if (n_tiles == 0) return hipSuccess;
     if (chunk_info && tile != kWaveChunk) return hipErrorInvalidValue;
+    // one wave per 64 tiles, four waves per workgroup
     uint64_t g = (n_tiles + 255) / 256;
     const uint32_t grid = (uint32_t)(g < 65536 ? g : 65536);
     hipLaunchKernelGGL(plan_kernel, dim3(grid), dim3(256), 0, s, offsets, n_texts, shift,
