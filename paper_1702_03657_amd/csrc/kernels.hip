@@ -458,8 +458,8 @@ __device__ __forceinline__ uint32_t wave_last_start(const uint64_t *offsets, uin
 // in ascending order, so that the filter kernel finds the distance from any
 // start position to the end of its text without searching the offsets.
 // One wave per 64 consecutive tiles: two wave searches bound the texts of
-// its tiles, whose starts the lanes then hold one each; every lane finds its
-// tile's text among them (or, past 64 texts, in global memory).
+// its tiles, whose starts the lanes then hold two each; every lane finds its
+// tile's text among them (or, past 128 texts, in global memory).
 __global__ void plan_kernel(const uint64_t *offsets, uint32_t n_texts, uint64_t shift,
                             uint64_t n_tiles, uint32_t tile, uint32_t *tile_first_text,
                             uint2 *chunk_info) {
@@ -473,24 +473,30 @@ __global__ void plan_kernel(const uint64_t *offsets, uint32_t n_texts, uint64_t 
         const uint64_t g = t * tile;
         const uint32_t lo_w = wave_last_start(offsets, shift, 0, n_texts, t0 * tile, lane);
         const uint32_t hi_w = wave_last_start(offsets, shift, lo_w, n_texts, tl * tile, lane);
-        // starts of texts lo_w .. lo_w + 63, one per lane (~0 past the end)
+        // starts of texts lo_w .. lo_w + 127, two per lane (~0 past the end)
         const uint32_t wi = lo_w + lane;
-        const unsigned long long wv = wi <= n_texts ? offsets[wi] + shift : ~0ull;
+        const unsigned long long wv0 = wi <= n_texts ? offsets[wi] + shift : ~0ull;
+        const unsigned long long wv1 = wi + 64 <= n_texts ? offsets[wi + 64] + shift : ~0ull;
+        auto window = [&](uint32_t r) -> uint64_t {  // r < 128; every lane calls it at once
+            const uint64_t a = __shfl(wv0, (int)(r & 63u), 64);
+            const uint64_t b = __shfl(wv1, (int)(r & 63u), 64);
+            return r < 64 ? a : b;
+        };
         // start of text i >= lo_w; every lane calls it at the same time
         auto start_of = [&](uint32_t i) -> uint64_t {
             const uint32_t r = i - lo_w;
-            const uint64_t v = __shfl(wv, (int)(r & 63u), 64);
-            if (r < 64) return v;
+            const uint64_t v = window(r & 127u);
+            if (r < 128) return v;
             return i <= n_texts ? offsets[i] + shift : ~0ull;
         };
         uint32_t lo;
-        if (hi_w - lo_w < 64) {
+        if (hi_w - lo_w < 128) {
             // largest r < span with start_of(lo_w + r) <= g (r = 0 when none)
             const uint32_t span = hi_w - lo_w + 1;
             uint32_t r = 0;
-            for (uint32_t step = 32; step > 0; step >>= 1) {
+            for (uint32_t step = 64; step > 0; step >>= 1) {
                 const uint32_t c = r + step;
-                const uint64_t v = __shfl(wv, (int)(c & 63u), 64);
+                const uint64_t v = window(c & 127u);
                 if (c < span && v <= g) r = c;
             }
             lo = lo_w + r;
