@@ -120,8 +120,8 @@ typedef struct {
                                   kernels (filter kernel writes walk candidates, a walk kernel
                                   runs them; for alphabets of at most four bytes it uses the
                                   16-symbol filter when every pattern has 16 bytes or more),
-                                  3 = by launch size: 2 with 64 chunks per unit for
-                                  launches (a text, or a whole batch) of 8 MiB or more,
+                                  3 = by launch size: 2 with units of up to 64 chunks
+                                  for launches (a text, or a whole batch) of 8 MiB or more,
                                   else 0 with 4 bytes per lane below 1 MiB and 8 from
                                   there (the default for byte
                                   alphabets with K = 2 and for alphabets of at most four
@@ -132,9 +132,10 @@ typedef struct {
     uint32_t wg_per_cu;        /* resident workgroups per compute unit (0 = occupancy max) */
     uint32_t waves_per_wg;     /* wave kernel: 4, 8, 12 or 16 waves per workgroup (fewer when
                                   the LDS tables leave no room) */
-    uint32_t chunks_per_unit;  /* wave kernel: 1 KiB chunks per output unit, 1..64; a launch
-                                  of fewer chunks than 2 units per resident wave of the grid
-                                  uses fewer (a batch of small texts fills the GPU) */
+    uint32_t chunks_per_unit;  /* wave kernel: at most this many 1 KiB chunks per output
+                                  unit, 1..64; each launch takes the number up to it that
+                                  spreads its units most evenly over the grid's waves (a
+                                  batch of small texts takes small units and fills the GPU) */
     uint32_t child_check;      /* wave kernel second stage: 0 = none, 1 = check the byte after
                                   the level index against the depth-K node's child labels in
                                   LDS when they fit, 2 = the prefix-4 filter (two hashed bits

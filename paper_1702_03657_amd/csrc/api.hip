@@ -383,18 +383,44 @@ extern "C" int pfac_build(const uint8_t *const *patterns, const uint64_t *length
 // ahead of the tile kernel from 8 MiB on (their three launches and the
 // persistent grid do not pay off below); under that the one-launch tile
 // kernel is fastest with 4 bytes per lane below 1 MiB and 8 from there.
-// The split kernels take 64-chunk units (on the 2.2 GiB batch of 65,600
-// texts and 20,000 patterns, 16-chunk units cost 7% more per scan and
+// The split kernels take units of up to 64 chunks (on the 2.2 GiB batch of
+// 65,600 texts and 20,000 patterns, 16-chunk units cost 7% more per scan and
 // 32-chunk units 2%: more units mean more walk waves and emissions).
 constexpr uint64_t kAutoSplitBytes = 8ull << 20;
 constexpr uint64_t kAutoWideLanes = 1ull << 20;
 constexpr uint32_t kAutoUnitChunks = 64;
 
+// Chunks per unit for a wave-kernel launch over `chunks` 1 KiB chunks on
+// `waves` resident waves.  Units go to the waves one by one (wave w takes
+// units w, w + waves, ...), so the wave with the most chunks bounds the
+// filter kernel, while every unit costs the walk kernel a wave: take the
+// largest G in 1 .. gmax whose most loaded wave is within 2% of the best G's.
+// On MI355X, c4's 65,536 small texts (40,000 chunks, 4,096 waves) scan in
+// 56 us with G = 10 (one unit of at most 10 chunks per wave) against 67 us
+// with G = 4 (up to three units); the 2.2 GiB batch takes G = 63 (567 chunks
+// on the most loaded wave against 576 with G = 64: 1% faster).
+static uint32_t balanced_unit_chunks(uint64_t chunks, uint64_t waves, uint32_t gmax) {
+    uint64_t m[65] = {0}, best = ~0ull;
+    gmax = std::min<uint32_t>(std::max<uint32_t>(gmax, 1), 64);
+    for (uint32_t G = 1; G <= gmax; G++) {
+        const uint64_t U = (chunks + G - 1) / G;         // units
+        const uint64_t k = (U + waves - 1) / waves;      // most units of one wave
+        const uint64_t nk = U - (k - 1) * waves;         // waves with k units
+        const uint64_t last = chunks - (U - 1) * G;      // chunks of the last unit
+        m[G] = nk == 1 ? (k - 1) * G + last : k * G;
+        best = std::min(best, m[G]);
+    }
+    uint32_t g = 1;
+    for (uint32_t G = 1; G <= gmax; G++)
+        if (m[G] <= best + best / 50) g = G;
+    return g;
+}
+
 // The tuning a launch over `total` bytes runs with: kernel 3 resolved, and
-// for the wave kernels at most as many chunks per unit as give every
-// resident wave two units (output units are independent; a launch of few
-// chunks, such as a batch of small texts, needs small units to fill the
-// grid).
+// for the wave kernels the chunks per unit (at most the tuning's) that
+// spread the launch's units evenly over the grid's waves (output units are
+// independent; a launch of few chunks, such as a batch of small texts,
+// needs small units to fill the grid).
 static pfac_tuning launch_tuning(const pfac_trie *t, uint64_t total) {
     pfac_tuning tn = t->tuning;
     if (tn.kernel == 3) {
@@ -407,10 +433,11 @@ static pfac_tuning launch_tuning(const pfac_trie *t, uint64_t total) {
         }
     }
     if (tn.kernel == 1 || tn.kernel == 2) {
-        const uint64_t chunks = total / kWaveChunk + 1;
-        const uint64_t slots = 2ull * (uint64_t)std::max(t->n_cu, 1) * tn.waves_per_wg;
-        const uint64_t g = std::max<uint64_t>(1, chunks / slots);
-        if (g < tn.chunks_per_unit) tn.chunks_per_unit = (uint32_t)g;
+        // chunks of the frame (the text and at most 15 bytes before it)
+        const uint64_t chunks =
+            total >= (1ull << 50) ? (1ull << 40) : std::max<uint64_t>(1, (total + 15 + kWaveChunk - 1) / kWaveChunk);
+        const uint64_t waves = (uint64_t)std::max(t->n_cu, 1) * std::max<uint32_t>(tn.wg_per_cu, 1) * tn.waves_per_wg;
+        tn.chunks_per_unit = balanced_unit_chunks(chunks, waves, tn.chunks_per_unit);
     }
     return tn;
 }
