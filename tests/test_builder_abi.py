@@ -181,6 +181,41 @@ def test_launch_kernel_by_size(lib):
     assert lib.pfac_trie_launch_kernel(t.handle, 1, None, None) == pf.PFAC_EINVAL
 
 
+def _balanced_unit_chunks(chunks, waves, gmax):
+    """Chunks per unit that spread a wave-kernel launch over the grid's
+    waves: units go to the waves one by one, the most loaded wave bounds the
+    filter kernel; the largest G whose most loaded wave is within 2% of the
+    best G's (retyped here as the host rule the library documents)."""
+    m = {}
+    for g in range(1, gmax + 1):
+        units = -(-chunks // g)
+        k = -(-units // waves)
+        nk = units - (k - 1) * waves
+        last = chunks - (units - 1) * g
+        m[g] = (k - 1) * g + last if nk == 1 else k * g
+    best = min(m.values())
+    return max(g for g in m if m[g] <= best + best // 50)
+
+
+def test_units_balance_the_grid(lib):
+    """Split launches take the chunks per unit that balance the grid's waves
+    (a host-only trie counts one CU: 16 waves), never more than the tuning's."""
+    t = pf.Trie(workloads.c2_signature_set(n_text=64, k=2000).patterns, host_only=True)
+    for total in (8 << 20, (8 << 20) + 12345, 40 << 20, 100 << 20, 1 << 30, 3 << 30):
+        chunks = (total + 15 + 1023) // 1024
+        _, tn = t.launch_kernel(total)
+        assert tn["chunks_per_unit"] == _balanced_unit_chunks(chunks, 16, 64), total
+    # worked by hand on 4,096 waves: c4's small texts (39,968 chunks) take one
+    # unit of 10 chunks a wave; the 2.2 GiB batch (2,302,146 chunks) 63 (567
+    # chunks on the most loaded wave, 576 with 64, 563 at best with 1); a
+    # 256 MiB text (262,145 chunks) 64 (65, as with every G)
+    assert _balanced_unit_chunks(39968, 4096, 64) == 10
+    assert _balanced_unit_chunks(2302146, 4096, 64) == 63
+    assert _balanced_unit_chunks(262145, 4096, 64) == 64
+    t.set_tuning(kernel=2, chunks_per_unit=8)
+    assert t.launch_kernel(1 << 30)[1]["chunks_per_unit"] <= 8
+
+
 def test_placement_depths_reach_the_requested_level_index():
     """The placement ablation's tunings resolve exactly the requested number
     of trie levels in LDS (0: none), for a byte alphabet and for DNA."""
