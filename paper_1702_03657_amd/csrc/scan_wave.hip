@@ -486,7 +486,89 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         return sl;
     };
 
+    // The split kernels of modes 1 and 2 filter two chunks of a unit with one
+    // compaction and one run of stage-2 rounds when neither holds a text
+    // boundary (PAIR): their window is 2 KiB + 16 bytes, and the stage-1
+    // queue holds QCAP positions per round (a round with more takes the hit
+    // masks PB bits at a time).
+    constexpr bool PAIR = SPLIT && (MODE == 1 || MODE == 2);
+    constexpr uint32_t QCAP = PAIR ? kQ16 / 2 : kQ16;
+    constexpr uint32_t PB = QCAP / 64;
+    uint16_t *const wq16 = (uint16_t *)wq;
+
+    // ---- stage 1 of modes 1 and 2 over a lane's 16 positions into a hit
+    // mask: code = (B[j] << 8) | B[j+1] indexes the table, B[j+2] picks the
+    // folded child bit.  The table is the first LDS section and the kernel
+    // has no static LDS, so the code is the LDS address; all sixteen lookups
+    // are issued before any is used.  w: the lane's 16 bytes and the next 4.
+    auto stage1_mask = [&](const uint32_t *w) -> uint32_t {
+        uint32_t ent[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const uint32_t r = j & 3;
+            const uint32_t code = __builtin_amdgcn_perm(w[(j >> 2) + 1], w[j >> 2], 0x0c0c0000u | (r << 8) | (r + 1));
+            ent[j] = MODE == 1 ? (uint32_t)lds_tab8()[code] : (uint32_t)lds_tab16()[code];
+        }
+        uint32_t bit[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) {
+            const uint32_t nx = __builtin_amdgcn_ubfe(w[(j + 2) >> 2], 8 * ((j + 2) & 3), MODE == 1 ? 3 : 4);
+            bit[j] = __builtin_amdgcn_ubfe(ent[j], nx, 1);
+        }
+        return gather_bits(bit, std::make_integer_sequence<int, 15>{});
+    };
+    // ---- stage 2 of modes 1 and 2 for a position whose first four bytes
+    // are `by` and that passed the range checks: the prefix-4 filter or the
+    // exact third byte against the depth-2 node's child labels; v = the
+    // depth-2 node (from the level index)
+    auto stage2_check = [&](uint32_t by, bool &pass2, uint32_t &v) {
+        if (pass2 && pfx4) {
+            // both bits of the first four bytes' hash must be set, in the
+            // word that h1 names
+            const uint32_t t8 = by >> 8;
+            const uint32_t h1 = __umul24(by, im.pfx4_m1) + t8;
+            const uint32_t h2 = __umul24(t8, im.pfx4_m2) + by;
+            const uint32_t sh = 32u - im.pfx4_log2;
+            const uint32_t wd = *(const uint32_t *)(pfx4_base + ((h1 >> (sh + 5u)) << 2));
+            pass2 = ((wd >> ((h1 >> sh) & 31u)) & (wd >> (h2 >> 27)) & 1u) != 0;
+        }
+        if (pass2) {
+            const uint32_t code = __builtin_amdgcn_perm(0u, by, 0x0c0c0001u);
+            const uint2 lv = s_lvl[code >> 5];
+            v = lv.y + (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(lv.x, 0, code));
+            if (krec) {
+                // up to three child labels, or a count above 3
+                const uint32_t rec = s_krec[v - im.lvl_start];
+                const uint32_t ncc = rec >> 24;
+                if (ncc <= 3) {
+                    const uint32_t c = (by >> 16) & 0xffu;
+                    const uint32_t x = rec ^ (c * 0x00010101u);
+                    const uint32_t mm = (x - 0x00010101u) & ~x & 0x00808080u;
+                    pass2 = mm != 0 && ((uint32_t)__builtin_ctz(mm) >> 3) < ncc;
+                }
+            }
+        }
+    };
+
     uint32_t cn = 0, mn = 0;  // candidates, matches of the current unit (wave-uniform)
+    // split kernels: queue a candidate of unit u (ballot mask mk over the
+    // wave) with the 8 text bytes after the level index, B[pl+K ..
+    // pl+K+8), so that short walks read no text from global memory (bytes
+    // past the window are not text of it; the walk knows how many are valid)
+    auto push_cand = [&](uint32_t u, bool pass, unsigned long long mk, uint32_t entry, uint32_t v,
+                         uint32_t pl) {
+        const uint32_t idx = cn + mbcnt(mk);
+        if (pass && idx < a.cand_cap) {
+            const uint32_t q = pl + K, q4 = q & ~3u;
+            const uint32_t e0 = *(const uint32_t *)(wtext + q4);
+            const uint32_t e1 = *(const uint32_t *)(wtext + q4 + 4);
+            const uint32_t e2 = *(const uint32_t *)(wtext + q4 + 8);
+            a.cand[(uint64_t)u * a.cand_cap + idx] =
+                make_uint4(entry, v, __builtin_amdgcn_alignbyte(e1, e0, q & 3u), __builtin_amdgcn_alignbyte(e2, e1, q & 3u));
+        }
+        cn += (uint32_t)__popcll(mk);
+    };
+
     // Filter chunk cc with the data of slot sl, close its unit after its last
     // chunk, and step cc to the wave's next chunk (nothing past the wave's
     // last chunk).
@@ -501,26 +583,14 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             cn = 0;
             mn = 0;
         }
-        uint4 *const wcg = SPLIT ? a.cand + (uint64_t)u * a.cand_cap : nullptr;
-        // queue a candidate (ballot mask mk over the wave); the split kernels
-        // also pass on the 8 text bytes after the level index, B[pl+K ..
-        // pl+K+8), so that short walks read no text from global memory
+        // queue a candidate (ballot mask mk over the wave)
         auto push = [&](bool pass, unsigned long long mk, uint32_t entry, uint32_t v, uint32_t pl) {
-            const uint32_t idx = cn + mbcnt(mk);
-            if (pass) {
-                if (!SPLIT) {
-                    wc[idx] = make_uint2(entry, v);
-                } else if (idx < a.cand_cap) {
-                    // bytes at or past kWin are not text of this window;
-                    // the walk knows how many are valid
-                    const uint32_t q = pl + K, q4 = q & ~3u;
-                    const uint32_t e0 = *(const uint32_t *)(wtext + q4);
-                    const uint32_t e1 = *(const uint32_t *)(wtext + q4 + 4);
-                    const uint32_t e2 = *(const uint32_t *)(wtext + q4 + 8);
-                    wcg[idx] = make_uint4(entry, v, __builtin_amdgcn_alignbyte(e1, e0, q & 3u),
-                                          __builtin_amdgcn_alignbyte(e2, e1, q & 3u));
-                }
+            if (SPLIT) {
+                push_cand(u, pass, mk, entry, v, pl);
+                return;
             }
+            const uint32_t idx = cn + mbcnt(mk);
+            if (pass) wc[idx] = make_uint2(entry, v);
             cn += (uint32_t)__popcll(mk);
         };
 
@@ -648,40 +718,16 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         };
 
         if (MODE == 1 || MODE == 2) {
-            // ---- stage 1 over the lane's 16 positions into a hit mask:
-            // code = (B[j] << 8) | B[j+1] indexes the table, B[j+2]
-            // picks the folded child bit.  The table is the first LDS
-            // section and the kernel has no static LDS, so the code is
-            // the LDS address; all sixteen lookups are issued before any
-            // is used.
-            uint32_t ent[16];
-#pragma unroll
-            for (int j = 0; j < 16; j++) {
-                const uint32_t r = j & 3;
-                const uint32_t code =
-                    __builtin_amdgcn_perm(w[(j >> 2) + 1], w[j >> 2], 0x0c0c0000u | (r << 8) | (r + 1));
-                ent[j] = MODE == 1 ? (uint32_t)lds_tab8()[code] : (uint32_t)lds_tab16()[code];
-            }
-            uint32_t bit[16];
-#pragma unroll
-            for (int j = 0; j < 16; j++) {
-                const uint32_t nx = __builtin_amdgcn_ubfe(w[(j + 2) >> 2], 8 * ((j + 2) & 3),
-                                                          MODE == 1 ? 3 : 4);
-                bit[j] = __builtin_amdgcn_ubfe(ent[j], nx, 1);
-            }
-            const uint32_t hm = gather_bits(bit, std::make_integer_sequence<int, 15>{});
-            // compact the hits of the wave, at most kQ16 per round
-            uint16_t *wq16 = (uint16_t *)wq;
+            const uint32_t hm = stage1_mask(w);
+            // compact the hits of the wave, at most QCAP per round
             uint32_t tot;
             const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
-            const int rounds = tot > kQ16 ? 2 : 1;
-            // valid positions and the distance to the next text boundary,
-            // relative to the chunk (wave-uniform)
-            for (int half = 0; half < rounds; half++) {
+            const int parts = tot > QCAP ? (int)(16 / PB) : 1;
+            for (int part = 0; part < parts; part++) {
                 uint32_t mset = hm, o = off_all, qn = tot, jb = 0;
-                if (rounds == 2) {
-                    mset = half == 0 ? (hm & 0xffu) : (hm >> 8);
-                    jb = half == 0 ? 0u : 8u;
+                if (parts > 1) {
+                    jb = (uint32_t)part * PB;
+                    mset = (hm >> jb) & ((1u << PB) - 1u);
                     o = wave_excl_scan((uint32_t)__builtin_popcount(mset), qn);
                 }
                 while (mset) {
@@ -690,10 +736,10 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                     mset &= mset - 1;
                 }
                 wave_sync();
-                // ---- stage 2 (K = 2): the text's end, the exact third
-                // byte against the depth-2 node's child labels, the node
-                // the filters read 4 bytes (prefix-4 filter: every pattern
-                // is that long) or 3 (child labels); in a chunk without
+                // ---- stage 2 (K = 2): the text's end, then the prefix-4
+                // filter or the child labels and the depth-2 node.  The
+                // filters read 4 bytes (prefix-4 filter: every pattern is
+                // that long) or 3 (child labels); in a chunk without
                 // boundaries the positions [vlo, top) have them in the text
                 const uint32_t need = pfx4 ? 4u : 3u;
                 const uint32_t top = min(vhi, nrel + 1u - need);
@@ -716,32 +762,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                             lim = lim_of(pl);
                             pass2 = pl >= vlo && pl < vhi && lim >= need;
                         }
-                        if (pass2 && pfx4) {
-                            // both bits of the first four bytes' hash must be
-                            // set, in the word that h1 names
-                            const uint32_t t8 = by >> 8;
-                            const uint32_t h1 = __umul24(by, im.pfx4_m1) + t8;
-                            const uint32_t h2 = __umul24(t8, im.pfx4_m2) + by;
-                            const uint32_t sh = 32u - im.pfx4_log2;
-                            const uint32_t wd = *(const uint32_t *)(pfx4_base + ((h1 >> (sh + 5u)) << 2));
-                            pass2 = ((wd >> ((h1 >> sh) & 31u)) & (wd >> (h2 >> 27)) & 1u) != 0;
-                        }
-                        if (pass2) {
-                            const uint32_t code = __builtin_amdgcn_perm(0u, by, 0x0c0c0001u);
-                            const uint2 lv = s_lvl[code >> 5];
-                            v = lv.y + (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(lv.x, 0, code));
-                            if (krec) {
-                                // up to three child labels, or a count above 3
-                                const uint32_t rec = s_krec[v - im.lvl_start];
-                                const uint32_t ncc = rec >> 24;
-                                if (ncc <= 3) {
-                                    const uint32_t c = (by >> 16) & 0xffu;
-                                    const uint32_t x = rec ^ (c * 0x00010101u);
-                                    const uint32_t mm = (x - 0x00010101u) & ~x & 0x00808080u;
-                                    pass2 = mm != 0 && ((uint32_t)__builtin_ctz(mm) >> 3) < ncc;
-                                }
-                            }
-                        }
+                        stage2_check(by, pass2, v);
                         entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
                     }
                     push(pass2, __ballot(pass2), entry, v, entry & (kChunk - 1));
@@ -774,7 +795,6 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
 #pragma unroll
             for (int j = 0; j < 16; j++)
                 hm |= ((ent[j] >> hh[j]) & (ent[j] >> (hh[j] >> 5)) & 1u) << j;
-            uint16_t *wq16 = (uint16_t *)wq;
             uint32_t tot;
             const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
             const int rounds = tot > kQ16 ? 2 : 1;
@@ -929,6 +949,85 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         advance(cc);
     };
 
+    // Chunks cc and cc + 1 from slots sa and sb: together when they are
+    // chunks g and g + 1 of one unit, both inside the text (see interior)
+    // and neither holding a text boundary; else one by one.  Together they
+    // share one window (chunk g at 0, chunk g + 1 at kChunk), one
+    // compaction of their 32 stage-1 bits per lane and one run of stage-2
+    // rounds over positions 0 .. 2 kChunk - 1 relative to chunk g.
+    auto pair = [&](const Slot &sa, const Slot &sb, Cur &cc) {
+        if (cc.u >= n_u) return;
+        const uint32_t u = cc.u, g = cc.g, nch = cc.n;
+        const uint32_t c = u * G + g;
+        const uint32_t bxa = (uint32_t)__builtin_amdgcn_readfirstlane((int)sa.info.x);
+        const uint32_t bxb = (uint32_t)__builtin_amdgcn_readfirstlane((int)sb.info.x);
+        bool together = g + 1 < nch && interior(c) && interior(c + 1);
+        if (a.chunk_info) together = together && ((bxa | bxb) & (7u << 17)) == 0;
+        if (!together) {
+            chunk(sa, cc);
+            chunk(sb, cc);
+            return;
+        }
+        if (g == 0) cn = 0;
+        const uint64_t chunk_lo = (uint64_t)c * kChunk;
+        *(uint4 *)(wtext + 16 * lane) = sa.v;
+        *(uint4 *)(wtext + kChunk + 16 * lane) = sb.v;
+        if (lane_at(c) == 63) *(uint4 *)(wtext + 2 * kChunk) = sb.h;
+        wave_sync();
+        // distance from chunk g's start to the first text boundary at or
+        // past its end, which lies at or past chunk g + 1's end
+        const uint32_t nrel = a.chunk_info
+                                  ? (bxa & 0x1ffffu)
+                                  : (n_ch - c > 128u ? 0x1ffffu : min((uint32_t)hi_valid - (uint32_t)chunk_lo, 0x1ffffu));
+        const uint32_t wa[5] = {sa.v.x, sa.v.y, sa.v.z, sa.v.w, sa.h.x};
+        const uint32_t wb[5] = {sb.v.x, sb.v.y, sb.v.z, sb.v.w, sb.h.x};
+        // bit j < 16: position 16 lane + j of chunk g; bit 16 + j: of chunk g + 1
+        const uint32_t hm = stage1_mask(wa) | (stage1_mask(wb) << 16);
+        uint32_t tot;
+        const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
+        const int parts = tot > QCAP ? (int)(32 / PB) : 1;
+        for (int part = 0; part < parts; part++) {
+            uint32_t mset = hm, o = off_all, qn = tot, jb = 0;
+            if (parts > 1) {
+                jb = (uint32_t)part * PB;
+                mset = (hm >> jb) & ((1u << PB) - 1u);
+                o = wave_excl_scan((uint32_t)__builtin_popcount(mset), qn);
+            }
+            while (mset) {
+                const uint32_t j = jb + (uint32_t)__builtin_ctz(mset);
+                wq16[o++] = (uint16_t)((j >> 4) * kChunk + 16 * lane + (j & 15u));
+                mset &= mset - 1;
+            }
+            wave_sync();
+            // ---- stage 2 as in chunk(), for a window without boundaries:
+            // positions below top have the bytes the filters read
+            const uint32_t need = pfx4 ? 4u : 3u;
+            const uint32_t top = min(2 * kChunk + 16, nrel + 1u - need);
+            for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
+                const uint32_t e = r0 + lane;
+                bool pass2 = false;
+                uint32_t entry = 0, v = 0, pl = 0;
+                if (e < qn) {
+                    pl = wq16[e];
+                    const uint32_t a4 = pl & ~3u;
+                    const uint32_t d0 = *(const uint32_t *)(wtext + a4);
+                    const uint32_t d1 = *(const uint32_t *)(wtext + a4 + 4);
+                    const uint32_t by = __builtin_amdgcn_alignbyte(d1, d0, pl);  // B[pl..pl+3]
+                    const uint32_t lim = min(nrel - pl, 0xffffu);
+                    pass2 = pl < top;
+                    stage2_check(by, pass2, v);
+                    entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
+                }
+                push_cand(u, pass2, __ballot(pass2), entry, v, pl);
+            }
+            wave_sync();
+        }
+        // the unit's last two chunks: hand over its candidates
+        if (g + 2 == nch && lane_at(u) == 0) a.cand_count[u] = cn;
+        advance(cc);
+        advance(cc);
+    };
+
     // Three chunks in flight: the loads of the chunk two ahead are issued
     // before a chunk is filtered.  The loop runs over whole groups of three
     // with its one exit at the bottom (slot variables keep their registers
@@ -942,20 +1041,45 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         n_wave = (nu - 1) * G + unit_chunks(u0 + (nu - 1) * ustride);
     }
     Cur cc = start_at(u0), pc = cc;
-    Slot sa = load_slot(pc);
-    advance(pc);
-    Slot sb = load_slot(pc);
-    advance(pc);
-    for (uint32_t grp = 0; grp < (n_wave + 2) / 3; grp++) {
-        const Slot sc = load_slot(pc);
+    if constexpr (PAIR) {
+        // two pairs of chunks in flight, the loop over whole groups of two
+        // pairs with its one exit at the bottom
+        Slot sa = load_slot(pc);
         advance(pc);
-        chunk(sa, cc);
-        sa = load_slot(pc);
+        Slot sb = load_slot(pc);
         advance(pc);
-        chunk(sb, cc);
-        sb = load_slot(pc);
+        Slot sc = load_slot(pc);
         advance(pc);
-        chunk(sc, cc);
+        Slot sd = load_slot(pc);
+        advance(pc);
+        for (uint32_t grp = 0; grp < (n_wave + 3) / 4; grp++) {
+            pair(sa, sb, cc);
+            sa = load_slot(pc);
+            advance(pc);
+            sb = load_slot(pc);
+            advance(pc);
+            pair(sc, sd, cc);
+            sc = load_slot(pc);
+            advance(pc);
+            sd = load_slot(pc);
+            advance(pc);
+        }
+    } else {
+        Slot sa = load_slot(pc);
+        advance(pc);
+        Slot sb = load_slot(pc);
+        advance(pc);
+        for (uint32_t grp = 0; grp < (n_wave + 2) / 3; grp++) {
+            const Slot sc = load_slot(pc);
+            advance(pc);
+            chunk(sa, cc);
+            sa = load_slot(pc);
+            advance(pc);
+            chunk(sb, cc);
+            sb = load_slot(pc);
+            advance(pc);
+            chunk(sc, cc);
+        }
     }
 }
 
@@ -1110,6 +1234,13 @@ __global__ __launch_bounds__(64 * kWalkWaves, 4) void walk_units(const ScanArgs 
 
 // ------------------------------------------------------------------ launchers
 
+// modes 1 and 2: byte symbols, K = 2, the third byte folded to 8 or 16 bits
+// (and not the four-symbol filter, which the split kernel prefers)
+static bool byte_table_mode(const ScanArgs &a) {
+    return a.q16_words == 0 && a.im.identity && a.im.K == 2 && (a.fold == 8 || a.fold == 16) &&
+           a.im.fold_syms == 1;
+}
+
 void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit, bool split) {
     uint32_t off = 0;
     auto take = [&](uint32_t bytes) {
@@ -1136,9 +1267,12 @@ void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit, bool split
     // the split filter kernel keeps no candidate or match lists in LDS
     a.mcap = split ? 0 : 64;
     a.ccap = split ? 0 : 128;
-    a.woff_bnd = (kWin + 16 + 15) & ~15u;
+    // the split kernels of modes 1 and 2 filter chunks in pairs: a 2 KiB
+    // window and a queue of half the size
+    const bool pair = split && byte_table_mode(a);
+    a.woff_bnd = ((pair ? 2 * kChunk : kWin) + 16 + 15) & ~15u;
     a.woff_queue = a.woff_bnd + ((4 * (kWin / 32 + 2) + 15) & ~15u);
-    a.woff_cand = a.woff_queue + std::max(4 * kQ1, 8 * a.mcap);
+    a.woff_cand = a.woff_queue + std::max(pair ? 2 * kQ1 : 4 * kQ1, 8 * a.mcap);
     a.woff_match = a.woff_cand + 8 * a.ccap;
     a.wave_bytes = a.woff_match + 8 * a.mcap;
     a.lds_total = off + waves * a.wave_bytes;
@@ -1153,8 +1287,7 @@ int wave_mode(const ScanArgs &a) {
     if (a.off_ftab != 0) return split;  // modes 1..3 need the table at LDS address 0
     if (split && a.q16_words) return 6;
     const bool p4 = split && a.pfx4_words != 0;
-    if (a.im.identity && a.im.K == 2 && a.fold == 8 && a.im.fold_syms == 1) return p4 ? 7 : 1 + split;
-    if (a.im.identity && a.im.K == 2 && a.fold == 16 && a.im.fold_syms == 1) return p4 ? 8 : 2 + split;
+    if (byte_table_mode(a)) return (a.fold == 8 ? 1 : 2) + (p4 ? 6 : split);
     return split;
 }
 
