@@ -769,7 +769,7 @@ static uint32_t unit_bytes(const pfac_trie *t, const pfac_tuning &tn) {
 // Opt a kernel into more than 64 KiB of dynamic LDS (once per size).
 static hipError_t grant_lds(int slot, uint32_t bytes, hipError_t (*fn)(int, uint32_t), int arg) {
     static std::mutex mu;
-    static uint32_t granted[16] = {};
+    static uint32_t granted[32] = {};
     std::lock_guard<std::mutex> lock(mu);
     if (granted[slot] >= bytes) return hipSuccess;
     hipError_t e = fn(arg, bytes);

@@ -361,7 +361,7 @@ __device__ __forceinline__ void unit_from_root(const ScanArgs &a, uint64_t u, ui
 // without the LDS tables); otherwise walk and emit here.
 // P4 (modes 1 and 2, split): stage 2 checks the prefix-4 filter, which the
 // launch guarantees, and has no child-record path.
-template <int MODE, bool SPLIT, bool P4 = false>
+template <int MODE, bool SPLIT, bool P4 = false, int TX = 0>
 __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
     const ImageView &im = a.im;
@@ -421,6 +421,9 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     const uint32_t ccap = a.ccap, mcap = a.mcap;
     const bool krec = !P4 && a.krec_words != 0;
     const bool pfx4 = P4 || a.pfx4_words != 0;
+    // text boundaries per chunk from the batch plan (TX 2), from the one
+    // text's two ends (TX 1), or as chunk_info says (TX 0)
+    const bool has_info = TX == 0 ? a.chunk_info != nullptr : TX == 2;
 
     // Chunk c covers frame bytes [c KiB, (c + 1) KiB); chunks 0 .. n_ch - 1
     // hold text.  Chunk and unit indices are 32-bit (the host refuses texts
@@ -481,8 +484,12 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         }
         sl.v = *(const uint4 *)(a.base + sb + ov);
         sl.h = *(const uint4 *)(a.base + sb + oh);
-        const uint2 *ip = a.chunk_info ? a.chunk_info + min(c, n_ch - 1) : (const uint2 *)(a.base + blk_lo);
-        sl.info = *ip;
+        if (TX == 1) {
+            sl.info = make_uint2(0u, 0u);
+        } else {
+            const uint2 *ip = has_info ? a.chunk_info + min(c, n_ch - 1) : (const uint2 *)(a.base + blk_lo);
+            sl.info = *ip;
+        }
         return sl;
     };
 
@@ -629,11 +636,11 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         // load into its registers)
         uint32_t bx = (uint32_t)__builtin_amdgcn_readfirstlane((int)sl.info.x);
         uint32_t by = (uint32_t)__builtin_amdgcn_readfirstlane((int)sl.info.y);
-        if (!a.chunk_info && inner) {
+        if (!has_info && inner) {
             // no end of the text in the chunk; the next one is its end
             bx = n_ch - c > 128u ? 0x1ffffu : min((uint32_t)hi_valid - (uint32_t)chunk_lo, 0x1ffffu);
             by = 0;
-        } else if (!a.chunk_info) {
+        } else if (!has_info) {
             // the text's first byte and its end: ascending, at most one of
             // each in the chunk
             const bool lo_in = lo_valid >= chunk_lo && lo_valid < chunk_lo + kChunk;
@@ -962,7 +969,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         const uint32_t bxa = (uint32_t)__builtin_amdgcn_readfirstlane((int)sa.info.x);
         const uint32_t bxb = (uint32_t)__builtin_amdgcn_readfirstlane((int)sb.info.x);
         bool together = g + 1 < nch && interior(c) && interior(c + 1);
-        if (a.chunk_info) together = together && ((bxa | bxb) & (7u << 17)) == 0;
+        if (has_info) together = together && ((bxa | bxb) & (7u << 17)) == 0;
         if (!together) {
             chunk(sa, cc);
             chunk(sb, cc);
@@ -976,7 +983,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         wave_sync();
         // distance from chunk g's start to the first text boundary at or
         // past its end, which lies at or past chunk g + 1's end
-        const uint32_t nrel = a.chunk_info
+        const uint32_t nrel = has_info
                                   ? (bxa & 0x1ffffu)
                                   : (n_ch - c > 128u ? 0x1ffffu : min((uint32_t)hi_valid - (uint32_t)chunk_lo, 0x1ffffu));
         const uint32_t wa[5] = {sa.v.x, sa.v.y, sa.v.z, sa.v.w, sa.h.x};
@@ -1281,32 +1288,39 @@ void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit, bool split
 
 // 0..2: fused kernels; 3..5: the split filter kernels of modes 0..2; 6: the
 // split filter kernel of mode 3 (four-symbol alphabets); 7, 8: the split
-// filter kernels of modes 1 and 2 with the prefix-4 filter
+// filter kernels of modes 1 and 2 with the prefix-4 filter.  The split
+// kernels of modes 1 and 2 (4, 5, 7, 8) come in two forms: for one text, and
+// for batches (9, 10, 11, 12), which read the plan's boundaries per chunk.
 int wave_mode(const ScanArgs &a) {
     const int split = a.cand != nullptr ? 3 : 0;
     if (a.off_ftab != 0) return split;  // modes 1..3 need the table at LDS address 0
     if (split && a.q16_words) return 6;
     const bool p4 = split && a.pfx4_words != 0;
-    if (byte_table_mode(a)) return (a.fold == 8 ? 1 : 2) + (p4 ? 6 : split);
+    if (byte_table_mode(a)) {
+        const int m = (a.fold == 8 ? 1 : 2) + (p4 ? 6 : split);
+        if (!split || !a.chunk_info) return m;
+        return m <= 5 ? m + 5 : m + 4;
+    }
     return split;
 }
 
-template <int MODE>
-static const void *wave_fn(bool split) {
-    return split ? (const void *)scan_waves<MODE, true> : (const void *)scan_waves<MODE, false>;
-}
-
 // modes 3..5 are the split variants of modes 0..2, 6 of mode 3, 7 and 8 of
-// modes 1 and 2 with the prefix-4 filter
+// modes 1 and 2 with the prefix-4 filter, 9..12 the batch forms of 4, 5, 7, 8
 static const void *wave_fn_for(int mode) {
-    if (mode == 6) return (const void *)scan_waves<3, true>;
-    if (mode == 7) return (const void *)scan_waves<1, true, true>;
-    if (mode == 8) return (const void *)scan_waves<2, true, true>;
-    const bool split = mode >= 3;
-    switch (mode % 3) {
-        case 1: return wave_fn<1>(split);
-        case 2: return wave_fn<2>(split);
-        default: return wave_fn<0>(split);
+    switch (mode) {
+        case 1: return (const void *)scan_waves<1, false>;
+        case 2: return (const void *)scan_waves<2, false>;
+        case 3: return (const void *)scan_waves<0, true>;
+        case 4: return (const void *)scan_waves<1, true, false, 1>;
+        case 5: return (const void *)scan_waves<2, true, false, 1>;
+        case 6: return (const void *)scan_waves<3, true>;
+        case 7: return (const void *)scan_waves<1, true, true, 1>;
+        case 8: return (const void *)scan_waves<2, true, true, 1>;
+        case 9: return (const void *)scan_waves<1, true, false, 2>;
+        case 10: return (const void *)scan_waves<2, true, false, 2>;
+        case 11: return (const void *)scan_waves<1, true, true, 2>;
+        case 12: return (const void *)scan_waves<2, true, true, 2>;
+        default: return (const void *)scan_waves<0, false>;
     }
 }
 
@@ -1324,17 +1338,11 @@ hipError_t prepare_wave_kernel(int mode, uint32_t lds_bytes) {
 hipError_t launch_scan_waves(const ScanArgs &a, uint32_t waves, uint32_t grid, hipStream_t s) {
     const int mode = wave_mode(a);
     const dim3 block(64 * waves);
-    switch (mode) {
-        case 1: hipLaunchKernelGGL((scan_waves<1, false>), dim3(grid), block, a.lds_total, s, a); break;
-        case 2: hipLaunchKernelGGL((scan_waves<2, false>), dim3(grid), block, a.lds_total, s, a); break;
-        case 3: hipLaunchKernelGGL((scan_waves<0, true>), dim3(grid), block, a.lds_total, s, a); break;
-        case 4: hipLaunchKernelGGL((scan_waves<1, true>), dim3(grid), block, a.lds_total, s, a); break;
-        case 5: hipLaunchKernelGGL((scan_waves<2, true>), dim3(grid), block, a.lds_total, s, a); break;
-        case 6: hipLaunchKernelGGL((scan_waves<3, true>), dim3(grid), block, a.lds_total, s, a); break;
-        case 7: hipLaunchKernelGGL((scan_waves<1, true, true>), dim3(grid), block, a.lds_total, s, a); break;
-        case 8: hipLaunchKernelGGL((scan_waves<2, true, true>), dim3(grid), block, a.lds_total, s, a); break;
-        default: hipLaunchKernelGGL((scan_waves<0, false>), dim3(grid), block, a.lds_total, s, a); break;
-    }
+    const void *fn = wave_fn_for(mode);
+    ScanArgs arg = a;
+    void *args[] = {(void *)&arg};
+    const hipError_t e = hipLaunchKernel(fn, dim3(grid), block, args, a.lds_total, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
