@@ -1010,22 +1010,48 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             // positions below top have the bytes the filters read
             const uint32_t need = pfx4 ? 4u : 3u;
             const uint32_t top = min(2 * kChunk + 16, nrel + 1u - need);
-            for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
-                const uint32_t e = r0 + lane;
-                bool pass2 = false;
-                uint32_t entry = 0, v = 0, pl = 0;
-                if (e < qn) {
-                    pl = wq16[e];
+            if constexpr (P4) {
+                // without branches until the record: lanes past the queue
+                // read its last entry (so every lookup stays inside its
+                // table) and fail
+                const uint32_t sh = 32u - im.pfx4_log2;
+                for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
+                    const uint32_t e = r0 + lane;
+                    const uint32_t pl = wq16[min(e, qn - 1u)];
                     const uint32_t a4 = pl & ~3u;
                     const uint32_t d0 = *(const uint32_t *)(wtext + a4);
                     const uint32_t d1 = *(const uint32_t *)(wtext + a4 + 4);
                     const uint32_t by = __builtin_amdgcn_alignbyte(d1, d0, pl);  // B[pl..pl+3]
+                    const uint32_t t8 = by >> 8;
+                    const uint32_t h1 = __umul24(by, im.pfx4_m1) + t8;
+                    const uint32_t h2 = __umul24(t8, im.pfx4_m2) + by;
+                    const uint32_t wd = *(const uint32_t *)(pfx4_base + ((h1 >> (sh + 5u)) << 2));
+                    const uint32_t code = __builtin_amdgcn_perm(0u, by, 0x0c0c0001u);
+                    const uint2 lv = s_lvl[code >> 5];
+                    const uint32_t v = lv.y + (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(lv.x, 0, code));
                     const uint32_t lim = min(nrel - pl, 0xffffu);
-                    pass2 = pl < top;
-                    stage2_check(by, pass2, v);
-                    entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
+                    const uint32_t entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
+                    const bool pass2 = e < qn && pl < top && ((wd >> ((h1 >> sh) & 31u)) & (wd >> (h2 >> 27)) & 1u) != 0;
+                    push_cand(u, pass2, __ballot(pass2), entry, v, pl);
                 }
-                push_cand(u, pass2, __ballot(pass2), entry, v, pl);
+            } else {
+                for (uint32_t r0 = 0; r0 < qn; r0 += 64) {
+                    const uint32_t e = r0 + lane;
+                    bool pass2 = false;
+                    uint32_t entry = 0, v = 0, pl = 0;
+                    if (e < qn) {
+                        pl = wq16[e];
+                        const uint32_t a4 = pl & ~3u;
+                        const uint32_t d0 = *(const uint32_t *)(wtext + a4);
+                        const uint32_t d1 = *(const uint32_t *)(wtext + a4 + 4);
+                        const uint32_t by = __builtin_amdgcn_alignbyte(d1, d0, pl);  // B[pl..pl+3]
+                        const uint32_t lim = min(nrel - pl, 0xffffu);
+                        pass2 = pl < top;
+                        stage2_check(by, pass2, v);
+                        entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
+                    }
+                    push_cand(u, pass2, __ballot(pass2), entry, v, pl);
+                }
             }
             wave_sync();
         }
