@@ -1315,12 +1315,13 @@ void wave_lds_layout(ScanArgs &a, uint32_t waves, uint32_t lds_limit, bool split
 // 0..2: fused kernels; 3..5: the split filter kernels of modes 0..2; 6: the
 // split filter kernel of mode 3 (four-symbol alphabets); 7, 8: the split
 // filter kernels of modes 1 and 2 with the prefix-4 filter.  The split
-// kernels of modes 1 and 2 (4, 5, 7, 8) come in two forms: for one text, and
-// for batches (9, 10, 11, 12), which read the plan's boundaries per chunk.
+// kernels of modes 1..3 (4, 5, 6, 7, 8) come in two forms: for one text, and
+// for batches (9, 10, 13, 11, 12), which read the plan's boundaries per
+// chunk.
 int wave_mode(const ScanArgs &a) {
     const int split = a.cand != nullptr ? 3 : 0;
     if (a.off_ftab != 0) return split;  // modes 1..3 need the table at LDS address 0
-    if (split && a.q16_words) return 6;
+    if (split && a.q16_words) return a.chunk_info ? 13 : 6;
     const bool p4 = split && a.pfx4_words != 0;
     if (byte_table_mode(a)) {
         const int m = (a.fold == 8 ? 1 : 2) + (p4 ? 6 : split);
@@ -1331,7 +1332,8 @@ int wave_mode(const ScanArgs &a) {
 }
 
 // modes 3..5 are the split variants of modes 0..2, 6 of mode 3, 7 and 8 of
-// modes 1 and 2 with the prefix-4 filter, 9..12 the batch forms of 4, 5, 7, 8
+// modes 1 and 2 with the prefix-4 filter, 9..13 the batch forms of 4, 5, 7,
+// 8 and 6
 static const void *wave_fn_for(int mode) {
     switch (mode) {
         case 1: return (const void *)scan_waves<1, false>;
@@ -1339,13 +1341,14 @@ static const void *wave_fn_for(int mode) {
         case 3: return (const void *)scan_waves<0, true>;
         case 4: return (const void *)scan_waves<1, true, false, 1>;
         case 5: return (const void *)scan_waves<2, true, false, 1>;
-        case 6: return (const void *)scan_waves<3, true>;
+        case 6: return (const void *)scan_waves<3, true, false, 1>;
         case 7: return (const void *)scan_waves<1, true, true, 1>;
         case 8: return (const void *)scan_waves<2, true, true, 1>;
         case 9: return (const void *)scan_waves<1, true, false, 2>;
         case 10: return (const void *)scan_waves<2, true, false, 2>;
         case 11: return (const void *)scan_waves<1, true, true, 2>;
         case 12: return (const void *)scan_waves<2, true, true, 2>;
+        case 13: return (const void *)scan_waves<3, true, false, 2>;
         default: return (const void *)scan_waves<0, false>;
     }
 }
