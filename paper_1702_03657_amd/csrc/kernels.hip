@@ -472,11 +472,18 @@ __global__ void plan_kernel(const uint64_t *offsets, uint32_t n_texts, uint64_t 
         const uint64_t tl = min(t0 + 63, n_tiles - 1);
         const uint64_t g = t * tile;
         const uint32_t lo_w = wave_last_start(offsets, shift, 0, n_texts, t0 * tile, lane);
-        const uint32_t hi_w = wave_last_start(offsets, shift, lo_w, n_texts, tl * tile, lane);
         // starts of texts lo_w .. lo_w + 127, two per lane (~0 past the end)
         const uint32_t wi = lo_w + lane;
         const unsigned long long wv0 = wi <= n_texts ? offsets[wi] + shift : ~0ull;
         const unsigned long long wv1 = wi + 64 <= n_texts ? offsets[wi + 64] + shift : ~0ull;
+        // the last text starting at or before the last tile's first byte:
+        // counted in the window when the window holds a start past that byte
+        // (or the last text), else a second wave search
+        const uint64_t gl = tl * tile;
+        const uint32_t in_w = (uint32_t)__popcll(__ballot(wi < n_texts && wv0 <= gl)) +
+                              (uint32_t)__popcll(__ballot(wi + 64 < n_texts && wv1 <= gl));
+        const uint32_t hi_w = in_w < 128 ? lo_w + (in_w > 0 ? in_w - 1 : 0u)
+                                         : wave_last_start(offsets, shift, lo_w, n_texts, gl, lane);
         auto window = [&](uint32_t r) -> uint64_t {  // r < 128; every lane calls it at once
             const uint64_t a = __shfl(wv0, (int)(r & 63u), 64);
             const uint64_t b = __shfl(wv1, (int)(r & 63u), 64);
