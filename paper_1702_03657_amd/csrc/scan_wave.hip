@@ -1000,10 +1000,22 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                 mset = (hm >> jb) & ((1u << PB) - 1u);
                 o = wave_excl_scan((uint32_t)__builtin_popcount(mset), qn);
             }
-            while (mset) {
-                const uint32_t j = jb + (uint32_t)__builtin_ctz(mset);
-                wq16[o++] = (uint16_t)((j >> 4) * kChunk + 16 * lane + (j & 15u));
-                mset &= mset - 1;
+            // bit j < 16: position 16 lane + j of chunk g, else 16 lane + j - 16
+            // of chunk g + 1 (one compare and select per survivor)
+            const uint32_t pa = 16 * lane, pb = kChunk - 16 + 16 * lane;
+            if (parts == 1) {
+                while (mset) {
+                    const uint32_t j = (uint32_t)__builtin_ctz(mset);
+                    wq16[o++] = (uint16_t)(j + (j < 16 ? pa : pb));
+                    mset &= mset - 1;
+                }
+            } else {
+                const uint32_t pj = jb < 16 ? pa : pb;  // a part's bits lie in one chunk
+                while (mset) {
+                    const uint32_t j = jb + (uint32_t)__builtin_ctz(mset);
+                    wq16[o++] = (uint16_t)(j + pj);
+                    mset &= mset - 1;
+                }
             }
             wave_sync();
             // ---- stage 2 as in chunk(), for a window without boundaries:
