@@ -1043,7 +1043,12 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                     const uint32_t v = lv.y + (uint32_t)__builtin_popcount(__builtin_amdgcn_ubfe(lv.x, 0, code));
                     const uint32_t lim = min(nrel - pl, 0xffffu);
                     const uint32_t entry = (uint32_t)(g * kChunk + pl) | (lim << 16);
-                    const bool pass2 = e < qn && pl < top && ((wd >> ((h1 >> sh) & 31u)) & (wd >> (h2 >> 27)) & 1u) != 0;
+                    // both filter bits, e < qn and pl < top (sign bits of the
+                    // differences) in one word, so that no branch splits the
+                    // round before its ballot
+                    const uint32_t ok = (wd >> ((h1 >> sh) & 31u)) & (wd >> (h2 >> 27)) &
+                                        ((e - qn) >> 31) & ((pl - top) >> 31);
+                    const bool pass2 = (ok & 1u) != 0;
                     push_cand(u, pass2, __ballot(pass2), entry, v, pl);
                 }
             } else {
