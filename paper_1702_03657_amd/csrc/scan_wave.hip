@@ -392,8 +392,19 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
 
     // ---- shared tables, once per workgroup
     {
+        // the filter table and the prefix-4 filter by direct global-to-LDS
+        // loads: 1 KiB per wave instruction, no registers, one wait
         const uint4 *tab = (const uint4 *)(a.q16_words ? (const void *)im.q16 : (const void *)im.ftab);
-        for (uint32_t i = tid; i < a.ftab_bytes / 16; i += nthreads) ((uint4 *)s_ftab)[i] = tab[i];
+        const uint32_t n_tab = a.ftab_bytes / 16, n_p4 = a.pfx4_words / 4;
+        for (uint32_t b = wave * 64; b < n_tab; b += waves * 64)
+            if (b + lane < n_tab)
+                __builtin_amdgcn_global_load_lds((const void *)(tab + b + lane),
+                                                 (__attribute__((address_space(3))) void *)(s_ftab + 16 * b), 16, 0, 0);
+        for (uint32_t b = wave * 64; b < n_p4; b += waves * 64)
+            if (b + lane < n_p4)
+                __builtin_amdgcn_global_load_lds((const void *)((const uint4 *)im.pfx4 + b + lane),
+                                                 (__attribute__((address_space(3))) void *)((uint8_t *)s_pfx4 + 16 * b), 16, 0, 0);
+        for (uint32_t i = 4 * n_p4 + tid; i < a.pfx4_words; i += nthreads) s_pfx4[i] = im.pfx4[i];
     }
     for (uint32_t i = tid; i < a.lvl_lds; i += nthreads) {
         const uint2 e = ((const uint2 *)im.lvl)[i];
@@ -401,7 +412,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     }
     for (uint32_t i = tid; i < a.root_words; i += nthreads) s_root[i] = im.root_bits[i];
     for (uint32_t i = tid; i < a.krec_words; i += nthreads) s_krec[i] = im.krec[i];
-    for (uint32_t i = tid; i < a.pfx4_words; i += nthreads) s_pfx4[i] = im.pfx4[i];
+    __builtin_amdgcn_s_waitcnt(0);
     if (MODE == 0 && !im.identity)
         for (uint32_t i = tid; i < 256; i += nthreads) s_sym[i] = im.sym[i];
     __syncthreads();
