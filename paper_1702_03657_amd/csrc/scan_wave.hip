@@ -361,6 +361,10 @@ __device__ __forceinline__ void unit_from_root(const ScanArgs &a, uint64_t u, ui
 // without the LDS tables); otherwise walk and emit here.
 // P4 (modes 1 and 2, split): stage 2 checks the prefix-4 filter, which the
 // launch guarantees, and has no child-record path.
+// TX: 1 for one text (every chunk's boundaries follow from the text's two
+// ends; no boundary record is loaded), 2 for batches (the plan's record per
+// chunk), 0 decided at run time; the split kernels of modes 1..3 come in
+// forms 1 and 2, so that neither keeps the other's state in registers.
 template <int MODE, bool SPLIT, bool P4 = false, int TX = 0>
 __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
     extern __shared__ __align__(16) uint8_t lds[];
