@@ -1,8 +1,9 @@
 """Seeded parity sweep: random pattern sets and texts (alphabets of 2 to 256
 bytes, planted copies and prefixes) scanned under random launch tunings
 (kernel, tile size, level-index bits, fold width, occupancy, waves, unit
-size, second filter stage, bitmapped top nodes, truncated and merged
-images), every result against the oracle's brute force.  Single texts start
+size with odd sizes and the default's 63 and 64, second filter stage,
+bitmapped top nodes, truncated and merged images), every result against
+the oracle's brute force.  Single texts start
 at any alignment and get an output buffer that may be too small (the exact
 count comes back, then a retry); batches run as one launch, one launch per
 text, or a graph replayed twice; one workspace serves all tunings of a case.
@@ -33,7 +34,8 @@ def _tuning(rng):
     t = dict(kernel=int(rng.integers(0, 3)), bytes_per_lane=int(rng.choice([4, 8, 16])),
              index_bits=int(rng.choice([1, 8, 12, 16, 18])), fold_bits=int(rng.choice([0, 8, 16])),
              wg_per_cu=int(rng.integers(0, 3)), waves_per_wg=int(rng.choice([4, 8, 12, 16])),
-             chunks_per_unit=int(rng.choice([1, 2, 4, 8, 16, 32])), child_check=int(rng.integers(0, 3)),
+             chunks_per_unit=int(rng.choice([1, 2, 3, 4, 8, 16, 32, 63, 64])),
+             child_check=int(rng.integers(0, 3)),
              top_nodes=0, trunc_depth=0, dag=0)
     v = int(rng.integers(0, 5))
     if v == 1:
