@@ -1037,6 +1037,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             // positions below top have the bytes the filters read
             const uint32_t need = pfx4 ? 4u : 3u;
             const uint32_t top = min(2 * kChunk + 16, nrel + 1u - need);
+            __builtin_amdgcn_s_setprio(2);  // the dependent LDS chains of stage 2 first
             if constexpr (P4) {
                 // without branches until the record: lanes past the queue
                 // read its last entry (so every lookup stays inside its
@@ -1085,6 +1086,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                     push_cand(u, pass2, __ballot(pass2), entry, v, pl);
                 }
             }
+            __builtin_amdgcn_s_setprio(0);
             wave_sync();
         }
         // the unit's last two chunks: hand over its candidates
