@@ -741,6 +741,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
 
         if (MODE == 1 || MODE == 2) {
             const uint32_t hm = stage1_mask(w);
+            __builtin_amdgcn_s_setprio(2);  // compaction and stage 2 (as in pair())
             // compact the hits of the wave, at most QCAP per round
             uint32_t tot;
             const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
@@ -791,6 +792,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                 }
                 wave_sync();
             }
+            __builtin_amdgcn_s_setprio(0);
         } else if (MODE == 3) {
             // ---- four-symbol alphabets.  Stage 1: the lane's 32 bytes
             // as 2-bit symbols (symbol j at bits 2j of P), the 16-symbol
@@ -817,6 +819,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
 #pragma unroll
             for (int j = 0; j < 16; j++)
                 hm |= ((ent[j] >> hh[j]) & (ent[j] >> (hh[j] >> 5)) & 1u) << j;
+            __builtin_amdgcn_s_setprio(2);  // compaction and stage 2 (as in pair())
             uint32_t tot;
             const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
             const int rounds = tot > kQ16 ? 2 : 1;
@@ -896,6 +899,7 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                 }
                 wave_sync();
             }
+            __builtin_amdgcn_s_setprio(0);
         } else {
             // generic filter: rolling code over L = K + m symbols
             const uint32_t b = im.b;
@@ -1005,6 +1009,9 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
         const uint32_t wb[5] = {sb.v.x, sb.v.y, sb.v.z, sb.v.w, sb.h.x};
         // bit j < 16: position 16 lane + j of chunk g; bit 16 + j: of chunk g + 1
         const uint32_t hm = stage1_mask(wa) | (stage1_mask(wb) << 16);
+        // compaction and stage 2 at raised wave priority: their chains of
+        // dependent scans and LDS reads issue ahead of other waves' stage 1
+        __builtin_amdgcn_s_setprio(2);
         uint32_t tot;
         const uint32_t off_all = wave_excl_scan((uint32_t)__builtin_popcount(hm), tot);
         const int parts = tot > QCAP ? (int)(32 / PB) : 1;
@@ -1037,7 +1044,6 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
             // positions below top have the bytes the filters read
             const uint32_t need = pfx4 ? 4u : 3u;
             const uint32_t top = min(2 * kChunk + 16, nrel + 1u - need);
-            __builtin_amdgcn_s_setprio(2);  // the dependent LDS chains of stage 2 first
             if constexpr (P4) {
                 // without branches until the record: lanes past the queue
                 // read its last entry (so every lookup stays inside its
@@ -1086,9 +1092,9 @@ __global__ __launch_bounds__(1024) void scan_waves(const ScanArgs a) {
                     push_cand(u, pass2, __ballot(pass2), entry, v, pl);
                 }
             }
-            __builtin_amdgcn_s_setprio(0);
             wave_sync();
         }
+        __builtin_amdgcn_s_setprio(0);
         // the unit's last two chunks: hand over its candidates
         if (g + 2 == nch && lane_at(u) == 0) a.cand_count[u] = cn;
         advance(cc);
